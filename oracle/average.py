@@ -1,0 +1,146 @@
+"""Oracle: angle-averaged figure of merit, brute force and reciprocal, and its gradient.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+* ``brute_force``   Eq. 6: integral over theta of alpha(theta) |w^dag u(theta)|^2
+                    with u(theta) = A^{-1} b0(theta), one forward solve per
+                    Gauss-Legendre node.
+* ``reciprocal``    Eq. 7: <|w^dag u|^2> = v^dag W v with v = A^{-dag} w on the
+                    incidence line, evaluated as the plain double sum
+                    sum_jl conj(v_j) C(x_j - x_l) v_l (no FFT).
+* ``adjoint``       gradient of the reciprocal average with respect to the cell
+                    permittivities and the pillar widths (Sec. "Reciprocal
+                    approach": grad F = 2 Re(v^dag W grad v), with grad v from
+                    one adjoint solve).  Reading: the printed
+                    grad v = -A^{-dag} grad A^dag v differentiates the full
+                    reciprocal field z = A^{-dag} w, then restricts it to the
+                    line: grad v = -P A^{-dag} (grad A^dag) z.  With
+                    lambda = A^{-1} P^T (W v) and dA = k^2 s_x s_y deps e_q e_q^T
+                    this gives dF/deps_q = -2 k^2 Re(conj(lambda_q) conj(s_x s_y) z_q).
+
+Because A = A^T, A^{-dag} w = conj(A^{-1} conj(w)): the reciprocal problem is the
+forward problem with the conjugated objective as its source (a point source at
+the focus for a concentrator, a planewave from the output direction for a
+collimator, Sec. "Reciprocal approach").
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from workloads import Problem
+from . import fdfd, light
+
+
+@dataclass
+class Solved:
+    """Factored operator of one problem (SuperLU) plus what the averages reuse."""
+
+    p: Problem
+    eps: np.ndarray
+    A: object
+    lu: object
+
+    def solve(self, b):
+        return self.lu.solve(np.ascontiguousarray(b, dtype=np.complex128))
+
+
+def setup(p: Problem, eps=None) -> Solved:
+    if eps is None:
+        eps = fdfd.permittivity(p)
+    A = fdfd.operator(p, eps)
+    return Solved(p=p, eps=eps, A=A, lu=fdfd.factor(A))
+
+
+def forward_fields(s: Solved, thetas) -> np.ndarray:
+    """u(theta) = A^{-1} b0(theta) for each angle (N x Q)."""
+    return s.solve(fdfd.planewave_sources(s.p, thetas))
+
+
+def per_angle_fom(s: Solved, thetas) -> np.ndarray:
+    """|w^dag u(theta)|^2 for each angle (one forward solve per angle)."""
+    w = fdfd.objective_vector(s.p)
+    U = forward_fields(s, thetas)
+    return np.abs(w.conj() @ U) ** 2
+
+
+def brute_force(s: Solved, n_nodes: int) -> float:
+    """Eq. 6 by n-node Gauss-Legendre quadrature in theta over I."""
+    th, wt = light.gauss_legendre(s.p, n_nodes)
+    return float(np.sum(wt * light.alpha(s.p, th) * per_angle_fom(s, th)))
+
+
+def reciprocal_field(s: Solved) -> np.ndarray:
+    """z = A^{-dag} w = conj(A^{-1} conj(w)) on the whole grid."""
+    w = fdfd.objective_vector(s.p)
+    return np.conj(s.solve(np.conj(w)))
+
+
+def line_field(s: Solved, z=None) -> np.ndarray:
+    """v = z restricted to the incidence line (physical columns of the source row)."""
+    if z is None:
+        z = reciprocal_field(s)
+    return z[fdfd.aperture_indices(s.p)]
+
+
+def quadratic_form(v: np.ndarray, T: np.ndarray) -> complex:
+    """v^dag T v as the plain double sum."""
+    return complex(np.sum(np.conj(v)[:, None] * T * v[None, :]))
+
+
+def reciprocal(s: Solved, T=None) -> float:
+    """Eq. 7 with the closed-form correlation (or a given T): one reciprocal solve."""
+    v = line_field(s)
+    if T is None:
+        T = light.toeplitz_matrix(s.p)
+    return quadratic_form(v, T).real
+
+
+@dataclass
+class Gradient:
+    F: float
+    z: np.ndarray               # reciprocal field, N
+    Tv: np.ndarray              # W v on the line, M
+    lam: np.ndarray             # adjoint field A^{-1} P^T (W v), N
+    grad_eps: np.ndarray        # dF/deps, nx x ny
+    grad_widths: np.ndarray     # dF/dw_p, one per pillar
+
+
+def adjoint(s: Solved) -> Gradient:
+    p = s.p
+    z = reciprocal_field(s)
+    v = line_field(s, z)
+    T = light.toeplitz_matrix(p)
+    Tv = T @ v
+    F = complex(np.vdot(v, Tv)).real
+    rhs = np.zeros(p.nx * p.ny, dtype=np.complex128)
+    rhs[fdfd.aperture_indices(p)] = Tv
+    lam = s.solve(rhs)
+    sxc, _, syc, _ = fdfd.stretches(p)
+    sxsy = (sxc[:, None] * syc[None, :]).ravel()
+    k2 = fdfd.k0(p) ** 2
+    g = -2.0 * k2 * np.real(np.conj(lam) * np.conj(sxsy) * z)
+    grad_eps = g.reshape(p.nx, p.ny)
+    return Gradient(F=F, z=z, Tv=Tv, lam=lam, grad_eps=grad_eps,
+                    grad_widths=width_gradient(p, grad_eps))
+
+
+def edge_cells(p: Problem, centre: float, width: float):
+    """Columns holding the left and right pillar edges (half-open cells)."""
+    x0 = (0.0 - p.npml) * p.h          # left face of column 0 in physical x
+    left = int(np.floor((centre - width / 2 - x0) / p.h))
+    right = int(np.floor((centre + width / 2 - x0) / p.h))
+    return left, right
+
+
+def width_gradient(p: Problem, grad_eps: np.ndarray, widths=None) -> np.ndarray:
+    """Chain rule eps(widths): each edge moves by dw/2, changing one cell's fill by dw/(2h)."""
+    widths = p.widths if widths is None else widths
+    rows = slice(p.pillar_row0, p.pillar_row0 + p.pillar_rows)
+    d = (p.eps_pillar - p.eps_bg) / (2.0 * p.h)
+    out = np.zeros(len(widths))
+    for k, (xc, w) in enumerate(zip(p.pillar_centers, widths)):
+        il, ir = edge_cells(p, xc, w)
+        out[k] = d * (grad_eps[il, rows].sum() + grad_eps[ir, rows].sum())
+    return out

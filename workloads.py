@@ -1,0 +1,247 @@
+"""Seeded synthetic workloads shared by the oracle and the GPU path.
+
+This module holds only *inputs*: grid sizes, cell indices of rows and points,
+pillar centres and seeded widths, light-distribution parameters and seeded
+request streams.  It contains none of the method's arithmetic (no permittivity
+map, no PML, no operator, no sources, no correlation functions); each side
+computes those from these numbers on its own.
+
+The shapes follow the paper's setting (Sec. "Designs": a single layer of
+dielectric pillars of sub-wavelength period on a substrate, concentrator /
+collimator objectives, light uniform in a cone or an annulus of angles), scaled
+to the synthetic configurations below:
+
+* ``config1``  10 x 8 wavelengths, 10 pillars, cone +-10 deg, concentrator
+                (240 x 200 cells with a 20-cell PML on every side).
+* ``config2``  100 x 52 wavelengths, 100 pillars, cone +-20 deg, concentrator
+                with focal distance 50 (2040 x 1080 cells).
+* ``config3``  200 x 20 wavelengths, 200 pillars, annulus 10-30 deg and its
+                mirror, collimator at output angle 0 (4040 x 440 cells).
+* ``config4_large`` 100 x 20 wavelengths, 100 pillars, cone +-10 deg,
+                concentrator 5 wavelengths above a 100 x 10 design region
+                (2040 x 440 cells).
+* ``serving_stream`` Poisson arrivals of concentrator / collimator requests of
+                random width and depth.
+
+Units: vacuum wavelength 1, grid step h = 1/20.  Cell (i, j) has its centre at
+x = (i - npml + 1/2) h, y = (j - npml + 1/2) h, origin at the lower-left corner
+of the physical (non-PML) region.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+CONCENTRATOR = 0
+COLLIMATOR = 1
+CONE = 0
+ANNULUS = 1
+
+
+@dataclass(frozen=True)
+class Problem:
+    """One metasurface evaluation: geometry, objective and light statistics."""
+
+    name: str
+    nx: int                      # cells along x (long axis, block index)
+    ny: int                      # cells along y (block size n)
+    npml: int = 20
+    h: float = 0.05
+    wavelength: float = 1.0
+    pml_R: float = 1e-8          # target normal-incidence PML reflection
+    pml_m: int = 3               # PML grading exponent
+    eps_bg: float = 1.0
+    eps_sub: float = 2.25
+    eps_pillar: float = 5.76
+    sub_rows: int = 40           # rows j < sub_rows hold substrate (y < 1), PML included
+    pillar_row0: int = 40        # first pillar-layer row (y = 1)
+    pillar_rows: int = 10        # pillar height 0.5 = 10 rows
+    pillar_centers: Tuple[float, ...] = ()
+    widths: Tuple[float, ...] = ()
+    objective: int = CONCENTRATOR
+    focus: Tuple[int, int] = (0, 0)          # concentrator: focus cell (i, j)
+    monitor_row: int = 0                     # collimator: monitor row j_m
+    phi: float = 0.0                         # collimator output angle (rad, in air)
+    n_monitor: float = 1.0
+    source_row: int = 30                     # incidence line (equivalent source plane) j_s
+    n_source: float = 1.5                    # index of the source-plane medium (substrate)
+    light: int = CONE
+    c: float = 0.0                           # cone half-angle (rad)
+    th1: float = 0.0                         # annulus inner edge (rad)
+    th2: float = 0.0                         # annulus outer edge (rad)
+
+    # derived, integer-only helpers (no physics)
+    @property
+    def n_cells(self) -> int:
+        return self.nx * self.ny
+
+    @property
+    def aperture(self) -> Tuple[int, int]:
+        """Physical columns [i0, i1) of the incidence line / monitor row."""
+        return self.npml, self.nx - self.npml
+
+    @property
+    def m_aperture(self) -> int:
+        i0, i1 = self.aperture
+        return i1 - i0
+
+
+def seeded_widths(n: int, seed: int, lo: float = 0.1, hi: float = 0.9) -> Tuple[float, ...]:
+    rng = np.random.default_rng(seed)
+    return tuple(float(w) for w in rng.uniform(lo, hi, size=n))
+
+
+def _pillars(n: int, period: float = 1.0) -> Tuple[float, ...]:
+    return tuple((p + 0.5) * period for p in range(n))
+
+
+def metasurface(name: str, width_wl: int, height_wl: int, seed: int, *,
+                objective: int = CONCENTRATOR, focus_height: float = 5.0,
+                light: int = CONE, c_deg: float = 10.0, th1_deg: float = 0.0,
+                th2_deg: float = 0.0, phi: float = 0.0, monitor_y: float = 11.5,
+                npml: int = 20, h: float = 0.05) -> Problem:
+    """A physical region width_wl x height_wl wavelengths, pillars of period 1."""
+    per = int(round(1.0 / h))
+    nxp, nyp = width_wl * per, height_wl * per
+    nx, ny = nxp + 2 * npml, nyp + 2 * npml
+    sub_rows = npml + per          # substrate y < 1
+    pillar_row0 = npml + per       # pillars y in [1, 1.5)
+    pillar_rows = per // 2
+    top = pillar_row0 + pillar_rows           # first row above the pillars
+    fj = top + int(round(focus_height * per))  # focus row: focus_height above pillar tops
+    fi = npml + nxp // 2
+    mj = npml + int(round((monitor_y - 0.5 * h) / h))
+    return Problem(name=name, nx=nx, ny=ny, npml=npml, h=h,
+                   sub_rows=sub_rows, pillar_row0=pillar_row0, pillar_rows=pillar_rows,
+                   pillar_centers=_pillars(width_wl), widths=seeded_widths(width_wl, seed),
+                   objective=objective, focus=(fi, fj), monitor_row=mj, phi=phi,
+                   source_row=npml + per // 2, light=light,
+                   c=math.radians(c_deg), th1=math.radians(th1_deg), th2=math.radians(th2_deg))
+
+
+def config1(seed: int = 1001) -> Problem:
+    """Plain FP64 concentrator, 10 x 8 wavelengths (240 x 200 cells)."""
+    return metasurface("config1", 10, 8, seed, focus_height=5.0, c_deg=10.0)
+
+
+def config2(seed: int = 1002) -> Problem:
+    """Concentrator 100 wavelengths wide, focal distance 50 (2040 x 1080 cells)."""
+    # 52 wavelengths of physical height: substrate (1) + pillars (0.5) + 50 to the
+    # focus + 0.5 clearance below the top PML.
+    return metasurface("config2", 100, 52, seed, focus_height=50.0, c_deg=20.0)
+
+
+def config3(seed: int = 1003) -> Problem:
+    """Collimator 200 x 20 wavelengths, annulus 10-30 deg + mirror (4040 x 440)."""
+    return metasurface("config3", 200, 20, seed, objective=COLLIMATOR, light=ANNULUS,
+                       th1_deg=10.0, th2_deg=30.0, phi=0.0, monitor_y=11.5)
+
+
+def config4_large(seed: int = 1004) -> Problem:
+    """Adjoint step at scale: 100 x 20 wavelengths, cone +-10 deg (2040 x 440)."""
+    return metasurface("config4_large", 100, 20, seed, focus_height=5.0 + 9.5, c_deg=10.0)
+
+
+def small_problem(width_wl: int = 4, height_wl: int = 4, seed: int = 7, *,
+                  objective: int = CONCENTRATOR, light: int = CONE, c_deg: float = 15.0,
+                  th1_deg: float = 5.0, th2_deg: float = 20.0, npml: int = 10,
+                  focus_height: float = 2.0, monitor_y: float = 3.0,
+                  phi: float = 0.0) -> Problem:
+    """A tiny problem the oracle factors in well under a second."""
+    return metasurface(f"small{width_wl}x{height_wl}", width_wl, height_wl, seed,
+                       objective=objective, light=light, c_deg=c_deg, th1_deg=th1_deg,
+                       th2_deg=th2_deg, npml=npml, focus_height=focus_height,
+                       monitor_y=monitor_y, phi=phi)
+
+
+def with_light(p: Problem, *, light: int, c: float = 0.0, th1: float = 0.0,
+               th2: float = 0.0) -> Problem:
+    return replace(p, light=light, c=c, th1=th1, th2=th2)
+
+
+def pixel_patch(p: Problem, width_cells: int, height_cells: int) -> Tuple[int, int, int, int]:
+    """Central patch of the pillar layer [i0, i1) x [j0, j1) for per-pixel gradients."""
+    ic = p.npml + (p.nx - 2 * p.npml) // 2
+    i0 = ic - width_cells // 2
+    return i0, i0 + width_cells, p.pillar_row0, p.pillar_row0 + height_cells
+
+
+def seeded_cells(p: Problem, count: int, seed: int,
+                 region: Optional[Tuple[int, int, int, int]] = None) -> np.ndarray:
+    """Distinct seeded cell indices q = i*ny + j inside region (default: physical)."""
+    rng = np.random.default_rng(seed)
+    if region is None:
+        region = (p.npml, p.nx - p.npml, p.npml, p.ny - p.npml)
+    i0, i1, j0, j1 = region
+    qs = set()
+    while len(qs) < count:
+        i = int(rng.integers(i0, i1))
+        j = int(rng.integers(j0, j1))
+        qs.add(i * p.ny + j)
+    return np.array(sorted(qs), dtype=np.int64)
+
+
+def complex_normal(shape, seed: int, dtype=np.complex128) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(dtype)
+
+
+# ----------------------------------------------------------------------------
+# Serving mix: Poisson request stream
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float               # seconds since stream start
+    problem: Problem
+    adjoint: bool
+
+
+def serving_stream(n_requests: int, rate: float = 200.0, seed: int = 5001, *,
+                   width_range=(20, 300), depth_range=(10, 60), adjoint_frac: float = 0.2,
+                   geometry_pool: int = 0, geom_seed: int = 5002,
+                   scale: float = 1.0) -> List[Request]:
+    """Seeded Poisson stream of concentrator / collimator evaluations.
+
+    Widths are uniform in width_range wavelengths, depths in depth_range; cone
+    half-angles are U[5, 40] deg, annuli have inner edge U[5, 20] deg and width
+    U[5, 40] deg.  ``scale`` shrinks widths and depths (for tests).  With
+    ``geometry_pool`` > 0 the geometries are drawn from a seeded pool of that
+    many, so that requests can share factors.
+    """
+    rng = np.random.default_rng(seed)
+    grng = np.random.default_rng(geom_seed)
+
+    def draw_geom(k: int):
+        w = int(round(grng.uniform(*width_range) * scale))
+        d = int(round(grng.uniform(*depth_range) * scale))
+        return max(w, 2), max(d, 4), 10_000 + k
+
+    pool = [draw_geom(k) for k in range(geometry_pool)] if geometry_pool > 0 else None
+    t = 0.0
+    out: List[Request] = []
+    for r in range(n_requests):
+        t += float(rng.exponential(1.0 / rate))
+        if pool is not None:
+            w, d, gseed = pool[int(rng.integers(0, len(pool)))]
+        else:
+            w, d, gseed = draw_geom(100 + r)
+        collim = bool(rng.uniform() < 0.5)
+        annulus = bool(rng.uniform() < 0.5)
+        adj = bool(rng.uniform() < adjoint_frac)
+        if annulus:
+            th1 = float(rng.uniform(5.0, 20.0))
+            th2 = th1 + float(rng.uniform(5.0, 40.0))
+            light = dict(light=ANNULUS, th1_deg=th1, th2_deg=th2)
+        else:
+            light = dict(light=CONE, c_deg=float(rng.uniform(5.0, 40.0)))
+        fh = min(5.0, d - 2.5)
+        p = metasurface(f"req{r}", w, d, gseed,
+                        objective=COLLIMATOR if collim else CONCENTRATOR,
+                        focus_height=fh, monitor_y=min(d - 1.0, 1.5 + fh), **light)
+        out.append(Request(rid=r, arrival=t, problem=p, adjoint=adj))
+    return out
