@@ -1,0 +1,217 @@
+/*
+ * recip.h -- C ABI of librecip: the reciprocal angle average of incoherent light
+ * through a 2D metasurface, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (Pestourie, Yao, Kante, Johnson, "Efficient inverse design of
+ * large-area metasurfaces for incoherent light"):
+ *   - Sec. "Reciprocal approach", Eq. 7: the angle-averaged figure of merit
+ *     <|w^dag u|^2> equals v^dag W v, with v = A^{-dag} w the field of ONE
+ *     "reciprocal" solve (the objective w used as the source), restricted to
+ *     the incidence line, and W the cross-correlation of the equivalent source
+ *     currents there.
+ *   - Sec. "Incoherent light", Eq. 3-4 and the annulus formula of Sec.
+ *     "Designs": for angle-uncorrelated light W(x1, x2) = C(x1 - x2) is
+ *     Toeplitz, so W v is a convolution evaluated by FFT.
+ *   - Eq. 6: the brute-force average it replaces integrates |w^dag u(theta)|^2
+ *     over incident angles, one forward solve per quadrature node
+ *     (Sec. "Brute-force quadrature": Gauss-Legendre in theta).
+ *   - Sec. "Reciprocal approach": gradient 2 Re(v^dag W grad v) by one adjoint
+ *     solve.
+ *
+ * The operator A is the symmetric stretched-coordinate PML finite-difference
+ * form of (laplacian + k0^2 eps) u = -f, multiplied through by s_x s_y, on an
+ * nx x ny cell grid.  It is block tridiagonal along x (block i = grid column i,
+ * block size ny) and is factored by a two-ended (twisted) block elimination
+ * whose dense Schur-complement blocks are inverted by a symmetric blocked
+ * Gauss-Jordan sweep on MFMA.
+ *
+ * Conventions
+ *   - Complex arrays are interleaved (re, im): double[2] per element
+ *     (torch.complex128) unless stated otherwise.
+ *   - Grid fields are x-major: cell (i, j) is element q = i * ny + j.
+ *   - Cell (i, j) has its centre at x = (i - npml + 1/2) h,
+ *     y = (j - npml + 1/2) h; the physical region is
+ *     npml <= i < nx - npml, npml <= j < ny - npml.
+ *   - All pointers named *_dev are device pointers owned by the caller; the
+ *     library never frees caller memory.  The library owns only the small host
+ *     handle returned by rcp_factor.
+ *   - Every call enqueues on `stream` and returns without waiting, except
+ *     where stated (rcp_factor waits once to check pivot health; refined
+ *     solves wait once per refinement step to test convergence).
+ *   - Calls that use the same rcp_factors must be ordered on one stream: they
+ *     share work vectors inside the factor buffer.
+ *   - Return value: 0 on success, or a negative RCP_E* code; the message of
+ *     the last failure on the calling thread is returned by rcp_last_error().
+ *     No C++ exception crosses this interface.
+ */
+#ifndef RECIP_H
+#define RECIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* rcp_stream; /* a hipStream_t; NULL = default stream */
+
+enum {
+  RCP_OK = 0,
+  RCP_EINVAL = -1,     /* bad shape, index outside the physical region, bad light, ... */
+  RCP_ENOMEM = -2,     /* caller buffer smaller than required                          */
+  RCP_ESINGULAR = -3,  /* non-finite or vanishing pivot; message names the block       */
+  RCP_ENOCONV = -4,    /* refinement did not reach tol; message gives the residual      */
+  RCP_EHIP = -5        /* HIP runtime error                                             */
+};
+
+enum { RCP_FP64 = 0, RCP_FP32_REFINED = 1 };
+enum { RCP_CONCENTRATOR = 0, RCP_COLLIMATOR = 1 };
+enum { RCP_CONE = 0, RCP_ANNULUS = 1, RCP_SYMBOL_TABLE = 2 };
+
+/* Grid and PML.  PML stretch s(xi) = 1 + i sigma (d/L)^m with d the depth into
+ * the layer, L = npml h, sigma = (m+1) ln(1/pml_R) / (2 k0 L).  k0 = 2 pi /
+ * vacuum wavelength.  eps_dev: nx*ny float64 cell permittivities (device);
+ * copied into the factor buffer by rcp_factor. */
+typedef struct {
+  int32_t nx, ny, npml;
+  double h, k0;
+  double pml_R;
+  int32_t pml_m;
+  const double* eps_dev;
+} rcp_grid;
+
+/* Pillar layer (Sec. "Designs": a single layer of dielectric pillars on a
+ * substrate).  Rows j < sub_rows hold eps_sub; rows [row0, row0 + rows) hold
+ * pillars of permittivity eps_pillar centred at centers_dev[p] (physical x)
+ * with widths widths_dev[p]; each cell takes the arithmetic mean of eps over
+ * its x extent.  Everything else is eps_bg.  Arrays are device float64. */
+typedef struct {
+  int32_t n;
+  const double* centers_dev;
+  const double* widths_dev;
+  double eps_bg, eps_sub, eps_pillar;
+  int32_t sub_rows, row0, rows;
+} rcp_pillars;
+
+/* Objective w (Sec. "Reciprocal approach": FOM |w^dag u|^2).
+ *   CONCENTRATOR: w = e_q at the focus cell (i_f, j_f): w^dag u = u(focus).
+ *   COLLIMATOR:   w = (h / L) exp(i k0 n_m sin(phi) x) on row j_m over columns
+ *                 [i0, i1), L = (i1 - i0) h: w^dag u is the amplitude of the
+ *                 planewave output mode at angle phi. */
+typedef struct {
+  int32_t kind;
+  int32_t i_f, j_f;
+  int32_t j_m, i0, i1;
+  double phi, n_m;
+} rcp_objective;
+
+/* Incoherent light on the incidence line: row j_s, columns [i0, i1) (M cells),
+ * medium index n_s; angles theta are measured in that medium.
+ *   CONE:    <|a|^2> = 1/(2c) on [-c, c]
+ *   ANNULUS: <|a|^2> = 1/(2(th2 - th1)) on [-th2, -th1] u [th1, th2]
+ *   SYMBOL_TABLE: symbol_dev holds 2M-1 complex128 values C(m h),
+ *                 m = -(M-1) .. M-1 (index m + M - 1); C(-d) = conj C(d).
+ * The equivalent source of a unit-power planewave is the line current
+ * J(theta) = -2 i k0 sqrt(n_s cos theta) spread over one cell height, so
+ * C(d) = int <|a|^2> |J|^2 / h^2 exp(i K d sin theta) dtheta, K = n_s k0. */
+typedef struct {
+  int32_t j_s, i0, i1;
+  double n_s;
+  int32_t kind;
+  double c, th1, th2;
+  const double* symbol_dev;
+} rcp_light;
+
+typedef struct rcp_factors rcp_factors;
+
+typedef struct {
+  int32_t iters;         /* refinement steps taken (0 for plain FP64)        */
+  double rel_residual;   /* ||b - A x|| / ||b|| after the last step (refined) */
+} rcp_solve_stats;
+
+/* a1 -- permittivity map from pillar widths (Sec. "Designs"; widths are the
+ * design parameters p of Sec. "Reciprocal approach").  eps_out_dev: nx*ny
+ * float64.  grid->eps_dev is ignored. */
+int rcp_eps_from_widths(const rcp_grid* grid, const rcp_pillars* pillars,
+                        double* eps_out_dev, rcp_stream stream);
+
+/* Bytes of device memory rcp_factor needs for this grid and precision
+ * (factor blocks, operator coefficients, work vectors).  Exact; serving
+ * admits requests by this number.  Returns 0 for an invalid grid. */
+size_t rcp_factor_bytes(const rcp_grid* grid, int32_t precision);
+
+/* a2 + a3 -- assemble A (Sec. "Reciprocal approach": u = A^{-1} b) and factor
+ * it: twisted block elimination along x, every Schur-complement block
+ * inverted on the GPU (complex128 for RCP_FP64, complex64 for
+ * RCP_FP32_REFINED).  buf_dev: caller buffer of at least
+ * rcp_factor_bytes(grid, precision) bytes, 256-byte aligned; it must stay
+ * alive and untouched while *out is used.  Waits for the stream once at the
+ * end to check pivots (RCP_ESINGULAR names the first bad block). */
+int rcp_factor(const rcp_grid* grid, int32_t precision, void* buf_dev, size_t buf_bytes,
+               rcp_stream stream, rcp_factors** out);
+
+/* Solve A X = B for nrhs right-hand sides (or A^dag X = B when
+ * conj_transpose != 0, using A = A^T).  B_dev, X_dev: nrhs x nx x ny
+ * complex128 (row r is one grid field); B_dev and X_dev must not overlap
+ * (RCP_EINVAL).  RCP_FP32_REFINED factors: iterative refinement with FP64 residuals
+ * until ||r|| / ||b|| <= tol or max_refine steps (RCP_ENOCONV); each step
+ * waits for the stream.  tol and max_refine are ignored for RCP_FP64.
+ * stats may be NULL. */
+int rcp_solve_multi_rhs(const rcp_factors* f, int32_t nrhs, const void* B_dev, void* X_dev,
+                        int32_t conj_transpose, double tol, int32_t max_refine,
+                        rcp_stream stream, rcp_solve_stats* stats);
+
+/* a4-a7 -- Eq. 7: F = v^dag W v with v = A^{-dag} w on the incidence line, W v
+ * by circulant embedding and FFT.  F_dev: one float64.  Optional outputs
+ * (NULL to skip): v_dev (M complex128), z_dev (nx*ny complex128, the whole
+ * reciprocal field A^{-dag} w). */
+int rcp_reciprocal_average(const rcp_factors* f, const rcp_objective* obj,
+                           const rcp_light* light, double* F_dev, void* v_dev, void* z_dev,
+                           rcp_stream stream);
+
+/* Device workspace rcp_brute_force_average needs for nangles nodes solved
+ * rhs_chunk at a time (node tables, line sources, one chunk of fields). */
+size_t rcp_brute_force_work_bytes(const rcp_factors* f, int32_t nangles, int32_t rhs_chunk);
+
+/* a8 -- Eq. 6 by nangles-point Gauss-Legendre quadrature in theta (split evenly
+ * over the two intervals of an annulus): one forward solve per node, in
+ * chunks of rhs_chunk right-hand sides on the same factors.  F_dev: one
+ * float64; per_angle_dev (optional, nangles float64): |w^dag u(theta_q)|^2 in
+ * node order (ascending theta).  RCP_FP64 factors and CONE / ANNULUS light only. */
+int rcp_brute_force_average(const rcp_factors* f, const rcp_objective* obj,
+                            const rcp_light* light, int32_t nangles, int32_t rhs_chunk,
+                            void* work_dev, size_t work_bytes, double* F_dev,
+                            double* per_angle_dev, rcp_stream stream);
+
+/* a9 -- gradient of F (Sec. "Reciprocal approach"): lambda = A^{-1} P^T (W v),
+ * dF/deps_q = -2 k0^2 Re(conj(lambda_q) conj(s_x s_y)_q z_q), from one extra
+ * solve.  F_dev: one float64 (same value as rcp_reciprocal_average);
+ * grad_eps_dev: nx*ny float64. */
+int rcp_adjoint_grad(const rcp_factors* f, const rcp_objective* obj, const rcp_light* light,
+                     double* F_dev, double* grad_eps_dev, rcp_stream stream);
+
+/* a1 backward -- chain rule from dF/deps to dF/dwidth_p: each pillar edge moves
+ * by dw/2 and changes the fill of the cell holding it by dw/(2h) in every
+ * pillar row.  grad_w_dev: pillars->n float64. */
+int rcp_width_grad(const rcp_grid* grid, const rcp_pillars* pillars, const double* grad_eps_dev,
+                   double* grad_w_dev, rcp_stream stream);
+
+/* Releases the host handle only; buf_dev stays with the caller. */
+void rcp_factors_release(rcp_factors* f);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* rcp_last_error(void);
+
+/* Iteration count and final relative residual of the last refined solve made
+ * by rcp_reciprocal_average / rcp_adjoint_grad on these factors. */
+int rcp_last_solve_stats(const rcp_factors* f, rcp_solve_stats* stats);
+
+/* Introspection for tests and benchmarks. */
+int rcp_factors_info(const rcp_factors* f, int32_t* nx, int32_t* ny, int32_t* precision,
+                     int32_t* padded_n, int32_t* tile);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RECIP_H */

@@ -1,0 +1,226 @@
+"""Reciprocal angle average of incoherent light through 2D metasurfaces on MI355X.
+
+Python front end of librecip (include/recip.h).  PyTorch provides device
+memory and streams; every step of the computation runs in librecip's HIP
+kernels.  Method: Pestourie, Yao, Kante, Johnson, "Efficient inverse design of
+large-area metasurfaces for incoherent light" -- one reciprocal solve
+v = A^{-dag} w followed by the Toeplitz form v^dag W v (Eq. 7) instead of an
+angle quadrature over forward solves (Eq. 6).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import Optional, Tuple
+
+import torch
+
+from workloads import ANNULUS, COLLIMATOR, CONCENTRATOR, CONE, Problem
+from . import _lib
+from ._lib import (RCP_ANNULUS, RCP_COLLIMATOR, RCP_CONCENTRATOR, RCP_CONE, RCP_FP32_REFINED,
+                   RCP_FP64, RCP_SYMBOL_TABLE, RecipError, check, lib)
+
+__all__ = ["Factors", "factor_bytes", "eps_from_widths", "reciprocal_average",
+           "brute_force_average", "adjoint_grad", "width_grad", "solve", "IncoherentFOM",
+           "RCP_FP64", "RCP_FP32_REFINED", "RecipError"]
+
+
+def _stream(stream: Optional[torch.cuda.Stream] = None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def k0_of(p: Problem) -> float:
+    return 2.0 * math.pi / p.wavelength
+
+
+def grid_struct(p: Problem, eps: Optional[torch.Tensor] = None) -> _lib.Grid:
+    return _lib.Grid(p.nx, p.ny, p.npml, p.h, k0_of(p), p.pml_R, p.pml_m,
+                     eps.data_ptr() if eps is not None else None)
+
+
+def objective_struct(p: Problem) -> _lib.Objective:
+    i0, i1 = p.aperture
+    kind = RCP_CONCENTRATOR if p.objective == CONCENTRATOR else RCP_COLLIMATOR
+    return _lib.Objective(kind, p.focus[0], p.focus[1], p.monitor_row, i0, i1, p.phi, p.n_monitor)
+
+
+def light_struct(p: Problem, symbol: Optional[torch.Tensor] = None) -> _lib.Light:
+    i0, i1 = p.aperture
+    if symbol is not None:
+        return _lib.Light(p.source_row, i0, i1, p.n_source, RCP_SYMBOL_TABLE, 0.0, 0.0, 0.0,
+                          symbol.data_ptr())
+    kind = RCP_CONE if p.light == CONE else RCP_ANNULUS
+    return _lib.Light(p.source_row, i0, i1, p.n_source, kind, p.c, p.th1, p.th2, None)
+
+
+class _PillarArgs:
+    """Keeps the device copies of pillar centres and widths alive with the struct."""
+
+    def __init__(self, p: Problem, widths: Optional[torch.Tensor], device):
+        self.centers = torch.tensor(p.pillar_centers, dtype=torch.float64, device=device)
+        if widths is None:
+            widths = torch.tensor(p.widths, dtype=torch.float64, device=device)
+        self.widths = widths.detach().to(device=device, dtype=torch.float64).contiguous()
+        self.struct = _lib.Pillars(len(p.pillar_centers), self.centers.data_ptr(),
+                                   self.widths.data_ptr(), p.eps_bg, p.eps_sub, p.eps_pillar,
+                                   p.sub_rows, p.pillar_row0, p.pillar_rows)
+
+
+def eps_from_widths(p: Problem, widths: Optional[torch.Tensor] = None, device="cuda",
+                    stream=None) -> torch.Tensor:
+    """Cell permittivity map (nx x ny float64) of the pillar layer (kernel a1)."""
+    pa = _PillarArgs(p, widths, device)
+    eps = torch.empty((p.nx, p.ny), dtype=torch.float64, device=device)
+    g = grid_struct(p)
+    check(lib.rcp_eps_from_widths(C.byref(g), C.byref(pa.struct), eps.data_ptr(), _stream(stream)))
+    return eps
+
+
+def factor_bytes(p: Problem, precision: int = RCP_FP64) -> int:
+    g = grid_struct(p)
+    n = lib.rcp_factor_bytes(C.byref(g), precision)
+    if n == 0:
+        raise RecipError(_lib.RCP_EINVAL, "invalid grid for factor_bytes")
+    return int(n)
+
+
+class Factors:
+    """Factored operator of one geometry; owns its device buffer (a torch tensor)."""
+
+    def __init__(self, p: Problem, eps: torch.Tensor, precision: int = RCP_FP64, stream=None,
+                 buffer: Optional[torch.Tensor] = None):
+        self.problem = p
+        self.precision = precision
+        self.nbytes = factor_bytes(p, precision)
+        if buffer is None:
+            buffer = torch.empty(self.nbytes, dtype=torch.uint8, device=eps.device)
+        if buffer.numel() < self.nbytes:
+            raise RecipError(_lib.RCP_ENOMEM, "factor buffer too small")
+        self.buf = buffer
+        eps = eps.to(dtype=torch.float64).contiguous()
+        g = grid_struct(p, eps)
+        h = C.c_void_p()
+        check(lib.rcp_factor(C.byref(g), precision, buffer.data_ptr(), self.nbytes,
+                             _stream(stream), C.byref(h)))
+        self.handle = h
+
+    def release(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib.rcp_factors_release(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+    def last_solve_stats(self) -> Tuple[int, float]:
+        st = _lib.SolveStats()
+        check(lib.rcp_last_solve_stats(self.handle, C.byref(st)))
+        return int(st.iters), float(st.rel_residual)
+
+
+def reciprocal_average(fac: Factors, p: Optional[Problem] = None, want_v: bool = False,
+                       want_z: bool = False, symbol: Optional[torch.Tensor] = None, stream=None,
+                       out: Optional[torch.Tensor] = None):
+    """F = v^dag W v (Eq. 7) on device; returns F (0-d float64 tensor) [, v] [, z]."""
+    p = p or fac.problem
+    dev = fac.buf.device
+    F = out if out is not None else torch.empty((), dtype=torch.float64, device=dev)
+    v = torch.empty(p.m_aperture, dtype=torch.complex128, device=dev) if want_v else None
+    z = torch.empty((p.nx, p.ny), dtype=torch.complex128, device=dev) if want_z else None
+    o, lt = objective_struct(p), light_struct(p, symbol)
+    check(lib.rcp_reciprocal_average(fac.handle, C.byref(o), C.byref(lt), F.data_ptr(),
+                                     v.data_ptr() if v is not None else None,
+                                     z.data_ptr() if z is not None else None, _stream(stream)))
+    res = [F]
+    if want_v:
+        res.append(v)
+    if want_z:
+        res.append(z)
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def brute_force_average(fac: Factors, nangles: int, p: Optional[Problem] = None,
+                        rhs_chunk: Optional[int] = None, per_angle: bool = False, stream=None,
+                        work: Optional[torch.Tensor] = None):
+    """Eq. 6 by nangles-node Gauss-Legendre quadrature over forward solves."""
+    p = p or fac.problem
+    dev = fac.buf.device
+    rhs_chunk = rhs_chunk or min(nangles, 256)
+    need = int(lib.rcp_brute_force_work_bytes(fac.handle, nangles, rhs_chunk))
+    if work is None or work.numel() < need:
+        work = torch.empty(need, dtype=torch.uint8, device=dev)
+    F = torch.empty((), dtype=torch.float64, device=dev)
+    pa = torch.empty(nangles, dtype=torch.float64, device=dev) if per_angle else None
+    o, lt = objective_struct(p), light_struct(p)
+    check(lib.rcp_brute_force_average(fac.handle, C.byref(o), C.byref(lt), nangles, rhs_chunk,
+                                      work.data_ptr(), need, F.data_ptr(),
+                                      pa.data_ptr() if pa is not None else None, _stream(stream)))
+    return (F, pa) if per_angle else F
+
+
+def adjoint_grad(fac: Factors, p: Optional[Problem] = None, stream=None):
+    """(F, dF/deps) with dF/deps an nx x ny float64 map, from one extra solve."""
+    p = p or fac.problem
+    dev = fac.buf.device
+    F = torch.empty((), dtype=torch.float64, device=dev)
+    g = torch.empty((p.nx, p.ny), dtype=torch.float64, device=dev)
+    o, lt = objective_struct(p), light_struct(p)
+    check(lib.rcp_adjoint_grad(fac.handle, C.byref(o), C.byref(lt), F.data_ptr(), g.data_ptr(),
+                               _stream(stream)))
+    return F, g
+
+
+def width_grad(p: Problem, grad_eps: torch.Tensor, widths: Optional[torch.Tensor] = None,
+               stream=None) -> torch.Tensor:
+    """Chain rule dF/deps -> dF/dwidths (kernel, backward of eps_from_widths)."""
+    dev = grad_eps.device
+    pa = _PillarArgs(p, widths, dev)
+    out = torch.empty(len(p.pillar_centers), dtype=torch.float64, device=dev)
+    g = grid_struct(p)
+    check(lib.rcp_width_grad(C.byref(g), C.byref(pa.struct), grad_eps.contiguous().data_ptr(),
+                             out.data_ptr(), _stream(stream)))
+    return out
+
+
+def solve(fac: Factors, B: torch.Tensor, conj_transpose: bool = False, tol: float = 1e-12,
+          max_refine: int = 10, stream=None):
+    """X = A^{-1} B (or A^{-dag} B) for B of shape (R, nx, ny) complex128."""
+    B = B.to(torch.complex128).contiguous()
+    if B.dim() == 2:
+        B = B.unsqueeze(0)
+    X = torch.empty_like(B)
+    st = _lib.SolveStats()
+    check(lib.rcp_solve_multi_rhs(fac.handle, B.shape[0], B.data_ptr(), X.data_ptr(),
+                                  1 if conj_transpose else 0, tol, max_refine, _stream(stream),
+                                  C.byref(st)))
+    return X, (int(st.iters), float(st.rel_residual))
+
+
+class IncoherentFOM(torch.autograd.Function):
+    """Angle-averaged FOM as a differentiable function of the pillar widths.
+
+    forward: widths -> eps (kernel) -> factor -> F = v^dag W v
+    backward: dF/dwidths from the adjoint solve and the eps(widths) chain rule.
+    """
+
+    @staticmethod
+    def forward(ctx, widths: torch.Tensor, problem: Problem, precision: int = RCP_FP64):
+        eps = eps_from_widths(problem, widths, device=widths.device)
+        fac = Factors(problem, eps, precision)
+        if widths.requires_grad:
+            F, g = adjoint_grad(fac, problem)
+            ctx.save_for_backward(width_grad(problem, g, widths))
+        else:
+            F = reciprocal_average(fac, problem)
+            ctx.save_for_backward(None)
+        fac.release()
+        return F
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (gw,) = ctx.saved_tensors
+        return (grad_out * gw if gw is not None else None), None, None

@@ -1,0 +1,382 @@
+// C ABI of librecip (declared in include/recip.h): argument checks, buffer
+// layout, and the host-side order of the steps of each call.
+#include <cmath>
+#include <new>
+#include <string>
+
+#include "rcp_internal.h"
+
+namespace rcp {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_check(hipError_t e, const char* what) {
+  g_err = std::string("HIP error ") + hipGetErrorString(e) + " in " + what;
+  return RCP_EHIP;
+}
+
+Layout compute_layout(int nx, int ny, int precision) {
+  Layout L{};
+  const int np = ceil_div(ny, TB) * TB, nt = np / TB;
+  const size_t tiles = size_t(nt) * (nt + 1) / 2;
+  const size_t eb = precision == RCP_FP64 ? 16 : 8;
+  const size_t N = size_t(nx) * ny;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  L.off_X = take(size_t(nx) * tiles * TB * TB * eb);
+  L.off_eps = take(N * 8);
+  L.off_sxc = take(size_t(nx) * 16);
+  L.off_sxf = take(size_t(nx + 1) * 16);
+  L.off_syc = take(size_t(ny) * 16);
+  L.off_syf = take(size_t(ny + 1) * 16);
+  L.off_dco = take(N * 16);
+  L.off_eco = take(N * 16);
+  L.off_cco = take(N * 16);
+  L.off_L = take(2 * size_t(np) * TB * eb);
+  L.off_Q = take(2 * size_t(np) * TB * eb);
+  L.off_P = take(2 * size_t(TB) * TB * 16);
+  L.off_health = take(size_t(nx) * nt * 8);
+  L.off_vec = take(NVEC * N * 16);
+  L.off_red = take((2 + 2 * ((N + 255) / 256)) * 8);
+  size_t cap = 2;
+  while (cap < 2 * size_t(nx)) cap <<= 1;
+  L.off_fft = take(4 * cap * 16);
+  L.total = o;
+  return L;
+}
+
+static size_t fft_capacity(int nx) {
+  size_t cap = 2;
+  while (cap < 2 * size_t(nx)) cap <<= 1;
+  return cap;
+}
+
+
+}  // namespace rcp
+
+using namespace rcp;
+
+namespace {
+
+constexpr double kRefineTol = 1e-12;
+constexpr int kRefineMax = 10;
+
+int check_grid(const rcp_grid* g) {
+  if (!g) return fail(RCP_EINVAL, "grid is NULL");
+  if (g->nx < 1 || g->ny < 1) return fail(RCP_EINVAL, "nx and ny must be positive");
+  if (g->npml < 0 || 2 * g->npml >= g->nx || 2 * g->npml >= g->ny)
+    return fail(RCP_EINVAL, "PML layers overlap or leave no physical region");
+  if (!(g->h > 0) || !(g->k0 > 0)) return fail(RCP_EINVAL, "h and k0 must be positive");
+  if (g->npml > 0 && (!(g->pml_R > 0 && g->pml_R < 1) || g->pml_m < 0))
+    return fail(RCP_EINVAL, "pml_R must lie in (0, 1) and pml_m >= 0");
+  if (ceil_div(g->ny, TB) * TB > 2048) return fail(RCP_EINVAL, "ny above 2048 is not supported");
+  return RCP_OK;
+}
+
+bool in_phys_x(const rcp_factors* f, int i) { return i >= f->npml && i < f->nx - f->npml; }
+bool in_phys_y(const rcp_factors* f, int j) { return j >= f->npml && j < f->ny - f->npml; }
+
+int check_objective(const rcp_factors* f, const rcp_objective* o) {
+  if (!o) return fail(RCP_EINVAL, "objective is NULL");
+  if (o->kind == RCP_CONCENTRATOR) {
+    if (!in_phys_x(f, o->i_f) || !in_phys_y(f, o->j_f))
+      return fail(RCP_EINVAL, "focus cell outside the physical region");
+  } else if (o->kind == RCP_COLLIMATOR) {
+    if (!in_phys_y(f, o->j_m)) return fail(RCP_EINVAL, "monitor row outside the physical region");
+    if (o->i0 >= o->i1 || !in_phys_x(f, o->i0) || !in_phys_x(f, o->i1 - 1))
+      return fail(RCP_EINVAL, "monitor columns empty or outside the physical region");
+    if (!(o->n_m > 0)) return fail(RCP_EINVAL, "monitor index must be positive");
+  } else {
+    return fail(RCP_EINVAL, "unknown objective kind");
+  }
+  return RCP_OK;
+}
+
+int check_light(const rcp_factors* f, const rcp_light* L, bool need_alpha) {
+  if (!L) return fail(RCP_EINVAL, "light is NULL");
+  if (!in_phys_y(f, L->j_s)) return fail(RCP_EINVAL, "incidence row outside the physical region");
+  if (L->i0 >= L->i1 || !in_phys_x(f, L->i0) || !in_phys_x(f, L->i1 - 1))
+    return fail(RCP_EINVAL, "incidence columns empty or outside the physical region");
+  if (!(L->n_s > 0)) return fail(RCP_EINVAL, "source medium index must be positive");
+  const double half_pi = 1.5707963267948966;
+  if (L->kind == RCP_CONE) {
+    if (!(L->c > 0 && L->c < half_pi)) return fail(RCP_EINVAL, "cone half-angle must lie in (0, pi/2)");
+  } else if (L->kind == RCP_ANNULUS) {
+    if (!(L->th1 >= 0 && L->th1 < L->th2 && L->th2 < half_pi))
+      return fail(RCP_EINVAL, "annulus needs 0 <= th1 < th2 < pi/2");
+  } else if (L->kind == RCP_SYMBOL_TABLE) {
+    if (need_alpha) return fail(RCP_EINVAL, "brute force needs a cone or annulus distribution");
+    if (!L->symbol_dev) return fail(RCP_EINVAL, "symbol table is NULL");
+  } else {
+    return fail(RCP_EINVAL, "unknown light kind");
+  }
+  return RCP_OK;
+}
+
+int reciprocal_field(rcp_factors* f, const rcp_objective* obj, double2* z, hipStream_t s) {
+  int lo, hi;
+  double2* w = f->vec[V_RHS];
+  int rc = objective_rhs(f, obj, w, &lo, &hi, s);
+  if (rc) return rc;
+  // z = A^{-dag} w = conj(A)^{-1} w  (A = A^T)
+  return solve_vec_refined(f, w, z, 1, lo, hi, kRefineTol, kRefineMax, s, nullptr);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rcp_last_error(void) { return g_err.c_str(); }
+
+int rcp_eps_from_widths(const rcp_grid* grid, const rcp_pillars* pillars, double* eps_out_dev,
+                        rcp_stream stream) {
+  if (!grid || grid->nx < 1 || grid->ny < 1) return fail(RCP_EINVAL, "bad grid");
+  if (!pillars || pillars->n < 0 || (pillars->n > 0 && (!pillars->centers_dev || !pillars->widths_dev)))
+    return fail(RCP_EINVAL, "bad pillar description");
+  if (!eps_out_dev) return fail(RCP_EINVAL, "eps_out_dev is NULL");
+  return launch_eps_from_widths(grid, pillars, eps_out_dev, stream);
+}
+
+size_t rcp_factor_bytes(const rcp_grid* grid, int32_t precision) {
+  if (check_grid(grid) != RCP_OK) return 0;
+  if (precision != RCP_FP64 && precision != RCP_FP32_REFINED) return 0;
+  return compute_layout(grid->nx, grid->ny, precision).total;
+}
+
+int rcp_factor(const rcp_grid* grid, int32_t precision, void* buf_dev, size_t buf_bytes,
+               rcp_stream stream, rcp_factors** out) {
+  if (!out) return fail(RCP_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!grid->eps_dev) return fail(RCP_EINVAL, "eps_dev is NULL");
+  if (precision != RCP_FP64 && precision != RCP_FP32_REFINED)
+    return fail(RCP_EINVAL, "unknown precision");
+  Layout L = compute_layout(grid->nx, grid->ny, precision);
+  if (!buf_dev || buf_bytes < L.total)
+    return fail(RCP_ENOMEM, "factor buffer holds " + std::to_string(buf_bytes) + " bytes, needs " +
+                                std::to_string(L.total));
+  if (reinterpret_cast<uintptr_t>(buf_dev) % 256 != 0)
+    return fail(RCP_EINVAL, "factor buffer must be 256-byte aligned");
+  rcp_factors* f = new (std::nothrow) rcp_factors();
+  if (!f) return fail(RCP_ENOMEM, "host allocation failed");
+  f->nx = grid->nx;
+  f->ny = grid->ny;
+  f->npml = grid->npml;
+  f->h = grid->h;
+  f->k0 = grid->k0;
+  f->pml_R = grid->pml_R;
+  f->pml_m = grid->pml_m;
+  f->precision = precision;
+  f->np = ceil_div(grid->ny, TB) * TB;
+  f->nt = f->np / TB;
+  f->tiles = size_t(f->nt) * (f->nt + 1) / 2;
+  f->block_elems = f->tiles * TB * TB;
+  f->elem_bytes = precision == RCP_FP64 ? 16 : 8;
+  f->m = grid->nx / 2;
+  f->fft_cap = fft_capacity(grid->nx);
+  f->lay = L;
+  char* b = static_cast<char*>(buf_dev);
+  f->base = b;
+  f->X = b + L.off_X;
+  f->eps = reinterpret_cast<double*>(b + L.off_eps);
+  f->sxc = reinterpret_cast<double2*>(b + L.off_sxc);
+  f->sxf = reinterpret_cast<double2*>(b + L.off_sxf);
+  f->syc = reinterpret_cast<double2*>(b + L.off_syc);
+  f->syf = reinterpret_cast<double2*>(b + L.off_syf);
+  f->dco = reinterpret_cast<double2*>(b + L.off_dco);
+  f->eco = reinterpret_cast<double2*>(b + L.off_eco);
+  f->cco = reinterpret_cast<double2*>(b + L.off_cco);
+  const size_t panel = size_t(f->np) * TB * f->elem_bytes;
+  for (int c = 0; c < 2; ++c) {
+    f->wsL[c] = b + L.off_L + c * panel;
+    f->wsQ[c] = b + L.off_Q + c * panel;
+    f->wsP[c] = reinterpret_cast<double2*>(b + L.off_P) + c * TB * TB;
+  }
+  f->health = reinterpret_cast<double*>(b + L.off_health);
+  const size_t N = size_t(f->nx) * f->ny;
+  for (int v = 0; v < NVEC; ++v) f->vec[v] = reinterpret_cast<double2*>(b + L.off_vec) + v * N;
+  f->red = reinterpret_cast<double*>(b + L.off_red);
+  for (int q = 0; q < 4; ++q) f->fft[q] = reinterpret_cast<double2*>(b + L.off_fft) + q * f->fft_cap;
+  f->last_iters = 0;
+  f->last_residual = 0.0;
+  rc = launch_assemble(f, grid->eps_dev, stream);
+  if (!rc) rc = factor_blocks(f, stream);
+  if (rc) {
+    delete f;
+    return rc;
+  }
+  *out = f;
+  return RCP_OK;
+}
+
+void rcp_factors_release(rcp_factors* f) { delete f; }
+
+int rcp_factors_info(const rcp_factors* f, int32_t* nx, int32_t* ny, int32_t* precision,
+                     int32_t* padded_n, int32_t* tile) {
+  if (!f) return fail(RCP_EINVAL, "factors is NULL");
+  if (nx) *nx = f->nx;
+  if (ny) *ny = f->ny;
+  if (precision) *precision = f->precision;
+  if (padded_n) *padded_n = f->np;
+  if (tile) *tile = TB;
+  return RCP_OK;
+}
+
+int rcp_last_solve_stats(const rcp_factors* f, rcp_solve_stats* st) {
+  if (!f || !st) return fail(RCP_EINVAL, "NULL argument");
+  st->iters = f->last_iters;
+  st->rel_residual = f->last_residual;
+  return RCP_OK;
+}
+
+int rcp_solve_multi_rhs(const rcp_factors* fc, int32_t nrhs, const void* B_dev, void* X_dev,
+                        int32_t conj_transpose, double tol, int32_t max_refine, rcp_stream stream,
+                        rcp_solve_stats* stats) {
+  rcp_factors* f = const_cast<rcp_factors*>(fc);
+  if (!f) return fail(RCP_EINVAL, "factors is NULL");
+  if (nrhs < 1) return fail(RCP_EINVAL, "nrhs must be >= 1");
+  if (!B_dev || !X_dev) return fail(RCP_EINVAL, "NULL right-hand side or solution");
+  const size_t N = size_t(f->nx) * f->ny;
+  const char* b0 = static_cast<const char*>(B_dev);
+  const char* x0 = static_cast<const char*>(X_dev);
+  const size_t bytes = size_t(nrhs) * N * 16;
+  if (b0 < x0 + bytes && x0 < b0 + bytes) return fail(RCP_EINVAL, "B and X must not overlap");
+  const double2* B = static_cast<const double2*>(B_dev);
+  double2* X = static_cast<double2*>(X_dev);
+  const int conjop = conj_transpose ? 1 : 0;
+  if (f->precision == RCP_FP64 && nrhs >= 8) {
+    int rc = solve_multi_fp64(f, nrhs, B, nullptr, 0, X, conjop, stream);
+    if (rc) return rc;
+    if (stats) {
+      stats->iters = 0;
+      stats->rel_residual = 0.0;
+    }
+    return RCP_OK;
+  }
+  double worst = 0.0;
+  int iters = 0;
+  for (int r = 0; r < nrhs; ++r) {
+    rcp_solve_stats st{};
+    int rc = solve_vec_refined(f, B + r * N, X + r * N, conjop, 0, f->nx - 1, tol, max_refine, stream,
+                               (stats || f->precision != RCP_FP64) ? &st : nullptr);
+    if (rc) return rc;
+    if (st.rel_residual > worst) worst = st.rel_residual;
+    if (st.iters > iters) iters = st.iters;
+  }
+  if (stats) {
+    stats->iters = iters;
+    stats->rel_residual = worst;
+  }
+  return RCP_OK;
+}
+
+int rcp_reciprocal_average(const rcp_factors* fc, const rcp_objective* obj, const rcp_light* light,
+                           double* F_dev, void* v_dev, void* z_dev, rcp_stream stream) {
+  rcp_factors* f = const_cast<rcp_factors*>(fc);
+  if (!f) return fail(RCP_EINVAL, "factors is NULL");
+  int rc = check_objective(f, obj);
+  if (!rc) rc = check_light(f, light, false);
+  if (rc) return rc;
+  if (!F_dev) return fail(RCP_EINVAL, "F_dev is NULL");
+  double2* z = z_dev ? static_cast<double2*>(z_dev) : f->vec[V_Z];
+  rc = reciprocal_field(f, obj, z, stream);
+  if (rc) return rc;
+  return toeplitz_form(f, light, z, F_dev, static_cast<double2*>(v_dev), nullptr, stream);
+}
+
+int rcp_adjoint_grad(const rcp_factors* fc, const rcp_objective* obj, const rcp_light* light,
+                     double* F_dev, double* grad_eps_dev, rcp_stream stream) {
+  rcp_factors* f = const_cast<rcp_factors*>(fc);
+  if (!f) return fail(RCP_EINVAL, "factors is NULL");
+  int rc = check_objective(f, obj);
+  if (!rc) rc = check_light(f, light, false);
+  if (rc) return rc;
+  if (!F_dev || !grad_eps_dev) return fail(RCP_EINVAL, "NULL output");
+  double2* z = f->vec[V_Z];
+  rc = reciprocal_field(f, obj, z, stream);
+  if (rc) return rc;
+  double2* Tv = f->fft[3];
+  rc = toeplitz_form(f, light, z, F_dev, nullptr, Tv, stream);
+  if (rc) return rc;
+  double2* arhs = f->vec[V_ARHS];
+  rc = scatter_line(f, light, Tv, arhs, stream);
+  if (rc) return rc;
+  double2* lam = f->vec[V_LAM];
+  rc = solve_vec_refined(f, arhs, lam, 0, light->i0, light->i1 - 1, kRefineTol, kRefineMax, stream,
+                         nullptr);
+  if (rc) return rc;
+  return grad_eps(f, lam, z, grad_eps_dev, stream);
+}
+
+int rcp_width_grad(const rcp_grid* grid, const rcp_pillars* pillars, const double* grad_eps_dev,
+                   double* grad_w_dev, rcp_stream stream) {
+  if (!grid || grid->nx < 1 || grid->ny < 1) return fail(RCP_EINVAL, "bad grid");
+  if (!pillars || pillars->n < 0) return fail(RCP_EINVAL, "bad pillar description");
+  if (!grad_eps_dev || (pillars->n > 0 && !grad_w_dev)) return fail(RCP_EINVAL, "NULL argument");
+  if (pillars->row0 < 0 || pillars->row0 + pillars->rows > grid->ny)
+    return fail(RCP_EINVAL, "pillar rows outside the grid");
+  return launch_width_grad(grid, pillars, grad_eps_dev, grad_w_dev, stream);
+}
+
+size_t rcp_brute_force_work_bytes(const rcp_factors* f, int32_t nangles, int32_t rhs_chunk) {
+  if (!f || nangles < 1 || rhs_chunk < 1) return 0;
+  const size_t N = size_t(f->nx) * f->ny;
+  size_t o = 0;
+  o = align256(o + 3 * size_t(nangles) * 8);
+  o = align256(o + size_t(rhs_chunk) * f->nx * 16);
+  o = align256(o + size_t(rhs_chunk) * N * 16);
+  return o;
+}
+
+int rcp_brute_force_average(const rcp_factors* fc, const rcp_objective* obj, const rcp_light* light,
+                            int32_t nangles, int32_t rhs_chunk, void* work_dev, size_t work_bytes,
+                            double* F_dev, double* per_angle_dev, rcp_stream stream) {
+  rcp_factors* f = const_cast<rcp_factors*>(fc);
+  if (!f) return fail(RCP_EINVAL, "factors is NULL");
+  if (f->precision != RCP_FP64)
+    return fail(RCP_EINVAL, "the brute-force baseline runs on RCP_FP64 factors");
+  int rc = check_objective(f, obj);
+  if (!rc) rc = check_light(f, light, true);
+  if (rc) return rc;
+  if (nangles < 1 || rhs_chunk < 1) return fail(RCP_EINVAL, "nangles and rhs_chunk must be >= 1");
+  if (light->kind == RCP_ANNULUS && nangles % 2)
+    return fail(RCP_EINVAL, "annulus needs an even node count");
+  if (!F_dev) return fail(RCP_EINVAL, "F_dev is NULL");
+  size_t need = rcp_brute_force_work_bytes(f, nangles, rhs_chunk);
+  if (!work_dev || work_bytes < need)
+    return fail(RCP_ENOMEM, "brute-force workspace needs " + std::to_string(need) + " bytes");
+  char* w = static_cast<char*>(work_dev);
+  double* theta = reinterpret_cast<double*>(w);
+  double* wts = theta + nangles;
+  double* pa = per_angle_dev ? per_angle_dev : wts + nangles;
+  size_t o = align256(3 * size_t(nangles) * 8);
+  double2* fline = reinterpret_cast<double2*>(w + o);
+  o = align256(o + size_t(rhs_chunk) * f->nx * 16);
+  double2* U = reinterpret_cast<double2*>(w + o);
+  rc = gl_nodes(light, nangles, theta, wts, stream);
+  if (rc) return rc;
+  for (int r0 = 0; r0 < nangles; r0 += rhs_chunk) {
+    int R = nangles - r0 < rhs_chunk ? nangles - r0 : rhs_chunk;
+    rc = planewave_lines(f, light, theta + r0, R, fline, stream);
+    if (rc) return rc;
+    rc = solve_multi_fp64(f, R, nullptr, fline, light->j_s, U, 0, stream);
+    if (rc) return rc;
+    rc = bf_per_angle_at(f, obj, U, R, pa, r0, stream);
+    if (rc) return rc;
+  }
+  return bf_sum(wts, pa, nangles, F_dev, stream);
+}
+
+}  // extern "C"

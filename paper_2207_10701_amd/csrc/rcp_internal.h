@@ -1,0 +1,195 @@
+// Internal declarations of librecip: the factor handle, device helpers and the
+// host-side launchers each translation unit exports to the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "recip.h"
+
+namespace rcp {
+
+// Storage tile edge and Gauss-Jordan panel width.  A Schur-complement block of
+// size ny is padded to np = ceil(ny / TB) * TB (identity in the padding) and
+// stored as its lower-triangular TB x TB tiles, packed row by row:
+// tile (I, J), I >= J, sits at index I (I + 1) / 2 + J, row-major inside.
+constexpr int TB = 32;
+constexpr int NVEC = 8;          // complex128 work vectors of nx*ny in the buffer
+
+// Work-vector roles.
+enum { V_Z = 0, V_Y = 1, V_RHS = 2, V_LAM = 3, V_ARHS = 4, V_RES = 5, V_DU = 6, V_TMP = 7 };
+
+struct Layout {
+  size_t off_X, off_eps, off_sxc, off_sxf, off_syc, off_syf;
+  size_t off_dco, off_eco, off_cco;
+  size_t off_L, off_Q, off_P;     // GJ panel workspace, 2 chains each
+  size_t off_health, off_vec, off_red, off_fft;
+  size_t total;
+};
+
+}  // namespace rcp
+
+struct rcp_factors {
+  int nx, ny, npml;
+  double h, k0, pml_R;
+  int pml_m;
+  int precision;
+  int np, nt;                 // padded block size, tiles per edge
+  size_t tiles;               // packed tiles per block = nt (nt + 1) / 2
+  size_t block_elems;         // complex elements per block = tiles * TB * TB
+  size_t elem_bytes;          // 16 (complex128) or 8 (complex64)
+  int m;                      // middle block of the twisted elimination
+  size_t fft_cap;             // complex128 capacity of each FFT buffer
+  char* base;
+  rcp::Layout lay;
+  void* X;
+  double* eps;
+  double2 *sxc, *sxf, *syc, *syf;
+  double2 *dco, *eco, *cco;
+  void* wsL[2];
+  void* wsQ[2];
+  double2* wsP[2];
+  double* health;
+  double2* vec[rcp::NVEC];
+  double* red;
+  double2* fft[4];            // symbol spectrum, work, temp, W v
+  // statistics of the last refined solve
+  int last_iters;
+  double last_residual;
+};
+
+namespace rcp {
+
+// ---------------------------------------------------------------------------
+// error plumbing
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_check(hipError_t e, const char* what);
+
+#define RCP_HIP(call)                                   \
+  do {                                                  \
+    hipError_t _e = (call);                             \
+    if (_e != hipSuccess) return rcp::hip_check(_e, #call); \
+  } while (0)
+
+Layout compute_layout(int nx, int ny, int precision);
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+__host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+inline void* block_ptr(const rcp_factors* f, int i) {
+  return static_cast<char*>(f->X) + size_t(i) * f->block_elems * f->elem_bytes;
+}
+
+// ---------------------------------------------------------------------------
+// launchers (assembly.hip)
+int launch_eps_from_widths(const rcp_grid* g, const rcp_pillars* p, double* eps, hipStream_t s);
+int launch_assemble(rcp_factors* f, const double* eps_src, hipStream_t s);
+int launch_width_grad(const rcp_grid* g, const rcp_pillars* p, const double* grad_eps,
+                      double* grad_w, hipStream_t s);
+
+// factor.hip
+int factor_blocks(rcp_factors* f, hipStream_t s);
+
+// solve.hip
+// u = A^{-1} f (conjop = 0) or conj(A)^{-1} f = A^{-dag} f (conjop = 1), one
+// right-hand side, f and u complex128 nx*ny, f != u.  Blocks outside
+// [nz_lo, nz_hi] of f are known to be zero.
+int solve_vec(rcp_factors* f, const double2* rhs, double2* u, int conjop, int nz_lo, int nz_hi,
+              hipStream_t s);
+// Refined (FP32 factors) or plain (FP64) single-RHS solve with statistics.
+int solve_vec_refined(rcp_factors* f, const double2* rhs, double2* u, int conjop, int nz_lo,
+                      int nz_hi, double tol, int max_refine, hipStream_t s, rcp_solve_stats* st);
+// nrhs right-hand sides in (R, nx, ny) layout, FP64 factors.  If fline != null
+// the right-hand sides are line sources: fline[r * nx + i] on row jline.
+int solve_multi_fp64(rcp_factors* f, int nrhs, const double2* B, const double2* fline, int jline,
+                     double2* X, int conjop, hipStream_t s);
+int residual_norms(rcp_factors* f, const double2* b, const double2* x, double2* r, int conjop,
+                   hipStream_t s, double* rnorm, double* bnorm);
+
+// form.hip
+int objective_rhs(rcp_factors* f, const rcp_objective* o, double2* w, int* nz_lo, int* nz_hi,
+                  hipStream_t s);
+int toeplitz_form(rcp_factors* f, const rcp_light* L, const double2* z, double* F_dev,
+                  double2* v_out, double2* Tv_out, hipStream_t s);
+int grad_eps(rcp_factors* f, const double2* lam, const double2* z, double* grad, hipStream_t s);
+int scatter_line(rcp_factors* f, const rcp_light* L, const double2* Tv, double2* rhs,
+                 hipStream_t s);
+int bf_per_angle_at(rcp_factors* f, const rcp_objective* o, const double2* U, int R,
+                    double* per_angle, int r0, hipStream_t s);
+int gl_nodes(const rcp_light* L, int n, double* theta, double* wts, hipStream_t s);
+int planewave_lines(rcp_factors* f, const rcp_light* L, const double* theta, int R,
+                    double2* fline, hipStream_t s);
+int bf_sum(const double* weights, const double* per_angle, int n, double* F_dev, hipStream_t s);
+int fill_zero(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace rcp
+
+// ---------------------------------------------------------------------------
+// device helpers
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ double2 csub(double2 a, double2 b) {
+  return make_double2(a.x - b.x, a.y - b.y);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) {
+  return make_double2(a.x * s, a.y * s);
+}
+__device__ __forceinline__ double2 cinv(double2 a) {
+  double d = a.x * a.x + a.y * a.y;
+  return make_double2(a.x / d, -a.y / d);
+}
+__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+template <typename T> struct cplx;
+template <> struct cplx<double> { using t = double2; };
+template <> struct cplx<float> { using t = float2; };
+
+__device__ __forceinline__ double2 to_c128(double2 a) { return a; }
+__device__ __forceinline__ double2 to_c128(float2 a) { return make_double2(a.x, a.y); }
+template <typename T2> __device__ __forceinline__ T2 from_c128(double2 a);
+template <> __device__ __forceinline__ double2 from_c128<double2>(double2 a) { return a; }
+template <> __device__ __forceinline__ float2 from_c128<float2>(double2 a) {
+  return make_float2(static_cast<float>(a.x), static_cast<float>(a.y));
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+template <typename T> struct v4of;
+template <> struct v4of<double> { using t = v4d; };
+template <> struct v4of<float> { using t = v4f; };
+
+// One 16x16x4 matrix-core product D = A B + C per wave.  Lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; D column l % 16 lands in lane l, and
+// register r of that lane holds D row mfma_row<T>(l / 16, r): 4 (l / 16) + r
+// for the f32 instruction, l / 16 + 4 r for the f64 one (both checked on gfx950).
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T> __device__ __forceinline__ int mfma_row(int lk, int r);
+template <> __device__ __forceinline__ int mfma_row<double>(int lk, int r) { return lk + 4 * r; }
+template <> __device__ __forceinline__ int mfma_row<float>(int lk, int r) { return 4 * lk + r; }
+
+// packed lower-tile index helpers
+__host__ __device__ __forceinline__ size_t tile_index(int I, int J) {
+  return size_t(I) * (I + 1) / 2 + J;
+}
+__device__ __forceinline__ void tile_coords(int t, int* I, int* J) {
+  int i = static_cast<int>((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  *I = i;
+  *J = t - i * (i + 1) / 2;
+}

@@ -1,0 +1,538 @@
+// Forward / back substitution with the block inverses of the twisted
+// elimination (the single reciprocal solve of Sec. "Reciprocal approach", and
+// the many forward solves of the brute-force average, Eq. 6).
+//
+// With X_i the stored block inverses and middle block m:
+//   forward left   g_i = X_i (f_i - C_{i-1} g_{i-1}),   i = 0 .. m-1
+//   forward right  g_i = X_i (f_i - C_i g_{i+1}),       i = nx-1 .. m+1
+//   middle         u_m = X_m (f_m - C_{m-1} g_{m-1} - C_m g_{m+1})
+//   back left      u_i = g_i - X_i (C_i u_{i+1}),       i = m-1 .. 0
+//   back right     u_i = g_i - X_i (C_{i-1} u_{i-1}),   i = m+1 .. nx-1
+// conj(A)^{-1} (= A^{-dag}, since A = A^T) uses conj(X_i) and conj(C_i).
+// One right-hand side: a matrix-vector product per block, bound by reading
+// the packed lower tiles once.  Many right-hand sides: an MFMA GEMM per block.
+#include <cmath>
+#include <vector>
+
+#include "rcp_internal.h"
+
+namespace {
+using namespace rcp;
+
+constexpr int NPMAX = 2048;   // largest padded block size the vector sweep keeps in LDS
+
+struct SvJob {
+  const void* X;
+  double2* out;
+  const double2* base;   // out = base + X g (base may be null)
+  const double2* f;      // g = f - C1 v1 - C2 v2 (each term optional)
+  const double2* v1;
+  const double2* c1;
+  const double2* v2;
+  const double2* c2;
+};
+struct SvJobs {
+  SvJob j[2];
+  int n;
+};
+
+__device__ __forceinline__ double2 maybe_conj(double2 a, int c) {
+  return c ? make_double2(a.x, -a.y) : a;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemv(SvJobs jobs, int nt, int ny, int conjop) {
+  using T2 = typename cplx<T>::t;
+  __shared__ double2 g[NPMAX];
+  __shared__ double2 red[TB][TB + 1];
+  __shared__ double2 rowsum[TB];
+  const int ji = blockIdx.x / nt, I = blockIdx.x % nt;
+  SvJob jb = jobs.j[0];
+  if (ji == 1) jb = jobs.j[1];
+  const int tid = threadIdx.x;
+  const int np = nt * TB;
+  for (int k = tid; k < np; k += 256) {
+    double2 v = make_double2(0.0, 0.0);
+    if (k < ny) {
+      if (jb.f) v = jb.f[k];
+      if (jb.v1) v = csub(v, cmul(maybe_conj(jb.c1[k], conjop), jb.v1[k]));
+      if (jb.v2) v = csub(v, cmul(maybe_conj(jb.c2[k], conjop), jb.v2[k]));
+    }
+    g[k] = v;
+  }
+  __syncthreads();
+  const T2* X = static_cast<const T2*>(jb.X);
+  const int r = tid >> 3, c0 = (tid & 7) * 4;
+  const double cs = conjop ? -1.0 : 1.0;
+  double2 arow = make_double2(0.0, 0.0);
+  double2 acol[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acol[c] = make_double2(0.0, 0.0);
+  // tiles (I, J), J <= I: rows of this strip
+  for (int J = 0; J <= I; ++J) {
+    const T2* t = X + tile_index(I, J) * TB * TB + r * TB + c0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double2 x = to_c128(t[c]);
+      x.y *= cs;
+      arow = cadd(arow, cmul(x, g[J * TB + c0 + c]));
+    }
+  }
+  // tiles (J, I), J > I: X(I-rows, J-cols) = tile(J, I)^T
+  for (int J = I + 1; J < nt; ++J) {
+    const T2* t = X + tile_index(J, I) * TB * TB + r * TB + c0;
+    double2 gv = g[J * TB + r];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double2 x = to_c128(t[c]);
+      x.y *= cs;
+      acol[c] = cadd(acol[c], cmul(x, gv));
+    }
+  }
+  // reduce
+#pragma unroll
+  for (int off = 1; off < 8; off <<= 1) {
+    arow.x += __shfl_xor(arow.x, off, 64);
+    arow.y += __shfl_xor(arow.y, off, 64);
+  }
+  if ((tid & 7) == 0) rowsum[r] = arow;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) red[r][c0 + c] = acol[c];
+  __syncthreads();
+  if (tid < TB) {
+    double2 s = rowsum[tid];
+    for (int q = 0; q < TB; ++q) s = cadd(s, red[q][tid]);
+    int row = I * TB + tid;
+    if (row < ny) {
+      double2 b = jb.base ? jb.base[row] : make_double2(0.0, 0.0);
+      jb.out[row] = cadd(b, s);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Many right-hand sides: out[r, :] = base[r, :] + (in[r, :] X)  (X symmetric),
+// in[r, k] = f[r, k] (+ line source) - C1 v1[r, k] - C2 v2[r, k].
+// Rows r of one block sit rstride apart (layout R x nx x ny).
+struct MmJob {
+  const double2* X;
+  double2* out;
+  const double2* base;
+  const double2* f;
+  const double2* fline;   // R x nx line-source values on row jline, or null
+  const double2* v1;
+  const double2* c1;
+  const double2* v2;
+  const double2* c2;
+  int block;
+};
+struct MmJobs {
+  MmJob j[2];
+  int n;
+};
+
+constexpr int MT = 64;   // workgroup tile (rows r) x (columns j)
+
+__global__ __launch_bounds__(256) void k_gemm_sweep(MmJobs jobs, int R, int nx, int ny, int nt,
+                                                     size_t rstride, int jline, int conjop) {
+  __shared__ double2 As[MT][TB + 1];
+  __shared__ double2 Bs[TB][MT + 1];
+  const int ntile_r = ceil_div(R, MT), ntile_j = ceil_div(nt * TB, MT);
+  const int per_job = ntile_r * ntile_j;
+  const int ji = blockIdx.x / per_job;
+  const int w = blockIdx.x % per_job;
+  const int rt = w / ntile_j, jt = w % ntile_j;
+  MmJob jb = jobs.j[0];
+  if (ji == 1) jb = jobs.j[1];
+  const int r0 = rt * MT, j0 = jt * MT;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  const size_t boff = size_t(jb.block) * ny;
+  v4d cre[2][2], cim[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cre[a][b] = v4d{0, 0, 0, 0};
+      cim[a][b] = v4d{0, 0, 0, 0};
+    }
+  for (int kt = 0; kt < nt; ++kt) {
+    // A tile: 64 rows x 32 k
+    for (int e = tid; e < MT * TB; e += 256) {
+      int rr = e / TB, kk = e % TB;
+      int r = r0 + rr, k = kt * TB + kk;
+      double2 v = make_double2(0.0, 0.0);
+      if (r < R && k < ny) {
+        size_t q = size_t(r) * rstride + boff + k;
+        if (jb.f) v = jb.f[q];
+        if (jb.fline && k == jline) v = cadd(v, jb.fline[size_t(r) * nx + jb.block]);
+        if (jb.v1) v = csub(v, cmul(maybe_conj(jb.c1[k], conjop), jb.v1[q]));
+        if (jb.v2) v = csub(v, cmul(maybe_conj(jb.c2[k], conjop), jb.v2[q]));
+      }
+      As[rr][kk] = v;
+    }
+    // B tile: X[kt*TB + kk][j0 + jj], jj < 64 (two storage tiles)
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      int jt2 = (j0 / TB) + half;
+      for (int e = tid; e < TB * TB; e += 256) {
+        int a = e / TB, b = e % TB;   // contiguous in memory order
+        double2 x = make_double2(0.0, 0.0);
+        int kk, jj;
+        if (jt2 < nt) {
+          if (kt >= jt2) {
+            x = jb.X[tile_index(kt, jt2) * TB * TB + e];
+            kk = a;
+            jj = b;
+          } else {
+            x = jb.X[tile_index(jt2, kt) * TB * TB + e];
+            kk = b;
+            jj = a;
+          }
+        } else {
+          kk = a;
+          jj = b;
+        }
+        if (conjop) x.y = -x.y;
+        Bs[kk][half * TB + jj] = x;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      double2 av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[32 * wr + 16 * a + lr][4 * s + lk];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[4 * s + lk][32 * wc + 16 * b + lr];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        double naim = -av[a].y;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          cre[a][b] = mfma16(av[a].x, bv[b].x, cre[a][b]);
+          cre[a][b] = mfma16(naim, bv[b].y, cre[a][b]);
+          cim[a][b] = mfma16(av[a].x, bv[b].y, cim[a][b]);
+          cim[a][b] = mfma16(av[a].y, bv[b].x, cim[a][b]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int r = r0 + 32 * wr + 16 * a + mfma_row<double>(lk, q);
+        int j = j0 + 32 * wc + 16 * b + lr;
+        if (r < R && j < ny) {
+          size_t o = size_t(r) * rstride + boff + j;
+          double2 v = make_double2(cre[a][b][q], cim[a][b][q]);
+          if (jb.base) v = cadd(v, jb.base[o]);
+          jb.out[o] = v;
+        }
+      }
+}
+
+// r = b - A x  (conj(A) if conjop) and per-workgroup partial sums of |r|^2, |b|^2
+__global__ __launch_bounds__(256) void k_residual(int nx, int ny, const double2* __restrict__ dco,
+                                                   const double2* __restrict__ eco,
+                                                   const double2* __restrict__ cco,
+                                                   const double2* __restrict__ b,
+                                                   const double2* __restrict__ x,
+                                                   double2* __restrict__ r, int conjop,
+                                                   double* __restrict__ part) {
+  __shared__ double sr[256], sb[256];
+  size_t q = size_t(blockIdx.x) * 256 + threadIdx.x;
+  double rr = 0.0, bb = 0.0;
+  if (q < size_t(nx) * ny) {
+    int i = static_cast<int>(q / ny), j = static_cast<int>(q % ny);
+    double2 ax = cmul(maybe_conj(dco[q], conjop), x[q]);
+    if (i > 0) ax = cadd(ax, cmul(maybe_conj(cco[q - ny], conjop), x[q - ny]));
+    if (i + 1 < nx) ax = cadd(ax, cmul(maybe_conj(cco[q], conjop), x[q + ny]));
+    if (j > 0) ax = cadd(ax, cmul(maybe_conj(eco[q - 1], conjop), x[q - 1]));
+    if (j + 1 < ny) ax = cadd(ax, cmul(maybe_conj(eco[q], conjop), x[q + 1]));
+    double2 bv = b[q];
+    double2 rv = csub(bv, ax);
+    if (r) r[q] = rv;
+    rr = cabs2(rv);
+    bb = cabs2(bv);
+  }
+  sr[threadIdx.x] = rr;
+  sb[threadIdx.x] = bb;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      sb[threadIdx.x] += sb[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sr[0];
+    part[2 * blockIdx.x + 1] = sb[0];
+  }
+}
+
+// fixed-order final sum of n pairs -> out[0], out[1]
+__global__ void k_sum_pairs(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double sa[256], sb[256];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sa[threadIdx.x] += sa[threadIdx.x + s];
+      sb[threadIdx.x] += sb[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sa[0];
+    out[1] = sb[0];
+  }
+}
+
+__global__ void k_axpy(size_t n, const double2* __restrict__ dx, double2* __restrict__ x) {
+  size_t q = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q < n) x[q] = cadd(x[q], dx[q]);
+}
+
+template <typename T>
+int run_solve_vec(rcp_factors* f, const double2* rhs, double2* u, int conjop, int nz_lo, int nz_hi,
+                  hipStream_t s) {
+  const int N = f->nx, ny = f->ny, nt = f->nt, m = f->m;
+  if (f->np > NPMAX) return fail(RCP_EINVAL, "block size too large for the vector sweep");
+  const int lenL = m, lenR = N - 1 - m;
+  auto U = [&](int i) { return u + size_t(i) * ny; };
+  auto Fb = [&](int i) { return rhs + size_t(i) * ny; };
+  auto C = [&](int i) { return f->cco + size_t(i) * ny; };
+  auto launch = [&](SvJobs& js) -> int {
+    if (js.n == 0) return RCP_OK;
+    k_gemv<T><<<nt * js.n, 256, 0, s>>>(js, nt, ny, conjop);
+    RCP_HIP(hipGetLastError());
+    return RCP_OK;
+  };
+  // forward sweeps; g_i is known zero while no source block has been passed
+  std::vector<char> zero(N, 0);
+  const int steps = lenL > lenR ? lenL : lenR;
+  for (int st = 0; st < steps; ++st) {
+    SvJobs js{};
+    if (st < lenL) {
+      int i = st;
+      bool prevz = (i == 0) || zero[i - 1];
+      if (i < nz_lo && prevz) {
+        zero[i] = 1;
+      } else {
+        js.j[js.n++] = SvJob{block_ptr(f, i), U(i), nullptr, Fb(i), prevz ? nullptr : U(i - 1),
+                             i > 0 ? C(i - 1) : nullptr, nullptr, nullptr};
+      }
+    }
+    if (st < lenR) {
+      int i = N - 1 - st;
+      bool prevz = (i == N - 1) || zero[i + 1];
+      if (i > nz_hi && prevz) {
+        zero[i] = 1;
+      } else {
+        js.j[js.n++] = SvJob{block_ptr(f, i), U(i), nullptr, Fb(i), prevz ? nullptr : U(i + 1),
+                             i < N - 1 ? C(i) : nullptr, nullptr, nullptr};
+      }
+    }
+    int rc = launch(js);
+    if (rc) return rc;
+  }
+  {
+    SvJobs js{};
+    SvJob z{block_ptr(f, m), U(m), nullptr, Fb(m), nullptr, nullptr, nullptr, nullptr};
+    if (m - 1 >= 0 && !zero[m - 1]) {
+      z.v1 = U(m - 1);
+      z.c1 = C(m - 1);
+    }
+    if (m + 1 < N && !zero[m + 1]) {
+      z.v2 = U(m + 1);
+      z.c2 = C(m);
+    }
+    js.j[js.n++] = z;
+    int rc = launch(js);
+    if (rc) return rc;
+  }
+  for (int st = 0; st < steps; ++st) {
+    SvJobs js{};
+    if (st < lenL) {
+      int i = m - 1 - st;
+      js.j[js.n++] = SvJob{block_ptr(f, i), U(i), zero[i] ? nullptr : U(i), nullptr, U(i + 1), C(i),
+                           nullptr, nullptr};
+    }
+    if (st < lenR) {
+      int i = m + 1 + st;
+      js.j[js.n++] = SvJob{block_ptr(f, i), U(i), zero[i] ? nullptr : U(i), nullptr, U(i - 1),
+                           C(i - 1), nullptr, nullptr};
+    }
+    int rc = launch(js);
+    if (rc) return rc;
+  }
+  return RCP_OK;
+}
+
+}  // namespace
+
+namespace rcp {
+
+int solve_vec(rcp_factors* f, const double2* rhs, double2* u, int conjop, int nz_lo, int nz_hi,
+              hipStream_t s) {
+  if (f->precision == RCP_FP64) return run_solve_vec<double>(f, rhs, u, conjop, nz_lo, nz_hi, s);
+  return run_solve_vec<float>(f, rhs, u, conjop, nz_lo, nz_hi, s);
+}
+
+int residual_norms(rcp_factors* f, const double2* b, const double2* x, double2* r, int conjop,
+                   hipStream_t s, double* rnorm, double* bnorm) {
+  size_t N = size_t(f->nx) * f->ny;
+  int blocks = static_cast<int>((N + 255) / 256);
+  // partial sums live in the reduction scratch after a 2-double result slot
+  double* part = f->red + 2;
+  k_residual<<<blocks, 256, 0, s>>>(f->nx, f->ny, f->dco, f->eco, f->cco, b, x, r, conjop, part);
+  RCP_HIP(hipGetLastError());
+  k_sum_pairs<<<1, 256, 0, s>>>(part, blocks, f->red);
+  RCP_HIP(hipGetLastError());
+  double h[2];
+  RCP_HIP(hipMemcpyAsync(h, f->red, sizeof(h), hipMemcpyDeviceToHost, s));
+  RCP_HIP(hipStreamSynchronize(s));
+  *rnorm = std::sqrt(h[0]);
+  *bnorm = std::sqrt(h[1]);
+  return RCP_OK;
+}
+
+int solve_vec_refined(rcp_factors* f, const double2* rhs, double2* u, int conjop, int nz_lo,
+                      int nz_hi, double tol, int max_refine, hipStream_t s, rcp_solve_stats* st) {
+  int rc = solve_vec(f, rhs, u, conjop, nz_lo, nz_hi, s);
+  if (rc) return rc;
+  if (f->precision == RCP_FP64) {
+    if (st) {
+      double rn, bn;
+      rc = residual_norms(f, rhs, u, nullptr, conjop, s, &rn, &bn);
+      if (rc) return rc;
+      st->iters = 0;
+      st->rel_residual = bn > 0 ? rn / bn : 0.0;
+    }
+    return RCP_OK;
+  }
+  double2* r = f->vec[V_RES];
+  double2* du = f->vec[V_DU];
+  size_t N = size_t(f->nx) * f->ny;
+  int it = 0;
+  double rel = 0.0;
+  for (;;) {
+    double rn, bn;
+    rc = residual_norms(f, rhs, u, r, conjop, s, &rn, &bn);
+    if (rc) return rc;
+    rel = bn > 0 ? rn / bn : 0.0;
+    if (rel <= tol) break;
+    if (it >= max_refine) {
+      f->last_iters = it;
+      f->last_residual = rel;
+      if (st) {
+        st->iters = it;
+        st->rel_residual = rel;
+      }
+      return fail(RCP_ENOCONV, "refinement stopped after " + std::to_string(it) +
+                                   " steps at relative residual " + std::to_string(rel));
+    }
+    rc = solve_vec(f, r, du, conjop, 0, f->nx - 1, s);
+    if (rc) return rc;
+    k_axpy<<<static_cast<int>((N + 255) / 256), 256, 0, s>>>(N, du, u);
+    RCP_HIP(hipGetLastError());
+    ++it;
+  }
+  f->last_iters = it;
+  f->last_residual = rel;
+  if (st) {
+    st->iters = it;
+    st->rel_residual = rel;
+  }
+  return RCP_OK;
+}
+
+int solve_multi_fp64(rcp_factors* f, int R, const double2* B, const double2* fline, int jline,
+                     double2* Xo, int conjop, hipStream_t s) {
+  const int N = f->nx, ny = f->ny, nt = f->nt, m = f->m;
+  const size_t rs = size_t(N) * ny;
+  const int lenL = m, lenR = N - 1 - m;
+  auto O = [&](int i) { return Xo + size_t(i) * ny; };
+  auto Bb = [&](int i) { return B ? B + size_t(i) * ny : nullptr; };
+  auto C = [&](int i) { return f->cco + size_t(i) * ny; };
+  const int per_job = ceil_div(R, MT) * ceil_div(nt * TB, MT);
+  auto launch = [&](MmJobs& js) -> int {
+    if (js.n == 0) return RCP_OK;
+    k_gemm_sweep<<<per_job * js.n, 256, 0, s>>>(js, R, N, ny, nt, rs, jline, conjop);
+    RCP_HIP(hipGetLastError());
+    return RCP_OK;
+  };
+  // job pointers address block i inside row 0; the kernel adds r * rstride
+  auto job = [&](int i, double2* out, const double2* base, const double2* fb, const double2* v1,
+                 const double2* c1, const double2* v2, const double2* c2) {
+    MmJob j{};
+    j.X = static_cast<const double2*>(block_ptr(f, i));
+    j.out = out - size_t(i) * ny;       // kernel adds block offset
+    j.base = base ? base - size_t(i) * ny : nullptr;
+    j.f = fb ? fb - size_t(i) * ny : nullptr;
+    j.fline = fline;
+    j.v1 = v1 ? v1 - size_t(i) * ny : nullptr;
+    j.c1 = c1;
+    j.v2 = v2 ? v2 - size_t(i) * ny : nullptr;
+    j.c2 = c2;
+    j.block = i;
+    return j;
+  };
+  const int steps = lenL > lenR ? lenL : lenR;
+  for (int st = 0; st < steps; ++st) {
+    MmJobs js{};
+    if (st < lenL) {
+      int i = st;
+      js.j[js.n++] = job(i, O(i), nullptr, Bb(i), i > 0 ? O(i - 1) : nullptr,
+                         i > 0 ? C(i - 1) : nullptr, nullptr, nullptr);
+    }
+    if (st < lenR) {
+      int i = N - 1 - st;
+      js.j[js.n++] = job(i, O(i), nullptr, Bb(i), i < N - 1 ? O(i + 1) : nullptr,
+                         i < N - 1 ? C(i) : nullptr, nullptr, nullptr);
+    }
+    int rc = launch(js);
+    if (rc) return rc;
+  }
+  {
+    MmJobs js{};
+    js.j[js.n++] = job(m, O(m), nullptr, Bb(m), m > 0 ? O(m - 1) : nullptr,
+                       m > 0 ? C(m - 1) : nullptr, m + 1 < N ? O(m + 1) : nullptr,
+                       m + 1 < N ? C(m) : nullptr);
+    int rc = launch(js);
+    if (rc) return rc;
+  }
+  for (int st = 0; st < steps; ++st) {
+    MmJobs js{};
+    if (st < lenL) {
+      int i = m - 1 - st;
+      MmJob j = job(i, O(i), O(i), nullptr, O(i + 1), C(i), nullptr, nullptr);
+      j.fline = nullptr;
+      js.j[js.n++] = j;
+    }
+    if (st < lenR) {
+      int i = m + 1 + st;
+      MmJob j = job(i, O(i), O(i), nullptr, O(i - 1), C(i - 1), nullptr, nullptr);
+      j.fline = nullptr;
+      js.j[js.n++] = j;
+    }
+    int rc = launch(js);
+    if (rc) return rc;
+  }
+  return RCP_OK;
+}
+
+}  // namespace rcp

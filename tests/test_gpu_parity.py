@@ -1,0 +1,136 @@
+"""GPU path (librecip through its C ABI) against the FP64 CPU oracle.
+
+Tolerances: FP64 path 1e-10 relative on fields and averages; refined FP32 path
+1e-8 on fields and 1e-6 on averages; gradients 1e-5 relative (the FP64 path is
+held to 1e-9).
+"""
+from functools import lru_cache
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import average as ora
+from oracle import fdfd, light
+
+pytestmark = pytest.mark.gpu
+
+
+@lru_cache(maxsize=None)
+def oracle_setup(p):
+    return ora.setup(p)
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+
+
+def gpu_factors(rcp, p, precision=None):
+    import torch
+    precision = rcp.RCP_FP64 if precision is None else precision
+    eps = rcp.eps_from_widths(p, device="cuda")
+    fac = rcp.Factors(p, eps, precision)
+    torch.cuda.synchronize()
+    return fac, eps
+
+
+PROBLEMS = {
+    "conc_cone": W.small_problem(4, 4, seed=7),
+    "coll_annulus": W.small_problem(5, 4, seed=8, objective=W.COLLIMATOR, light=W.ANNULUS,
+                                    th1_deg=6.0, th2_deg=25.0, monitor_y=3.0, phi=0.1),
+    "conc_odd": W.small_problem(3, 5, seed=9, npml=8, c_deg=30.0),
+}
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_eps_map_matches_oracle(rcp, name):
+    p = PROBLEMS[name]
+    eps = rcp.eps_from_widths(p, device="cuda").cpu().numpy()
+    ref = fdfd.permittivity(p)
+    assert np.max(np.abs(eps - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_solve_fp64_matches_superlu(rcp, name):
+    import torch
+    p = PROBLEMS[name]
+    fac, _ = gpu_factors(rcp, p)
+    s = oracle_setup(p)
+    B = W.complex_normal((3, p.nx * p.ny), seed=11)
+    X, _ = rcp.solve(fac, torch.from_numpy(B.reshape(3, p.nx, p.ny)).cuda())
+    ref = s.solve(B.T).T
+    assert rel(X.cpu().numpy().reshape(3, -1), ref) < 1e-10
+    # conjugate-transpose solve: A^{-dag} b = conj(A^{-1} conj b)
+    Xc, _ = rcp.solve(fac, torch.from_numpy(B[:1].reshape(1, p.nx, p.ny)).cuda(),
+                      conj_transpose=True)
+    refc = np.conj(s.solve(np.conj(B[0])))
+    assert rel(Xc.cpu().numpy().ravel(), refc) < 1e-10
+
+
+def test_solve_multi_rhs_gemm_path(rcp):
+    import torch
+    p = PROBLEMS["conc_cone"]
+    fac, _ = gpu_factors(rcp, p)
+    s = oracle_setup(p)
+    R = 70                       # several 64-row tiles with a ragged tail
+    B = W.complex_normal((R, p.nx * p.ny), seed=12)
+    X, _ = rcp.solve(fac, torch.from_numpy(B.reshape(R, p.nx, p.ny)).cuda())
+    ref = s.solve(B.T).T
+    assert rel(X.cpu().numpy().reshape(R, -1), ref) < 1e-10
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_reciprocal_average_fp64(rcp, name):
+    p = PROBLEMS[name]
+    fac, _ = gpu_factors(rcp, p)
+    F, v, z = rcp.reciprocal_average(fac, p, want_v=True, want_z=True)
+    s = oracle_setup(p)
+    z_ref = ora.reciprocal_field(s)
+    F_ref = ora.reciprocal(s)
+    assert rel(z.cpu().numpy().ravel(), z_ref) < 1e-10
+    assert rel(v.cpu().numpy(), ora.line_field(s, z_ref)) < 1e-10
+    assert abs(F.item() - F_ref) / abs(F_ref) < 1e-10
+
+
+@pytest.mark.parametrize("name", ["conc_cone", "coll_annulus"])
+def test_brute_force_fp64(rcp, name):
+    p = PROBLEMS[name]
+    fac, _ = gpu_factors(rcp, p)
+    s = oracle_setup(p)
+    n = 24
+    F, pa = rcp.brute_force_average(fac, n, p, rhs_chunk=10, per_angle=True)
+    th, wt = light.gauss_legendre(p, n)
+    pa_ref = ora.per_angle_fom(s, th)
+    assert rel(pa.cpu().numpy(), pa_ref) < 1e-10
+    F_ref = float(np.sum(wt * light.alpha(p, th) * pa_ref))
+    assert abs(F.item() - F_ref) / F_ref < 1e-10
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_adjoint_fp64(rcp, name):
+    p = PROBLEMS[name]
+    fac, _ = gpu_factors(rcp, p)
+    F, g = rcp.adjoint_grad(fac, p)
+    ref = ora.adjoint(oracle_setup(p))
+    assert abs(F.item() - ref.F) / abs(ref.F) < 1e-10
+    assert rel(g.cpu().numpy(), ref.grad_eps) < 1e-9
+    gw = rcp.width_grad(p, g)
+    assert rel(gw.cpu().numpy(), ref.grad_widths) < 1e-9
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_refined_fp32_vs_fp64(rcp, name):
+    p = PROBLEMS[name]
+    f64, _ = gpu_factors(rcp, p)
+    f32, _ = gpu_factors(rcp, p, rcp.RCP_FP32_REFINED)
+    F64, z64 = rcp.reciprocal_average(f64, p, want_z=True)
+    F32, z32 = rcp.reciprocal_average(f32, p, want_z=True)
+    iters, res = f32.last_solve_stats()
+    assert iters >= 1
+    assert rel(z32.cpu().numpy(), z64.cpu().numpy()) < 1e-8
+    assert abs(F32.item() - F64.item()) / F64.item() < 1e-6
+    Fa, ga = rcp.adjoint_grad(f32, p)
+    Fb, gb = rcp.adjoint_grad(f64, p)
+    assert rel(ga.cpu().numpy(), gb.cpu().numpy()) < 1e-5
