@@ -1,0 +1,268 @@
+"""Benchmark of the reciprocal incoherent-light average on one MI355X.
+
+One step = one inverse-design evaluation of a fresh seeded geometry: pillar
+widths -> permittivity map -> FDFD assembly -> twisted block factorisation ->
+reciprocal solve -> Toeplitz/FFT form F = v^dag W v -> adjoint solve ->
+dF/deps -> dF/dwidths, all in librecip's HIP kernels, inputs already on the
+device.  value = evaluations per second.
+
+Beside it, on the factors of the last step: the reciprocal average with cached
+factors, the 1000-node Gauss-Legendre brute force it replaces (the same
+solver over 1000 planewave right-hand sides), the FP32-factor + FP64-refinement
+variant, the factorisation rate (LU TF/s), the live roofline of the dominant
+kernel (HIP events on the launching stream), and the FP64 CPU oracle timed on
+a bounded sample of the same workload.
+
+Prints exactly one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "avg-intensity evals/s reciprocal vs 1000-angle brute force; LU TF/s; p99 ms"
+FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
+FP32_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    import workloads as W
+    return {"config1": W.config1, "config2": W.config2, "config3": W.config3,
+            "config4_large": W.config4_large}[name]()
+
+
+DESCR = {
+    "config1": "concentrator 10x8 wavelengths (240x200 cells), 10 seeded pillars, cone +-10 deg",
+    "config2": "concentrator 100 wavelengths wide, focal distance 50 (2040x1080 cells), "
+               "100 seeded pillars, cone +-20 deg",
+    "config3": "collimator 200x20 wavelengths (4040x440 cells), 200 seeded pillars, "
+               "annulus 10-30 deg and mirror",
+    "config4_large": "concentrator 100x20 wavelengths (2040x440 cells), 100 seeded pillars, "
+                     "cone +-10 deg",
+}
+
+
+def nominal_lu_flops(p):
+    """Nominal block-elimination count: a dense complex inverse per block, 8 n^3 flops."""
+    return 8.0 * p.ny ** 3 * p.nx
+
+
+def cpu_baseline(p_full, width_wl=10):
+    """FP64 oracle (SuperLU + direct Toeplitz sum + adjoint) on a width slice, scaled by width."""
+    from dataclasses import replace
+
+    import workloads as W
+    from oracle import average as ora
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:   # pragma: no cover
+        threadpool_limits = None
+    wl_full = (p_full.nx - 2 * p_full.npml) * p_full.h
+    height = int(round((p_full.ny - 2 * p_full.npml) * p_full.h))
+    fh = (p_full.focus[1] - (p_full.pillar_row0 + p_full.pillar_rows)) * p_full.h
+    ps = W.metasurface("cpu_sample", width_wl, height, 7001, focus_height=fh,
+                       c_deg=math.degrees(p_full.c) if p_full.light == W.CONE else 10.0,
+                       objective=p_full.objective, light=p_full.light,
+                       th1_deg=math.degrees(p_full.th1), th2_deg=math.degrees(p_full.th2))
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    t0 = time.perf_counter()
+    s = ora.setup(ps)
+    g = ora.adjoint(s)
+    t = time.perf_counter() - t0
+    if ctx is not None:
+        ctx.unregister() if hasattr(ctx, "unregister") else None
+    scale = ps.nx / p_full.nx
+    return {"value": scale / t, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle factor + reciprocal + adjoint on a {width_wl}-wavelength-wide "
+                      f"slice ({ps.nx}x{ps.ny} cells) of the same depth, {t:.1f} s, "
+                      f"scaled by width x{scale:.4f} (SuperLU, 1 thread)",
+            "sample_seconds": t, "sample_F": g.F}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="config2", choices=sorted(DESCR))
+    ap.add_argument("--bf-angles", type=int, default=1000)
+    ap.add_argument("--bf-chunk", type=int, default=500)
+    ap.add_argument("--timing-every", type=int, default=4)
+    ap.add_argument("--no-extras", action="store_true", help="time the step only")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU; the reciprocal solve of one "
+                                   "geometry is not sharded (N must be 1)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2207_10701_amd as rcp
+    import workloads as W
+
+    p = workload(args.config)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    log(f"bench: {p.name} {p.nx}x{p.ny}, steps={args.steps} warmup={args.warmup}")
+
+    # inputs resident in HBM before timing: one seeded geometry per step
+    nsteps = args.warmup + args.steps
+    widths = [torch.tensor(W.seeded_widths(len(p.pillar_centers), 1002 + 97 * k), dtype=torch.float64,
+                           device=dev) for k in range(nsteps)]
+    buf = torch.empty(rcp.factor_bytes(p, rcp.RCP_FP64), dtype=torch.uint8, device=dev)
+
+    def step(k):
+        eps = rcp.eps_from_widths(p, widths[k], device=dev)
+        fac = rcp.Factors(p, eps, rcp.RCP_FP64, buffer=buf)
+        F, g = rcp.adjoint_grad(fac, p)
+        gw = rcp.width_grad(p, g, widths[k])
+        return fac, F, gw
+
+    for k in range(args.warmup):
+        fac, F, gw = step(k)
+        torch.cuda.synchronize()
+        log(f"warmup {k}: F={F.item():.6e}")
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    rcp.kernel_timing_start(args.timing_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Fs = []
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        fac, F, gw = step(args.warmup + k)
+        ev[k][1].record(stream)
+        Fs.append(F)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kstats = rcp.kernel_timing_stop()
+    lat = sorted(a.elapsed_time(b) for a, b in ev)
+    wall = t1 - t0
+    ms_per_step = 1e3 * wall / args.steps
+    log(f"timed: {ms_per_step:.1f} ms/step, F={[round(f.item(), 8) for f in Fs]}")
+    p50 = float(np.percentile(lat, 50))
+    p99 = float(np.percentile(lat, 99))
+
+    upd = kstats["gj_update"]
+    achieved = upd["work"] / (upd["ms"] * 1e-3) / 1e12 if upd["ms"] > 0 else 0.0
+    roofline = {"bound": "mfma", "kernel": "k_gj_update<double>", "achieved": round(achieved, 3),
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "avg_launch_us": round(1e3 * upd["ms"] / max(upd["samples"], 1), 3),
+                "flops_per_launch": upd["work"] / max(upd["samples"], 1)}
+    kernels = {}
+    for name, st in kstats.items():
+        if st["samples"]:
+            per = st["ms"] / st["samples"]
+            rate = st["work"] / (st["ms"] * 1e-3) if st["ms"] > 0 else 0.0
+            kernels[name] = {"launches": st["launches"], "avg_us": round(1e3 * per, 3),
+                             "rate": round(rate / (1e9 if "gemv" in name or name == "schur" else 1e12), 3),
+                             "rate_unit": "GB/s" if ("gemv" in name or name == "schur") else "TFLOP/s"}
+
+    out = {"metric": METRIC, "value": round(args.steps / wall, 5), "unit": "evals/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{p.name}: {DESCR[p.name]}", "grid": [p.nx, p.ny],
+                      "step": "eps map + assemble + factor + reciprocal F + adjoint dF/dwidths",
+                      "precision": "complex FP64"},
+           "p50_ms": round(p50, 3), "p99_ms": round(p99, 3),
+           "F": Fs[-1].item(), "roofline": roofline, "kernels": kernels}
+
+    if not args.no_extras:
+        # factorisation alone
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        eps = rcp.eps_from_widths(p, widths[-1], device=dev)
+        a.record(stream)
+        fac = rcp.Factors(p, eps, rcp.RCP_FP64, buffer=buf)
+        b.record(stream)
+        torch.cuda.synchronize()
+        t_fac = a.elapsed_time(b) * 1e-3
+        out["lu_seconds"] = round(t_fac, 5)
+        out["lu_tflops_nominal"] = round(nominal_lu_flops(p) / t_fac / 1e12, 3)
+        # reciprocal average on cached factors
+        reps = 10
+        Fr = rcp.reciprocal_average(fac, p)
+        torch.cuda.synchronize()
+        a.record(stream)
+        for _ in range(reps):
+            Fr = rcp.reciprocal_average(fac, p, out=Fr)
+        b.record(stream)
+        torch.cuda.synchronize()
+        t_rec = a.elapsed_time(b) * 1e-3 / reps
+        out["reciprocal_cached_ms"] = round(1e3 * t_rec, 4)
+        log(f"factor {t_fac * 1e3:.1f} ms ({out['lu_tflops_nominal']} TF/s nominal), "
+            f"reciprocal cached {t_rec * 1e3:.3f} ms, F={Fr.item():.10e}")
+        # the brute force it replaces, same factors
+        if p.light in (W.CONE, W.ANNULUS) and args.bf_angles > 0:
+            chunk = min(args.bf_chunk, args.bf_angles)
+            torch.cuda.synchronize()
+            a.record(stream)
+            Fb = rcp.brute_force_average(fac, args.bf_angles, p, rhs_chunk=chunk)
+            b.record(stream)
+            torch.cuda.synchronize()
+            t_bf = a.elapsed_time(b) * 1e-3
+            rel = abs(Fb.item() - Fr.item()) / abs(Fr.item())
+            bf_flops = 16.0 * p.ny ** 2 * p.nx * args.bf_angles
+            out["brute_force"] = {
+                "angles": args.bf_angles, "rhs_chunk": chunk, "seconds": round(t_bf, 4),
+                "evals_per_s_cached": round(1.0 / t_bf, 4),
+                "evals_per_s_end_to_end": round(1.0 / (t_bf + t_fac), 4),
+                "F": Fb.item(), "rel_diff_vs_reciprocal": rel,
+                "gemm_tflops": round(bf_flops / t_bf / 1e12, 3)}
+            out["speedup"] = {"solve_count": args.bf_angles,
+                              "cached_factors": round(t_bf / t_rec, 2),
+                              "end_to_end": round((t_bf + t_fac) / (t_rec + t_fac), 3)}
+            log(f"brute force {args.bf_angles} angles: {t_bf:.3f} s, F={Fb.item():.10e}, "
+                f"rel diff {rel:.2e}")
+        # FP32 factors + FP64 refinement, error vs FP64
+        del fac
+        buf32 = torch.empty(rcp.factor_bytes(p, rcp.RCP_FP32_REFINED), dtype=torch.uint8,
+                            device=dev)
+        torch.cuda.synchronize()
+        a.record(stream)
+        f32 = rcp.Factors(p, eps, rcp.RCP_FP32_REFINED, buffer=buf32)
+        b.record(stream)
+        F32, z32 = rcp.reciprocal_average(f32, p, want_z=True)
+        torch.cuda.synchronize()
+        t_f32 = a.elapsed_time(b) * 1e-3
+        it, res = f32.last_solve_stats()
+        fac = rcp.Factors(p, eps, rcp.RCP_FP64, buffer=buf)
+        F64, z64 = rcp.reciprocal_average(fac, p, want_z=True)
+        torch.cuda.synchronize()
+        zerr = (torch.linalg.vector_norm(z32 - z64) / torch.linalg.vector_norm(z64)).item()
+        out["fp32_refined"] = {"lu_seconds": round(t_f32, 5),
+                               "lu_tflops_nominal": round(nominal_lu_flops(p) / t_f32 / 1e12, 3),
+                               "refine_steps": it, "rel_residual": res,
+                               "field_rel_err_vs_fp64": zerr,
+                               "F_rel_err_vs_fp64": abs(F32.item() - F64.item()) / abs(F64.item())}
+        log(f"fp32 refined: factor {t_f32 * 1e3:.1f} ms, {it} steps, field err {zerr:.2e}")
+        del f32, buf32
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(p)
+        log(f"cpu baseline {out['cpu_baseline']['value']:.4g} evals/s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

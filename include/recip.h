@@ -151,6 +151,14 @@ size_t rcp_factor_bytes(const rcp_grid* grid, int32_t precision);
 int rcp_factor(const rcp_grid* grid, int32_t precision, void* buf_dev, size_t buf_bytes,
                rcp_stream stream, rcp_factors** out);
 
+/* a2 + a3 for `count` (1..4) geometries of identical grid (only eps differs),
+ * factored in the same kernel launches (their elimination chains run side by
+ * side).  grids[g], bufs[g] (each buf_bytes >= rcp_factor_bytes, 256-byte
+ * aligned, non-overlapping) and out[g] as for rcp_factor.  On failure no
+ * handle is returned and the message names the geometry. */
+int rcp_factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, void* const* bufs,
+                     size_t buf_bytes, rcp_stream stream, rcp_factors** out);
+
 /* Solve A X = B for nrhs right-hand sides (or A^dag X = B when
  * conj_transpose != 0, using A = A^T).  B_dev, X_dev: nrhs x nx x ny
  * complex128 (row r is one grid field); B_dev and X_dev must not overlap
@@ -206,6 +214,25 @@ const char* rcp_last_error(void);
 /* Iteration count and final relative residual of the last refined solve made
  * by rcp_reciprocal_average / rcp_adjoint_grad on these factors. */
 int rcp_last_solve_stats(const rcp_factors* f, rcp_solve_stats* stats);
+
+/* Launch timing for benchmarks (not thread-safe across concurrent timing
+ * sessions).  rcp_timing_start(k) brackets every k-th launch of each kernel
+ * class with HIP events on the launching stream (k = 0 turns timing off);
+ * rcp_timing_stop waits for those events and fills stats[c] for the classes
+ *   0 Gauss-Jordan first panel of a block            work = algorithmic flops
+ *   1 Gauss-Jordan update k fused with panel k+1     work = algorithmic flops
+ *   2 Schur-complement formation   work = bytes of factor blocks read + written
+ *   3 single-RHS block product     work = bytes of factor blocks read
+ *   4 multi-RHS block GEMM         work = algorithmic flops (8 per complex MAC)
+ *   5 Gauss-Jordan last update of a block            work = algorithmic flops
+ * launches counts every launch, samples / ms / work only the timed ones. */
+#define RCP_NKCLASS 6
+typedef struct {
+  int64_t launches, samples;
+  double ms, work;
+} rcp_kernel_stat;
+int rcp_timing_start(int32_t sample_every);
+int rcp_timing_stop(rcp_kernel_stat* stats, int32_t n);
 
 /* Introspection for tests and benchmarks. */
 int rcp_factors_info(const rcp_factors* f, int32_t* nx, int32_t* ny, int32_t* precision,

@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import (RCP_ANNULUS, RCP_COLLIMATOR, RCP_CONCENTRATOR, RCP_CONE, RCP_FP32_REFINED,
                    RCP_FP64, RCP_SYMBOL_TABLE, RecipError, check, lib)
 
-__all__ = ["Factors", "factor_bytes", "eps_from_widths", "reciprocal_average",
+__all__ = ["Factors", "factor_batch", "factor_bytes", "eps_from_widths", "reciprocal_average",
            "brute_force_average", "adjoint_grad", "width_grad", "solve", "IncoherentFOM",
            "RCP_FP64", "RCP_FP32_REFINED", "RecipError"]
 
@@ -105,6 +105,16 @@ class Factors:
                              _stream(stream), C.byref(h)))
         self.handle = h
 
+    @classmethod
+    def _wrap(cls, p: Problem, precision: int, buffer: torch.Tensor, handle: C.c_void_p):
+        obj = cls.__new__(cls)
+        obj.problem = p
+        obj.precision = precision
+        obj.nbytes = factor_bytes(p, precision)
+        obj.buf = buffer
+        obj.handle = handle
+        return obj
+
     def release(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             lib.rcp_factors_release(self.handle)
@@ -120,6 +130,23 @@ class Factors:
         st = _lib.SolveStats()
         check(lib.rcp_last_solve_stats(self.handle, C.byref(st)))
         return int(st.iters), float(st.rel_residual)
+
+
+def factor_batch(problems, eps_list, precision: int = RCP_FP64, buffers=None, stream=None):
+    """Factor 1-4 same-grid geometries in the same kernel launches (chains side by side)."""
+    B = len(problems)
+    if B < 1 or B > 4 or len(eps_list) != B:
+        raise ValueError("factor_batch takes 1 to 4 problems with one eps map each")
+    nbytes = factor_bytes(problems[0], precision)
+    dev = eps_list[0].device
+    if buffers is None:
+        buffers = [torch.empty(nbytes, dtype=torch.uint8, device=dev) for _ in range(B)]
+    eps_c = [e.to(dtype=torch.float64).contiguous() for e in eps_list]
+    grids = (_lib.Grid * B)(*[grid_struct(p, e) for p, e in zip(problems, eps_c)])
+    bufs = (C.c_void_p * B)(*[b.data_ptr() for b in buffers])
+    outs = (C.c_void_p * B)()
+    check(lib.rcp_factor_batch(B, grids, precision, bufs, nbytes, _stream(stream), outs))
+    return [Factors._wrap(p, precision, b, C.c_void_p(h)) for p, b, h in zip(problems, buffers, outs)]
 
 
 def reciprocal_average(fac: Factors, p: Optional[Problem] = None, want_v: bool = False,
@@ -224,3 +251,19 @@ class IncoherentFOM(torch.autograd.Function):
     def backward(ctx, grad_out):
         (gw,) = ctx.saved_tensors
         return (grad_out * gw if gw is not None else None), None, None
+
+
+def kernel_timing_start(sample_every: int = 1) -> None:
+    """Bracket every sample_every-th launch of each kernel class with HIP events."""
+    check(lib.rcp_timing_start(int(sample_every)))
+
+
+def kernel_timing_stop() -> dict:
+    """Per kernel class: launches, timed samples, their total ms and algorithmic work."""
+    arr = (_lib.KernelStat * _lib.NKCLASS)()
+    check(lib.rcp_timing_stop(arr, _lib.NKCLASS))
+    out = {}
+    for name, st in zip(_lib.KCLASS_NAMES, arr):
+        out[name] = dict(launches=int(st.launches), samples=int(st.samples), ms=float(st.ms),
+                         work=float(st.work))
+    return out

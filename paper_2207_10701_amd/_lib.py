@@ -48,6 +48,15 @@ class SolveStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("rel_residual", C.c_double)]
 
 
+class KernelStat(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("samples", C.c_int64), ("ms", C.c_double),
+                ("work", C.c_double)]
+
+
+NKCLASS = 6
+KCLASS_NAMES = ["gj_panel", "gj_update", "schur", "block_gemv", "block_gemm", "gj_last"]
+
+
 class RecipError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
@@ -65,6 +74,7 @@ def _load():
         "rcp_eps_from_widths": (C.c_int, [P(Grid), P(Pillars), vp, vp]),
         "rcp_factor_bytes": (sz, [P(Grid), i32]),
         "rcp_factor": (C.c_int, [P(Grid), i32, vp, sz, vp, P(vp)]),
+        "rcp_factor_batch": (C.c_int, [i32, P(Grid), i32, P(vp), sz, vp, P(vp)]),
         "rcp_solve_multi_rhs": (C.c_int, [vp, i32, vp, vp, i32, f64, i32, vp, P(SolveStats)]),
         "rcp_reciprocal_average": (C.c_int, [vp, P(Objective), P(Light), vp, vp, vp, vp]),
         "rcp_brute_force_work_bytes": (sz, [vp, i32, i32]),
@@ -76,6 +86,8 @@ def _load():
         "rcp_last_error": (C.c_char_p, []),
         "rcp_last_solve_stats": (C.c_int, [vp, P(SolveStats)]),
         "rcp_factors_info": (C.c_int, [vp, P(i32), P(i32), P(i32), P(i32), P(i32)]),
+        "rcp_timing_start": (C.c_int, [i32]),
+        "rcp_timing_stop": (C.c_int, [P(KernelStat), i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

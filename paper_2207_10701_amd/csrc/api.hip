@@ -1,8 +1,10 @@
 // C ABI of librecip (declared in include/recip.h): argument checks, buffer
 // layout, and the host-side order of the steps of each call.
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "rcp_internal.h"
 
@@ -43,9 +45,9 @@ Layout compute_layout(int nx, int ny, int precision) {
   L.off_dco = take(N * 16);
   L.off_eco = take(N * 16);
   L.off_cco = take(N * 16);
-  L.off_L = take(2 * size_t(np) * TB * eb);
-  L.off_Q = take(2 * size_t(np) * TB * eb);
-  L.off_P = take(2 * size_t(TB) * TB * 16);
+  L.off_L = take(4 * size_t(np) * TB * eb);
+  L.off_Q = take(4 * size_t(np) * TB * eb);
+  L.off_P = take(4 * size_t(TB) * TB * 16);
   L.off_health = take(size_t(nx) * nt * 8);
   L.off_vec = take(NVEC * N * 16);
   L.off_red = take((2 + 2 * ((N + 255) / 256)) * 8);
@@ -54,6 +56,52 @@ Layout compute_layout(int nx, int ny, int precision) {
   L.off_fft = take(4 * cap * 16);
   L.total = o;
   return L;
+}
+
+// ---- launch timing ---------------------------------------------------------
+namespace {
+struct TimerSample {
+  int cls;
+  hipEvent_t e0, e1;
+  double work;
+};
+struct TimerState {
+  std::mutex mu;
+  int every = 0;
+  long long launches[K_NCLASS] = {};
+  std::vector<TimerSample*> pending;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+TimerState g_timer;
+}  // namespace
+
+void ktimer_begin(int cls, hipStream_t s, double work, void** token) {
+  *token = nullptr;
+  if (g_timer.every <= 0) return;
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  long long n = g_timer.launches[cls]++;
+  if (n % g_timer.every) return;
+  TimerSample* ts = new TimerSample{cls, g_timer.get(), g_timer.get(), work};
+  if (!ts->e0 || !ts->e1 || hipEventRecord(ts->e0, s) != hipSuccess) {
+    delete ts;
+    return;
+  }
+  g_timer.pending.push_back(ts);
+  *token = ts;
+}
+
+void ktimer_end(void* token, hipStream_t s) {
+  (void)hipEventRecord(static_cast<TimerSample*>(token)->e1, s);
 }
 
 static size_t fft_capacity(int nx) {
@@ -139,6 +187,48 @@ extern "C" {
 
 const char* rcp_last_error(void) { return g_err.c_str(); }
 
+int rcp_timing_start(int32_t sample_every) {
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  for (TimerSample* t : g_timer.pending) {
+    g_timer.pool.push_back(t->e0);
+    g_timer.pool.push_back(t->e1);
+    delete t;
+  }
+  g_timer.pending.clear();
+  for (auto& c : g_timer.launches) c = 0;
+  g_timer.every = sample_every > 0 ? sample_every : 0;
+  return RCP_OK;
+}
+
+int rcp_timing_stop(rcp_kernel_stat* out, int32_t n) {
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  g_timer.every = 0;
+  for (int c = 0; c < n && c < K_NCLASS; ++c) {
+    out[c].launches = g_timer.launches[c];
+    out[c].samples = 0;
+    out[c].ms = 0.0;
+    out[c].work = 0.0;
+  }
+  int rc = RCP_OK;
+  for (TimerSample* t : g_timer.pending) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(t->e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t->e0, t->e1);
+    if (e != hipSuccess) {
+      rc = hip_check(e, "rcp_timing_stop");
+    } else if (t->cls < n) {
+      out[t->cls].samples += 1;
+      out[t->cls].ms += ms;
+      out[t->cls].work += t->work;
+    }
+    g_timer.pool.push_back(t->e0);
+    g_timer.pool.push_back(t->e1);
+    delete t;
+  }
+  g_timer.pending.clear();
+  return rc;
+}
+
 int rcp_eps_from_widths(const rcp_grid* grid, const rcp_pillars* pillars, double* eps_out_dev,
                         rcp_stream stream) {
   if (!grid || grid->nx < 1 || grid->ny < 1) return fail(RCP_EINVAL, "bad grid");
@@ -154,71 +244,105 @@ size_t rcp_factor_bytes(const rcp_grid* grid, int32_t precision) {
   return compute_layout(grid->nx, grid->ny, precision).total;
 }
 
+int rcp_factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, void* const* bufs,
+                     size_t buf_bytes, rcp_stream stream, rcp_factors** out) {
+  if (!out || !grids || !bufs) return fail(RCP_EINVAL, "NULL argument");
+  if (count < 1 || count > 4) return fail(RCP_EINVAL, "count must be 1 to 4");
+  for (int g = 0; g < count; ++g) out[g] = nullptr;
+  if (precision != RCP_FP64 && precision != RCP_FP32_REFINED)
+    return fail(RCP_EINVAL, "unknown precision");
+  for (int g = 0; g < count; ++g) {
+    int rc = check_grid(&grids[g]);
+    if (rc) return rc;
+    if (!grids[g].eps_dev) return fail(RCP_EINVAL, "eps_dev is NULL");
+    const rcp_grid& a = grids[0];
+    const rcp_grid& c = grids[g];
+    if (c.nx != a.nx || c.ny != a.ny || c.npml != a.npml || c.h != a.h || c.k0 != a.k0 ||
+        c.pml_R != a.pml_R || c.pml_m != a.pml_m)
+      return fail(RCP_EINVAL, "a batch needs identical grids (only eps may differ)");
+  }
+  Layout L = compute_layout(grids[0].nx, grids[0].ny, precision);
+  if (buf_bytes < L.total)
+    return fail(RCP_ENOMEM, "factor buffer holds " + std::to_string(buf_bytes) + " bytes, needs " +
+                                std::to_string(L.total));
+  for (int g = 0; g < count; ++g) {
+    if (!bufs[g]) return fail(RCP_ENOMEM, "factor buffer is NULL");
+    if (reinterpret_cast<uintptr_t>(bufs[g]) % 256 != 0)
+      return fail(RCP_EINVAL, "factor buffer must be 256-byte aligned");
+    for (int h2 = 0; h2 < g; ++h2) {
+      const char* x0 = static_cast<const char*>(bufs[g]);
+      const char* y0 = static_cast<const char*>(bufs[h2]);
+      if (x0 < y0 + L.total && y0 < x0 + L.total) return fail(RCP_EINVAL, "factor buffers overlap");
+    }
+  }
+  rcp_factors* fs[4] = {nullptr, nullptr, nullptr, nullptr};
+  int rc = RCP_OK;
+  for (int g = 0; g < count && !rc; ++g) {
+    const rcp_grid* grid = &grids[g];
+    rcp_factors* f = new (std::nothrow) rcp_factors();
+    if (!f) {
+      rc = fail(RCP_ENOMEM, "host allocation failed");
+      break;
+    }
+    fs[g] = f;
+    f->nx = grid->nx;
+    f->ny = grid->ny;
+    f->npml = grid->npml;
+    f->h = grid->h;
+    f->k0 = grid->k0;
+    f->pml_R = grid->pml_R;
+    f->pml_m = grid->pml_m;
+    f->precision = precision;
+    f->np = ceil_div(grid->ny, TB) * TB;
+    f->nt = f->np / TB;
+    f->tiles = size_t(f->nt) * (f->nt + 1) / 2;
+    f->block_elems = f->tiles * TB * TB;
+    f->elem_bytes = precision == RCP_FP64 ? 16 : 8;
+    f->m = grid->nx / 2;
+    f->fft_cap = fft_capacity(grid->nx);
+    f->lay = L;
+    char* b = static_cast<char*>(bufs[g]);
+    f->base = b;
+    f->X = b + L.off_X;
+    f->eps = reinterpret_cast<double*>(b + L.off_eps);
+    f->sxc = reinterpret_cast<double2*>(b + L.off_sxc);
+    f->sxf = reinterpret_cast<double2*>(b + L.off_sxf);
+    f->syc = reinterpret_cast<double2*>(b + L.off_syc);
+    f->syf = reinterpret_cast<double2*>(b + L.off_syf);
+    f->dco = reinterpret_cast<double2*>(b + L.off_dco);
+    f->eco = reinterpret_cast<double2*>(b + L.off_eco);
+    f->cco = reinterpret_cast<double2*>(b + L.off_cco);
+    const size_t panel = size_t(f->np) * TB * f->elem_bytes;
+    for (int c = 0; c < 4; ++c) {
+      f->wsL[c] = b + L.off_L + c * panel;
+      f->wsQ[c] = b + L.off_Q + c * panel;
+      f->wsP[c] = reinterpret_cast<double2*>(b + L.off_P) + c * TB * TB;
+    }
+    f->health = reinterpret_cast<double*>(b + L.off_health);
+    const size_t N = size_t(f->nx) * f->ny;
+    for (int v = 0; v < NVEC; ++v) f->vec[v] = reinterpret_cast<double2*>(b + L.off_vec) + v * N;
+    f->red = reinterpret_cast<double*>(b + L.off_red);
+    for (int q = 0; q < 4; ++q)
+      f->fft[q] = reinterpret_cast<double2*>(b + L.off_fft) + q * f->fft_cap;
+    f->last_iters = 0;
+    f->last_residual = 0.0;
+    rc = launch_assemble(f, grid->eps_dev, stream);
+  }
+  if (!rc) rc = factor_blocks(fs, count, stream);
+  if (rc) {
+    for (int g = 0; g < count; ++g) delete fs[g];
+    return rc;
+  }
+  for (int g = 0; g < count; ++g) out[g] = fs[g];
+  return RCP_OK;
+}
+
 int rcp_factor(const rcp_grid* grid, int32_t precision, void* buf_dev, size_t buf_bytes,
                rcp_stream stream, rcp_factors** out) {
   if (!out) return fail(RCP_EINVAL, "out is NULL");
-  *out = nullptr;
-  int rc = check_grid(grid);
-  if (rc) return rc;
-  if (!grid->eps_dev) return fail(RCP_EINVAL, "eps_dev is NULL");
-  if (precision != RCP_FP64 && precision != RCP_FP32_REFINED)
-    return fail(RCP_EINVAL, "unknown precision");
-  Layout L = compute_layout(grid->nx, grid->ny, precision);
-  if (!buf_dev || buf_bytes < L.total)
-    return fail(RCP_ENOMEM, "factor buffer holds " + std::to_string(buf_bytes) + " bytes, needs " +
-                                std::to_string(L.total));
-  if (reinterpret_cast<uintptr_t>(buf_dev) % 256 != 0)
-    return fail(RCP_EINVAL, "factor buffer must be 256-byte aligned");
-  rcp_factors* f = new (std::nothrow) rcp_factors();
-  if (!f) return fail(RCP_ENOMEM, "host allocation failed");
-  f->nx = grid->nx;
-  f->ny = grid->ny;
-  f->npml = grid->npml;
-  f->h = grid->h;
-  f->k0 = grid->k0;
-  f->pml_R = grid->pml_R;
-  f->pml_m = grid->pml_m;
-  f->precision = precision;
-  f->np = ceil_div(grid->ny, TB) * TB;
-  f->nt = f->np / TB;
-  f->tiles = size_t(f->nt) * (f->nt + 1) / 2;
-  f->block_elems = f->tiles * TB * TB;
-  f->elem_bytes = precision == RCP_FP64 ? 16 : 8;
-  f->m = grid->nx / 2;
-  f->fft_cap = fft_capacity(grid->nx);
-  f->lay = L;
-  char* b = static_cast<char*>(buf_dev);
-  f->base = b;
-  f->X = b + L.off_X;
-  f->eps = reinterpret_cast<double*>(b + L.off_eps);
-  f->sxc = reinterpret_cast<double2*>(b + L.off_sxc);
-  f->sxf = reinterpret_cast<double2*>(b + L.off_sxf);
-  f->syc = reinterpret_cast<double2*>(b + L.off_syc);
-  f->syf = reinterpret_cast<double2*>(b + L.off_syf);
-  f->dco = reinterpret_cast<double2*>(b + L.off_dco);
-  f->eco = reinterpret_cast<double2*>(b + L.off_eco);
-  f->cco = reinterpret_cast<double2*>(b + L.off_cco);
-  const size_t panel = size_t(f->np) * TB * f->elem_bytes;
-  for (int c = 0; c < 2; ++c) {
-    f->wsL[c] = b + L.off_L + c * panel;
-    f->wsQ[c] = b + L.off_Q + c * panel;
-    f->wsP[c] = reinterpret_cast<double2*>(b + L.off_P) + c * TB * TB;
-  }
-  f->health = reinterpret_cast<double*>(b + L.off_health);
-  const size_t N = size_t(f->nx) * f->ny;
-  for (int v = 0; v < NVEC; ++v) f->vec[v] = reinterpret_cast<double2*>(b + L.off_vec) + v * N;
-  f->red = reinterpret_cast<double*>(b + L.off_red);
-  for (int q = 0; q < 4; ++q) f->fft[q] = reinterpret_cast<double2*>(b + L.off_fft) + q * f->fft_cap;
-  f->last_iters = 0;
-  f->last_residual = 0.0;
-  rc = launch_assemble(f, grid->eps_dev, stream);
-  if (!rc) rc = factor_blocks(f, stream);
-  if (rc) {
-    delete f;
-    return rc;
-  }
-  *out = f;
-  return RCP_OK;
+  if (!grid) return fail(RCP_EINVAL, "grid is NULL");
+  void* bufs[1] = {buf_dev};
+  return rcp_factor_batch(1, grid, precision, bufs, buf_bytes, stream, out);
 }
 
 void rcp_factors_release(rcp_factors* f) { delete f; }

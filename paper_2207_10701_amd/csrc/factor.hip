@@ -13,8 +13,17 @@
 //   P = S_KK^{-1},  L = S(:, K),  Q = L P,
 //   S_IJ <- S_IJ - Q_I L_J^T (I, J != K),  S_IK <- Q_I,  S_KK <- -P,
 // and after all panels the tiles hold -S^{-1}; the last panel negates.
-// The nb x nb pivot blocks are inverted without pivoting (in FP64 for both
-// storage precisions) and the smallest pivot modulus of every panel is
+//
+// Look-ahead: launch k applies update k to every tile outside tile column
+// k+1, while a few workgroups compute the update-k values of column k+1
+// directly in the layout the next panel needs, invert the next pivot block
+// and form Q for panel k+1 into the other half of double-buffered panel
+// buffers.  Column k+1 values never go back to the factor tiles: update k+1
+// overwrites that column anyway.  One launch per panel, no dependencies
+// between the workgroups of a launch.
+//
+// The TB x TB pivot blocks are inverted without pivoting, in FP64 for both
+// storage precisions, and the smallest pivot modulus of every panel is
 // recorded for the health check.
 #include <cmath>
 #include <vector>
@@ -25,101 +34,252 @@ namespace {
 using namespace rcp;
 
 struct GJJob {
-  int kind;      // 0: panel (P, L, Q), 1: trailing update
   int k;         // panel index
-  int last;      // update: final panel, negate
-  int wgs;       // workgroups of this job
+  int last;      // update: final panel, negate the result
+  int wgs;       // workgroups of this job (update part + look-ahead part)
+  int wgs_upd;   // of which the trailing-update part
   void* X;       // packed tiles of the block
-  void* L;       // np x TB panel copy
-  void* Q;       // np x TB  L P
-  double2* P;    // TB x TB pivot-block inverse
-  double* health;
+  void* L;       // panel k: TB-row tiles of L = S(:, k)
+  void* Q;       // panel k: Q = L P
+  double2* P;    // panel k: TB x TB pivot-block inverse
+  void* Ln;      // panel k+1 buffers (look-ahead output)
+  void* Qn;
+  double2* Pn;
+  double* health;   // min |pivot| slot of the panel this job inverts
 };
+constexpr int MAXJ = 8;   // chains per launch: two per geometry, up to four geometries
 struct GJJobs {
-  GJJob j[4];
+  GJJob j[MAXJ];
   int n;
 };
 
+#define RCP_SEL8(js, q, fld)                                                              \
+  ((q) < 4 ? ((q) < 2 ? ((q) == 0 ? js.j[0].fld : js.j[1].fld)                           \
+                      : ((q) == 2 ? js.j[2].fld : js.j[3].fld))                           \
+           : ((q) < 6 ? ((q) == 4 ? js.j[4].fld : js.j[5].fld)                            \
+                      : ((q) == 6 ? js.j[6].fld : js.j[7].fld)))
+
+// Job of this workgroup: every job of a launch has the same workgroup count;
+// fields are selected one at a time so that the table stays in kernel-argument
+// registers.
 __device__ __forceinline__ GJJob pick(const GJJobs& js, int* wg) {
-  GJJob jb = js.j[0];
-  int w = *wg;
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    if (q + 1 < js.n && w >= jb.wgs) {
-      w -= jb.wgs;
-      jb = js.j[q + 1];
-    }
-  }
-  *wg = w;
+  const int per = js.j[0].wgs;
+  const int q = *wg / per;
+  *wg -= q * per;
+#define RCP_SEL(fld) RCP_SEL8(js, q, fld)
+  GJJob jb;
+  jb.k = RCP_SEL(k);
+  jb.last = RCP_SEL(last);
+  jb.wgs = RCP_SEL(wgs);
+  jb.wgs_upd = RCP_SEL(wgs_upd);
+  jb.X = RCP_SEL(X);
+  jb.L = RCP_SEL(L);
+  jb.Q = RCP_SEL(Q);
+  jb.P = RCP_SEL(P);
+  jb.Ln = RCP_SEL(Ln);
+  jb.Qn = RCP_SEL(Qn);
+  jb.Pn = RCP_SEL(Pn);
+  jb.health = RCP_SEL(health);
+#undef RCP_SEL
   return jb;
 }
 
-// Panel step: every workgroup inverts the pivot block (FP64, in LDS), then each
-// wave forms one row tile I of L (copied) and Q = L P.
-template <typename T>
-__device__ void panel_work(const GJJob& jb, int wg, int nt, double2 (*Ps)[TB + 1]) {
-  using T2 = typename cplx<T>::t;
-  using V4 = typename v4of<T>::t;
-  T2* X = static_cast<T2*>(jb.X);
-  const int K = jb.k;
-  const int tid = threadIdx.x;
-  const T2* D = X + tile_index(K, K) * TB * TB;
-  for (int e = tid; e < TB * TB; e += 256) Ps[e / TB][e % TB] = to_c128(D[e]);
-  __syncthreads();
+// 1 / d for d > 0: hardware reciprocal estimate refined by two steps of
+// Newton's method r <- r (2 - d r).
+__device__ __forceinline__ double recip_pos(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return r;
+}
 
-  // Gauss-Jordan inversion without pivoting; thread owns row r, columns c0..c0+3.
+// k index carried by MFMA operand slot (k-step s, lane group lk) when the left
+// operand comes straight from an accumulator of the transposed block (see
+// lookahead_work): 4 s + lk for the f64 layout, 16 (s / 4) + 4 lk + s % 4 for f32.
+template <typename T> __device__ __forceinline__ int acc_k(int s, int lk);
+template <> __device__ __forceinline__ int acc_k<double>(int s, int lk) { return 4 * s + lk; }
+template <> __device__ __forceinline__ int acc_k<float>(int s, int lk) {
+  return 16 * (s >> 2) + 4 * lk + (s & 3);
+}
+
+__device__ __forceinline__ double2 cneg(double2 a) { return make_double2(-a.x, -a.y); }
+
+// Gauss-Jordan inversion of the TB x TB block in Ps (FP64), result back in Ps,
+// eliminating two columns per step with the 2 x 2 diagonal block B of rows and
+// columns p, p+1 as pivot (inverted in closed form; no row exchanges):
+//   pivot rows      R <- B^{-1} R,       their pivot columns <- B^{-1}
+//   other rows r    m_r <- m_r - F_r B^{-1} R,   their pivot columns <- -F_r B^{-1}
+// with F_r = (m_rp, m_r,p+1).  256 threads; thread owns row r, columns
+// c0..c0+3 in registers; pivot rows/columns are exchanged through
+// double-buffered LDS, one barrier per step.  Returns min |det B|^(1/2).
+__device__ double invert_pivot_block(double2 (*Ps)[TB + 1], double2 (*xr)[TB],
+                                     double2 (*xc)[TB]) {
+  const int tid = threadIdx.x;
   const int r = tid >> 3, c0 = (tid & 7) * 4;
-  double minpiv = INFINITY;
-  for (int p = 0; p < TB; ++p) {
-    double2 piv = Ps[p][p];
-    double2 ip = cinv(piv);
-    double2 fr = Ps[r][p];
-    double2 prow[4], mine[4];
+  double2 m[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      prow[c] = Ps[p][c0 + c];
-      mine[c] = Ps[r][c0 + c];
-    }
-    double a = sqrt(cabs2(piv));
-    minpiv = (a < minpiv || a != a) ? a : minpiv;
-    __syncthreads();
+  for (int c = 0; c < 4; ++c) m[c] = Ps[r][c0 + c];
+  double mindet2 = INFINITY;
+  for (int p = 0; p < TB; p += 2) {
+    const int b = (p >> 1) & 1;
     if (r == p) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) Ps[p][c0 + c] = (c0 + c == p) ? ip : cmul(prow[c], ip);
-    } else {
-      double2 fi = cmul(fr, ip);
+      for (int c = 0; c < 4; ++c) xr[2 * b][c0 + c] = m[c];
+    }
+    if (r == p + 1) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        Ps[r][c0 + c] = (c0 + c == p) ? make_double2(-fi.x, -fi.y) : csub(mine[c], cmul(fi, prow[c]));
+      for (int c = 0; c < 4; ++c) xr[2 * b + 1][c0 + c] = m[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (c0 + c == p) xc[2 * b][r] = m[c];
+      if (c0 + c == p + 1) xc[2 * b + 1][r] = m[c];
     }
     __syncthreads();
-  }
-  if (wg == 0) {
-    for (int e = tid; e < TB * TB; e += 256) jb.P[e] = Ps[e / TB][e % TB];
-    if (tid == 0) *jb.health = minpiv;
-  }
-
-  const int wave = tid >> 6, lane = tid & 63;
-  const int I = wg * 4 + wave;
-  if (I >= nt || I == K) return;
-  const int lr = lane & 15, lk = lane >> 4;
-  const T2* src = (I >= K) ? X + tile_index(I, K) * TB * TB : X + tile_index(K, I) * TB * TB;
-  const bool trans = I < K;
-  T2 af[2][8];
+    const double2 a = xr[2 * b][p], bb = xr[2 * b][p + 1], cc = xr[2 * b + 1][p],
+                  d = xr[2 * b + 1][p + 1];
+    const double2 det = csub(cmul(a, d), cmul(bb, cc));
+    const double dd = det.x * det.x + det.y * det.y;
+    mindet2 = (dd < mindet2 || dd != dd) ? dd : mindet2;
+    const double rd = recip_pos(dd);
+    const double2 idet = make_double2(det.x * rd, -det.y * rd);
+    const double2 i00 = cmul(d, idet), i01 = cneg(cmul(bb, idet)), i10 = cneg(cmul(cc, idet)),
+                  i11 = cmul(a, idet);
+    const bool r0 = (r == p), r1 = (r == p + 1);
+    const double2 f0 = xc[2 * b][r], f1 = xc[2 * b + 1][r];
+    const double2 g0 = cadd(cmul(f0, i00), cmul(f1, i10));
+    const double2 g1 = cadd(cmul(f0, i01), cmul(f1, i11));
+    const double2 b0 = r0 ? cneg(i00) : r1 ? cneg(i10) : g0;
+    const double2 b1 = r0 ? cneg(i01) : r1 ? cneg(i11) : g1;
+    const bool keep = !(r0 || r1);
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      int rr = 16 * a + lr, kk = 4 * s + lk;
-      af[a][s] = trans ? src[kk * TB + rr] : src[rr * TB + kk];
+    for (int c = 0; c < 4; ++c) {
+      const int col = c0 + c;
+      double2 v = keep ? m[c] : make_double2(0.0, 0.0);
+      v = csub(v, cmul(b0, xr[2 * b][col]));
+      v = csub(v, cmul(b1, xr[2 * b + 1][col]));
+      m[c] = (col == p) ? cneg(b0) : (col == p + 1) ? cneg(b1) : v;
     }
-  T2* Lb = static_cast<T2*>(jb.L) + size_t(I) * TB * TB;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 4; ++c) Ps[r][c0 + c] = m[c];
+  __syncthreads();
+  return sqrt(sqrt(mindet2));   // |det B|^(1/2): same scale as a scalar pivot
+}
+
+// acc (one 32 x 32 tile in MFMA accumulator layout) -= A B^T, with A and B
+// 32 x 32 row-major tiles; blocks (a, b) with a in [a0, a1), b in [b0, b1).
+template <typename T>
+__device__ __forceinline__ void tile_nt_update(typename v4of<T>::t (*cre)[2],
+                                               typename v4of<T>::t (*cim)[2],
+                                               const typename cplx<T>::t* A,
+                                               const typename cplx<T>::t* B, int lr, int lk,
+                                               int a0, int a1, int b0, int b1) {
+  using T2 = typename cplx<T>::t;
+  T2 av[2][8], bv[2][8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      if (x >= a0 && x < a1) av[x][s] = A[(16 * x + lr) * TB + 4 * s + lk];
+      if (x >= b0 && x < b1) bv[x][s] = B[(16 * x + lr) * TB + 4 * s + lk];
+    }
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      if (a < a0 || a >= a1) continue;
+      const T nare = -av[a][s].x, aim = av[a][s].y, naim = -av[a][s].y;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        if (b < b0 || b >= b1) continue;
+        cre[a][b] = mfma16(nare, bv[b][s].x, cre[a][b]);
+        cim[a][b] = mfma16(nare, bv[b][s].y, cim[a][b]);
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        if (b < b0 || b >= b1) continue;
+        cre[a][b] = mfma16(aim, bv[b][s].y, cre[a][b]);
+        cim[a][b] = mfma16(naim, bv[b][s].x, cim[a][b]);
+      }
+    }
+  }
+}
+
+// Load a stored tile into accumulators, transposed if tr (acc(i, j) = S(j, i)).
+template <typename T>
+__device__ __forceinline__ void tile_load_acc(typename v4of<T>::t (*cre)[2],
+                                              typename v4of<T>::t (*cim)[2],
+                                              const typename cplx<T>::t* S, bool tr, int lr,
+                                              int lk) {
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int s = 0; s < 8; ++s) Lb[(16 * a + lr) * TB + 4 * s + lk] = af[a][s];
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = 16 * a + mfma_row<T>(lk, q), j = 16 * b + lr;
+        typename cplx<T>::t v = tr ? S[j * TB + i] : S[i * TB + j];
+        cre[a][b][q] = v.x;
+        cim[a][b][q] = v.y;
+      }
+}
 
-  V4 cre[2][2], cim[2][2];
+template <typename T>
+__device__ __forceinline__ void tile_store_acc(typename v4of<T>::t (*cre)[2],
+                                               typename v4of<T>::t (*cim)[2],
+                                               typename cplx<T>::t* D, T sg, int lr, int lk) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        typename cplx<T>::t v;
+        v.x = cre[a][b][q] * sg;
+        v.y = cim[a][b][q] * sg;
+        D[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr] = v;
+      }
+}
+
+// Q tile = L tile * P with L given row-major in memory (panel kernel) ...
+template <typename T>
+__device__ __forceinline__ void q_from_rows(typename v4of<T>::t (*cre)[2],
+                                            typename v4of<T>::t (*cim)[2],
+                                            const typename cplx<T>::t (*af)[8],
+                                            double2 (*Ps)[TB + 1], int lr, int lk, bool acc_kmap) {
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int kk = acc_kmap ? acc_k<T>(s, lk) : 4 * s + lk;
+    T bre[2], bim[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      double2 pv = Ps[kk][16 * b + lr];
+      bre[b] = static_cast<T>(pv.x);
+      bim[b] = static_cast<T>(pv.y);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const T are = af[a][s].x, aim = af[a][s].y, naim = -aim;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cre[a][b] = mfma16(are, bre[b], cre[a][b]);
+        cim[a][b] = mfma16(are, bim[b], cim[a][b]);
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cre[a][b] = mfma16(naim, bim[b], cre[a][b]);
+        cim[a][b] = mfma16(aim, bre[b], cim[a][b]);
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void zero_acc(typename v4of<T>::t (*cre)[2],
+                                         typename v4of<T>::t (*cim)[2]) {
+  using V4 = typename v4of<T>::t;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -127,44 +287,59 @@ __device__ void panel_work(const GJJob& jb, int wg, int nt, double2 (*Ps)[TB + 1
       cre[a][b] = V4{0, 0, 0, 0};
       cim[a][b] = V4{0, 0, 0, 0};
     }
-#pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    T bre[2], bim[2];
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      double2 pv = Ps[4 * s + lk][16 * b + lr];
-      bre[b] = static_cast<T>(pv.x);
-      bim[b] = static_cast<T>(pv.y);
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      T are = af[a][s].x, aim = af[a][s].y, naim = -aim;
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        cre[a][b] = mfma16(are, bre[b], cre[a][b]);
-        cre[a][b] = mfma16(naim, bim[b], cre[a][b]);
-        cim[a][b] = mfma16(are, bim[b], cim[a][b]);
-        cim[a][b] = mfma16(aim, bre[b], cim[a][b]);
-      }
-    }
+}
+
+// Panel 0 of a block: every workgroup inverts the pivot block, then each wave
+// forms one row tile I of L (copied out) and Q = L P.
+template <typename T>
+__device__ void panel_work(const GJJob& jb, int wg, int nt, double2 (*Ps)[TB + 1],
+                           double2 (*xrow)[TB], double2 (*xcol)[TB]) {
+  using T2 = typename cplx<T>::t;
+  using V4 = typename v4of<T>::t;
+  T2* X = static_cast<T2*>(jb.X);
+  const int K = jb.k;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int I = wg * 4 + wave;
+  const bool active = I < nt && I != K;
+  {
+    const T2* D = X + tile_index(K, K) * TB * TB;
+    for (int e = tid; e < TB * TB; e += 256) Ps[e / TB][e % TB] = to_c128(D[e]);
   }
-  T2* Qb = static_cast<T2*>(jb.Q) + size_t(I) * TB * TB;
+  T2 af[2][8];
+  if (active) {
+    const T2* src = (I >= K) ? X + tile_index(I, K) * TB * TB : X + tile_index(K, I) * TB * TB;
+    const bool trans = I < K;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        int rr = 16 * a + lr, kk = 4 * s + lk;
+        af[a][s] = trans ? src[kk * TB + rr] : src[rr * TB + kk];
+      }
+  }
+  __syncthreads();
+  const double minpiv = invert_pivot_block(Ps, xrow, xcol);
+  if (wg == 0) {
+    for (int e = tid; e < TB * TB; e += 256) jb.Pn[e] = Ps[e / TB][e % TB];
+    if (tid == 0) *jb.health = minpiv;
+  }
+  if (!active) return;
+  T2* Lb = static_cast<T2*>(jb.Ln) + size_t(I) * TB * TB;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        T2 v;
-        v.x = cre[a][b][q];
-        v.y = cim[a][b][q];
-        Qb[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr] = v;
-      }
+    for (int s = 0; s < 8; ++s) Lb[(16 * a + lr) * TB + 4 * s + lk] = af[a][s];
+  V4 cre[2][2], cim[2][2];
+  zero_acc<T>(cre, cim);
+  q_from_rows<T>(cre, cim, af, Ps, lr, lk, false);
+  tile_store_acc<T>(cre, cim, static_cast<T2*>(jb.Qn) + size_t(I) * TB * TB, T(1), lr, lk);
 }
 
-// Trailing update: one wave per packed tile.
+// Trailing update k: one wave per packed tile, skipping tile column `skip`.
 template <typename T>
-__device__ void update_work(const GJJob& jb, int wg, size_t tiles) {
+__device__ void update_work(const GJJob& jb, int wg, size_t tiles, int skip) {
   using T2 = typename cplx<T>::t;
   using V4 = typename v4of<T>::t;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -172,6 +347,7 @@ __device__ void update_work(const GJJob& jb, int wg, size_t tiles) {
   if (t >= tiles) return;
   int I, J;
   tile_coords(static_cast<int>(t), &I, &J);
+  if (I == skip || J == skip) return;
   const int K = jb.k;
   T2* dst = static_cast<T2*>(jb.X) + t * TB * TB;
   const T sg = jb.last ? T(-1) : T(1);
@@ -200,59 +376,156 @@ __device__ void update_work(const GJJob& jb, int wg, size_t tiles) {
   }
   const int lr = lane & 15, lk = lane >> 4;
   V4 cre[2][2], cim[2][2];
+  tile_load_acc<T>(cre, cim, dst, false, lr, lk);
+  tile_nt_update<T>(cre, cim, Q + size_t(I) * TB * TB, L + size_t(J) * TB * TB, lr, lk, 0, 2, 0, 2);
+  tile_store_acc<T>(cre, cim, dst, sg, lr, lk);
+}
+
+// Look-ahead for panel Kn = k + 1, one workgroup per row tile I, one wave per
+// 16 x 16 quadrant (qa, qb):
+//  1. the two 16 x 16 blocks (a', qa), a' = 0, 1, of L_{Kn}[I]^T after update k,
+//     in accumulator layout:
+//       I >  Kn: S(I,Kn)^T - L_k[Kn] Q_k[I]^T
+//       I <  Kn, I != k: S(Kn,I) - Q_k[Kn] L_k[I]^T
+//       I == k: Q_k[Kn]                  (tile (Kn, k) lies in pivot column k)
+//     these registers are rows 16 qa .. 16 qa + 15 of L_{Kn}[I], i.e. the left
+//     operand of Q = L P, without a transpose;
+//  2. quadrant (qa, qb) of the updated pivot block S(Kn,Kn) - Q_k[Kn] L_k[Kn]^T
+//     into LDS; 3. invert it (all waves); 4. quadrant (qa, qb) of
+//     Q_{Kn}[I] = L_{Kn}[I] P.
+template <typename T>
+__device__ void lookahead_work(const GJJob& jb, int I, int nt, double2 (*Ps)[TB + 1],
+                               double2 (*xrow)[TB], double2 (*xcol)[TB]) {
+  using T2 = typename cplx<T>::t;
+  using V4 = typename v4of<T>::t;
+  const T2* X = static_cast<const T2*>(jb.X);
+  const T2* Q = static_cast<const T2*>(jb.Q);
+  const T2* L = static_cast<const T2*>(jb.L);
+  const int k = jb.k, Kn = k + 1;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int qa = wave >> 1, qb = wave & 1;
+  const bool active = I < nt && I != Kn;
+  V4 cre[2][2], cim[2][2];   // [a'][0] used
+  if (active) {
+    // accumulator init: element (i, j) of block (a', qa) of L^T
+    const T2* src;
+    bool tr;
+    if (I == k) {
+      src = Q + size_t(Kn) * TB * TB;
+      tr = false;
+    } else if (I > Kn) {
+      src = X + tile_index(I, Kn) * TB * TB;
+      tr = true;
+    } else {
+      src = X + tile_index(Kn, I) * TB * TB;
+      tr = false;
+    }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int a2 = 0; a2 < 2; ++a2)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        T2 v = dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr];
-        cre[a][b][q] = v.x;
-        cim[a][b][q] = v.y;
+        const int i = 16 * a2 + mfma_row<T>(lk, q), j = 16 * qa + lr;
+        T2 v = tr ? src[j * TB + i] : src[i * TB + j];
+        cre[a2][0][q] = v.x;
+        cim[a2][0][q] = v.y;
       }
-  const T2* QI = Q + size_t(I) * TB * TB;
-  const T2* LJ = L + size_t(J) * TB * TB;
+    if (I > Kn)
+      tile_nt_update<T>(cre, cim, L + size_t(Kn) * TB * TB, Q + size_t(I) * TB * TB + 16 * qa * TB,
+                        lr, lk, 0, 2, 0, 1);
+    else if (I != k)
+      tile_nt_update<T>(cre, cim, Q + size_t(Kn) * TB * TB, L + size_t(I) * TB * TB + 16 * qa * TB,
+                        lr, lk, 0, 2, 0, 1);
+    if (qb == 0) {   // rows 16 qa .. of L_{Kn}[I] for the update of panel Kn
+      T2* Lb = static_cast<T2*>(jb.Ln) + size_t(I) * TB * TB;
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    T2 av[2], bv[2];
+      for (int a2 = 0; a2 < 2; ++a2)
 #pragma unroll
-    for (int a = 0; a < 2; ++a) av[a] = QI[(16 * a + lr) * TB + 4 * s + lk];
-#pragma unroll
-    for (int b = 0; b < 2; ++b) bv[b] = LJ[(16 * b + lr) * TB + 4 * s + lk];
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      T nare = -av[a].x, aim = av[a].y, naim = -av[a].y;
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        cre[a][b] = mfma16(nare, bv[b].x, cre[a][b]);
-        cre[a][b] = mfma16(aim, bv[b].y, cre[a][b]);
-        cim[a][b] = mfma16(nare, bv[b].y, cim[a][b]);
-        cim[a][b] = mfma16(naim, bv[b].x, cim[a][b]);
-      }
+        for (int q = 0; q < 4; ++q) {
+          T2 v;
+          v.x = cre[a2][0][q];
+          v.y = cim[a2][0][q];
+          Lb[(16 * qa + lr) * TB + 16 * a2 + mfma_row<T>(lk, q)] = v;
+        }
     }
   }
+  {  // quadrant (qa, qb) of the updated pivot block
+    V4 dre[2][2], dim[2][2];
+    const T2* S = X + tile_index(Kn, Kn) * TB * TB + (16 * qa) * TB + 16 * qb;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+    for (int q = 0; q < 4; ++q) {
+      T2 v = S[mfma_row<T>(lk, q) * TB + lr];
+      dre[0][0][q] = v.x;
+      dim[0][0][q] = v.y;
+    }
+    tile_nt_update<T>(dre, dim, Q + size_t(Kn) * TB * TB + (16 * qa) * TB,
+                      L + size_t(Kn) * TB * TB + (16 * qb) * TB, lr, lk, 0, 1, 0, 1);
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int q = 0; q < 4; ++q)
+      Ps[16 * qa + mfma_row<T>(lk, q)][16 * qb + lr] =
+          make_double2(static_cast<double>(dre[0][0][q]), static_cast<double>(dim[0][0][q]));
+  }
+  __syncthreads();
+  const double minpiv = invert_pivot_block(Ps, xrow, xcol);
+  if (I == 0) {
+    for (int e = tid; e < TB * TB; e += 256) jb.Pn[e] = Ps[e / TB][e % TB];
+    if (tid == 0) *jb.health = minpiv;
+  }
+  if (!active) return;
+  // Q quadrant (qa, qb): A fragments (row 16 qa + lr, k-step 4 a' + q) come from
+  // the L^T accumulators, B fragments from P with the matching k index
+  V4 qre[2][2], qim[2][2];
+  qre[0][0] = V4{0, 0, 0, 0};
+  qim[0][0] = V4{0, 0, 0, 0};
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        T2 v;
-        v.x = cre[a][b][q] * sg;
-        v.y = cim[a][b][q] * sg;
-        dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr] = v;
-      }
+  for (int s = 0; s < 8; ++s) {
+    const int kk = acc_k<T>(s, lk);
+    const double2 pv = Ps[kk][16 * qb + lr];
+    const T bre = static_cast<T>(pv.x), bim = static_cast<T>(pv.y);
+    const T are = cre[s >> 2][0][s & 3], aim = cim[s >> 2][0][s & 3];
+    qre[0][0] = mfma16(are, bre, qre[0][0]);
+    qim[0][0] = mfma16(are, bim, qim[0][0]);
+    qre[0][0] = mfma16(-aim, bim, qre[0][0]);
+    qim[0][0] = mfma16(aim, bre, qim[0][0]);
+  }
+  T2* Qb = static_cast<T2*>(jb.Qn) + size_t(I) * TB * TB + (16 * qa) * TB + 16 * qb;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    T2 v;
+    v.x = qre[0][0][q];
+    v.y = qim[0][0][q];
+    Qb[mfma_row<T>(lk, q) * TB + lr] = v;
+  }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_gj(GJJobs jobs, int nt, size_t tiles) {
+__global__ __launch_bounds__(256) void k_gj_panel(GJJobs jobs, int nt) {
   __shared__ double2 Ps[TB][TB + 1];
+  __shared__ double2 xrow[4][TB], xcol[4][TB];
   int wg = blockIdx.x;
   GJJob jb = pick(jobs, &wg);
-  if (jb.kind == 0)
-    panel_work<T>(jb, wg, nt, Ps);
+  panel_work<T>(jb, wg, nt, Ps, xrow, xcol);
+}
+
+// Update k (all tiles; negated when last) -- the final panel of a block.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gj_update(GJJobs jobs, size_t tiles) {
+  int wg = blockIdx.x;
+  GJJob jb = pick(jobs, &wg);
+  update_work<T>(jb, wg, tiles, -1);
+}
+
+// Update k outside column k+1, plus the look-ahead panel k+1.
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_gj_fused(GJJobs jobs, int nt, size_t tiles) {
+  __shared__ double2 Ps[TB][TB + 1];
+  __shared__ double2 xrow[4][TB], xcol[4][TB];
+  int wg = blockIdx.x;
+  GJJob jb = pick(jobs, &wg);
+  if (wg < jb.wgs_upd)
+    update_work<T>(jb, wg, tiles, jb.k + 1);
   else
-    update_work<T>(jb, wg, tiles);
+    lookahead_work<T>(jb, wg - jb.wgs_upd, nt, Ps, xrow, xcol);
 }
 
 // dst = D - C1 src1 C1 - C2 src2 C2 on packed tiles (src may be null), with
@@ -267,7 +540,7 @@ struct SchurJob {
   const double2* c2;
 };
 struct SchurJobs {
-  SchurJob j[2];
+  SchurJob j[MAXJ];
   int n;
 };
 
@@ -276,8 +549,14 @@ __global__ __launch_bounds__(256) void k_schur(SchurJobs jobs, int ny, size_t ti
   using T2 = typename cplx<T>::t;
   const size_t t = blockIdx.x % tiles;
   const int ji = static_cast<int>(blockIdx.x / tiles);
-  SchurJob jb = jobs.j[0];
-  if (ji == 1) jb = jobs.j[1];
+  SchurJob jb;
+  jb.dst = RCP_SEL8(jobs, ji, dst);
+  jb.src1 = RCP_SEL8(jobs, ji, src1);
+  jb.src2 = RCP_SEL8(jobs, ji, src2);
+  jb.dco = RCP_SEL8(jobs, ji, dco);
+  jb.eco = RCP_SEL8(jobs, ji, eco);
+  jb.c1 = RCP_SEL8(jobs, ji, c1);
+  jb.c2 = RCP_SEL8(jobs, ji, c2);
   int I, J;
   tile_coords(static_cast<int>(t), &I, &J);
   T2* dst = static_cast<T2*>(jb.dst) + t * TB * TB;
@@ -301,99 +580,148 @@ __global__ __launch_bounds__(256) void k_schur(SchurJobs jobs, int ny, size_t ti
   }
 }
 
+// Factor B same-shape geometries in lockstep: every launch carries the chains
+// of all of them (two per geometry).
 template <typename T>
-int run_factor(rcp_factors* f, hipStream_t s) {
-  const int N = f->nx, ny = f->ny, nt = f->nt, m = f->m;
-  const size_t tiles = f->tiles;
+int run_factor(rcp_factors* const* fs, int B, hipStream_t s) {
+  const rcp_factors* f0 = fs[0];
+  const int N = f0->nx, ny = f0->ny, nt = f0->nt, m = f0->m;
+  const size_t tiles = f0->tiles;
   const int lenL = m, lenR = N - 1 - m;
-  auto D = [&](int i) { return f->dco + size_t(i) * ny; };
-  auto E = [&](int i) { return f->eco + size_t(i) * ny; };
-  auto C = [&](int i) { return f->cco + size_t(i) * ny; };
+  auto D = [&](int g, int i) { return fs[g]->dco + size_t(i) * ny; };
+  auto E = [&](int g, int i) { return fs[g]->eco + size_t(i) * ny; };
+  auto C = [&](int g, int i) { return fs[g]->cco + size_t(i) * ny; };
 
   auto schur = [&](SchurJobs js) -> int {
     if (js.n == 0) return RCP_OK;
+    int nsrc = 0;
+    for (int q = 0; q < js.n; ++q) nsrc += 1 + (js.j[q].src1 != nullptr) + (js.j[q].src2 != nullptr);
+    KTimer kt(K_SCHUR, s, double(nsrc) * tiles * TB * TB * f0->elem_bytes);
     k_schur<T><<<static_cast<int>(tiles * js.n), 256, 0, s>>>(js, ny, tiles);
     RCP_HIP(hipGetLastError());
     return RCP_OK;
   };
   const int upd_wgs = static_cast<int>((tiles + 3) / 4);
-  const int pan_wgs = ceil_div(nt, 4);
-  // sweep the blocks of up to two chains through all panels
-  auto sweep = [&](int nb, const int* blocks) -> int {
-    for (int k = 0; k < nt; ++k) {
-      GJJobs pj{}, uj{};
-      int gp = 0, gu = 0;
-      for (int c = 0; c < nb; ++c) {
-        GJJob b{};
-        b.kind = 0;
-        b.k = k;
+  const int pan_wgs = ceil_div(nt, 4);   // first panel: four row tiles per workgroup
+  const int look_wgs = nt;               // look-ahead: one row tile per workgroup
+  const double cmac = 8.0 * TB * TB * TB;   // flops of one TB^3 complex product
+  // Sweep the given blocks (chain c of geometry g) through all panels; the
+  // panel buffers of chain c alternate between halves 2c and 2c+1.
+  struct Chain {
+    int g, c, block;
+  };
+  auto sweep = [&](int nch, const Chain* ch) -> int {
+    auto job = [&](const Chain& x, int k) {
+      const rcp_factors* f = fs[x.g];
+      GJJob b{};
+      b.k = k;
+      b.X = block_ptr(f, x.block);
+      const int cur = 2 * x.c + (k & 1), nxt = 2 * x.c + ((k + 1) & 1);
+      b.L = f->wsL[cur];
+      b.Q = f->wsQ[cur];
+      b.P = f->wsP[cur];
+      b.Ln = f->wsL[nxt];
+      b.Qn = f->wsQ[nxt];
+      b.Pn = f->wsP[nxt];
+      b.health = f->health + size_t(x.block) * nt + (k + 1 < nt ? k + 1 : k);
+      return b;
+    };
+    {   // panel 0 (writes the "next" buffers of k = -1, i.e. half 2c)
+      GJJobs js{};
+      for (int q = 0; q < nch; ++q) {
+        GJJob b = job(ch[q], -1);
+        b.k = 0;
+        b.health = fs[ch[q].g]->health + size_t(ch[q].block) * nt;
         b.wgs = pan_wgs;
-        b.X = block_ptr(f, blocks[c]);
-        b.L = f->wsL[c];
-        b.Q = f->wsQ[c];
-        b.P = f->wsP[c];
-        b.health = f->health + size_t(blocks[c]) * nt + k;
-        pj.j[pj.n++] = b;
-        gp += pan_wgs;
-        GJJob u = b;
-        u.kind = 1;
-        u.last = (k == nt - 1);
-        u.wgs = upd_wgs;
-        uj.j[uj.n++] = u;
-        gu += upd_wgs;
+        js.j[js.n++] = b;
       }
-      k_gj<T><<<gp, 256, 0, s>>>(pj, nt, tiles);
+      KTimer kt(K_GJ_PANEL, s, nch * cmac * nt);
+      k_gj_panel<T><<<nch * pan_wgs, 256, 0, s>>>(js, nt);
       RCP_HIP(hipGetLastError());
-      k_gj<T><<<gu, 256, 0, s>>>(uj, nt, tiles);
+    }
+    for (int k = 0; k + 1 < nt; ++k) {
+      GJJobs js{};
+      for (int q = 0; q < nch; ++q) {
+        GJJob b = job(ch[q], k);
+        b.wgs_upd = upd_wgs;
+        b.wgs = upd_wgs + look_wgs;
+        js.j[js.n++] = b;
+      }
+      KTimer kt(K_GJ_UPDATE, s, nch * cmac * double(tiles));
+      k_gj_fused<T><<<nch * (upd_wgs + look_wgs), 256, 0, s>>>(js, nt, tiles);
+      RCP_HIP(hipGetLastError());
+    }
+    {   // final update, negated
+      GJJobs js{};
+      for (int q = 0; q < nch; ++q) {
+        GJJob b = job(ch[q], nt - 1);
+        b.last = 1;
+        b.wgs = upd_wgs;
+        b.wgs_upd = upd_wgs;
+        js.j[js.n++] = b;
+      }
+      KTimer kt(K_GJ_LAST, s, nch * cmac * double(tiles - nt));
+      k_gj_update<T><<<nch * upd_wgs, 256, 0, s>>>(js, tiles);
       RCP_HIP(hipGetLastError());
     }
     return RCP_OK;
   };
 
-  // chain heads
-  {
+  {   // chain heads
     SchurJobs js{};
-    if (lenL > 0) js.j[js.n++] = SchurJob{block_ptr(f, 0), nullptr, nullptr, D(0), E(0), nullptr, nullptr};
-    if (lenR > 0)
-      js.j[js.n++] = SchurJob{block_ptr(f, N - 1), nullptr, nullptr, D(N - 1), E(N - 1), nullptr, nullptr};
+    for (int g = 0; g < B; ++g) {
+      if (lenL > 0)
+        js.j[js.n++] = SchurJob{block_ptr(fs[g], 0), nullptr, nullptr, D(g, 0), E(g, 0), nullptr, nullptr};
+      if (lenR > 0)
+        js.j[js.n++] = SchurJob{block_ptr(fs[g], N - 1), nullptr, nullptr, D(g, N - 1), E(g, N - 1),
+                                nullptr, nullptr};
+    }
     int rc = schur(js);
     if (rc) return rc;
   }
   const int steps = lenL > lenR ? lenL : lenR;
   for (int st = 0; st < steps; ++st) {
-    int blocks[2], nb = 0;
-    int bL = st < lenL ? st : -1, bR = st < lenR ? N - 1 - st : -1;
-    if (bL >= 0) blocks[nb++] = bL;
-    if (bR >= 0) blocks[nb++] = bR;
-    int rc = sweep(nb, blocks);
+    Chain ch[MAXJ];
+    int nch = 0;
+    const int bL = st < lenL ? st : -1, bR = st < lenR ? N - 1 - st : -1;
+    for (int g = 0; g < B; ++g) {
+      if (bL >= 0) ch[nch++] = Chain{g, 0, bL};
+      if (bR >= 0) ch[nch++] = Chain{g, 1, bR};
+    }
+    int rc = sweep(nch, ch);
     if (rc) return rc;
     SchurJobs js{};
-    if (bL >= 0 && bL + 1 < m)
-      js.j[js.n++] = SchurJob{block_ptr(f, bL + 1), block_ptr(f, bL), nullptr, D(bL + 1), E(bL + 1),
-                              C(bL), nullptr};
-    if (bR >= 0 && bR - 1 > m)
-      js.j[js.n++] = SchurJob{block_ptr(f, bR - 1), block_ptr(f, bR), nullptr, D(bR - 1), E(bR - 1),
-                              C(bR - 1), nullptr};
+    for (int g = 0; g < B; ++g) {
+      if (bL >= 0 && bL + 1 < m)
+        js.j[js.n++] = SchurJob{block_ptr(fs[g], bL + 1), block_ptr(fs[g], bL), nullptr,
+                                D(g, bL + 1), E(g, bL + 1), C(g, bL), nullptr};
+      if (bR >= 0 && bR - 1 > m)
+        js.j[js.n++] = SchurJob{block_ptr(fs[g], bR - 1), block_ptr(fs[g], bR), nullptr,
+                                D(g, bR - 1), E(g, bR - 1), C(g, bR - 1), nullptr};
+    }
     rc = schur(js);
     if (rc) return rc;
   }
-  // middle block
-  {
+  {   // middle blocks
     SchurJobs js{};
-    SchurJob z{block_ptr(f, m), nullptr, nullptr, D(m), E(m), nullptr, nullptr};
-    if (m - 1 >= 0) {
-      z.src1 = block_ptr(f, m - 1);
-      z.c1 = C(m - 1);
+    Chain ch[MAXJ];
+    int nch = 0;
+    for (int g = 0; g < B; ++g) {
+      SchurJob z{block_ptr(fs[g], m), nullptr, nullptr, D(g, m), E(g, m), nullptr, nullptr};
+      if (m - 1 >= 0) {
+        z.src1 = block_ptr(fs[g], m - 1);
+        z.c1 = C(g, m - 1);
+      }
+      if (m + 1 < N) {
+        z.src2 = block_ptr(fs[g], m + 1);
+        z.c2 = C(g, m);
+      }
+      js.j[js.n++] = z;
+      ch[nch++] = Chain{g, 0, m};
     }
-    if (m + 1 < N) {
-      z.src2 = block_ptr(f, m + 1);
-      z.c2 = C(m);
-    }
-    js.j[js.n++] = z;
     int rc = schur(js);
     if (rc) return rc;
-    int blocks[1] = {m};
-    rc = sweep(1, blocks);
+    rc = sweep(nch, ch);
     if (rc) return rc;
   }
   return RCP_OK;
@@ -403,21 +731,27 @@ int run_factor(rcp_factors* f, hipStream_t s) {
 
 namespace rcp {
 
-int factor_blocks(rcp_factors* f, hipStream_t s) {
-  int rc = (f->precision == RCP_FP64) ? run_factor<double>(f, s) : run_factor<float>(f, s);
+int factor_blocks(rcp_factors* const* fs, int B, hipStream_t s) {
+  if (B < 1 || B > MAXJ / 2) return fail(RCP_EINVAL, "batch of 1 to 4 geometries");
+  const int prec = fs[0]->precision;
+  int rc = (prec == RCP_FP64) ? run_factor<double>(fs, B, s) : run_factor<float>(fs, B, s);
   if (rc) return rc;
   // pivot health: one wait, then scan the smallest pivot modulus of every panel
-  const size_t nh = size_t(f->nx) * f->nt;
-  std::vector<double> h(nh);
-  RCP_HIP(hipMemcpyAsync(h.data(), f->health, nh * sizeof(double), hipMemcpyDeviceToHost, s));
   RCP_HIP(hipStreamSynchronize(s));
-  // diagonal entries are O(4/h^2); a pivot below 1e-13 of that scale is treated as singular
-  const double tiny = 1e-13 * 4.0 / (f->h * f->h);
-  for (size_t q = 0; q < nh; ++q) {
-    if (!(h[q] > tiny) || !std::isfinite(h[q])) {
-      return fail(RCP_ESINGULAR, "pivot block " + std::to_string(q % f->nt) + " of column block " +
-                                     std::to_string(q / f->nt) + " has pivot modulus " +
-                                     std::to_string(h[q]));
+  for (int g = 0; g < B; ++g) {
+    const rcp_factors* f = fs[g];
+    const size_t nh = size_t(f->nx) * f->nt;
+    std::vector<double> h(nh);
+    RCP_HIP(hipMemcpy(h.data(), f->health, nh * sizeof(double), hipMemcpyDeviceToHost));
+    // diagonal entries are O(4/h^2); a pivot below 1e-13 of that scale is treated as singular
+    const double tiny = 1e-13 * 4.0 / (f->h * f->h);
+    for (size_t q = 0; q < nh; ++q) {
+      if (!(h[q] > tiny) || !std::isfinite(h[q])) {
+        return fail(RCP_ESINGULAR, "geometry " + std::to_string(g) + ": pivot block " +
+                                       std::to_string(q % f->nt) + " of column block " +
+                                       std::to_string(q / f->nt) + " has pivot modulus " +
+                                       std::to_string(h[q]));
+      }
     }
   }
   return RCP_OK;

@@ -50,9 +50,9 @@ struct rcp_factors {
   double* eps;
   double2 *sxc, *sxf, *syc, *syf;
   double2 *dco, *eco, *cco;
-  void* wsL[2];
-  void* wsQ[2];
-  double2* wsP[2];
+  void* wsL[4];                // panel buffers: chain c, parity p at index 2c + p
+  void* wsQ[4];
+  double2* wsP[4];
   double* health;
   double2* vec[rcp::NVEC];
   double* red;
@@ -85,6 +85,30 @@ inline void* block_ptr(const rcp_factors* f, int i) {
 }
 
 // ---------------------------------------------------------------------------
+// Optional launch timing for benchmarks: when enabled, every sample_every-th
+// launch of a kernel class is bracketed by two HIP events on its stream, and
+// the algorithmic work of that launch (flops or bytes) is recorded with it.
+enum KClass {
+  K_GJ_PANEL = 0,
+  K_GJ_UPDATE = 1,
+  K_SCHUR = 2,
+  K_GEMV = 3,
+  K_GEMM = 4,
+  K_GJ_LAST = 5,
+  K_NCLASS = 6
+};
+void ktimer_begin(int cls, hipStream_t s, double work, void** token);
+void ktimer_end(void* token, hipStream_t s);
+struct KTimer {
+  void* tok = nullptr;
+  hipStream_t s;
+  KTimer(int cls, hipStream_t st, double work) : s(st) { ktimer_begin(cls, st, work, &tok); }
+  ~KTimer() {
+    if (tok) ktimer_end(tok, s);
+  }
+};
+
+// ---------------------------------------------------------------------------
 // launchers (assembly.hip)
 int launch_eps_from_widths(const rcp_grid* g, const rcp_pillars* p, double* eps, hipStream_t s);
 int launch_assemble(rcp_factors* f, const double* eps_src, hipStream_t s);
@@ -92,7 +116,8 @@ int launch_width_grad(const rcp_grid* g, const rcp_pillars* p, const double* gra
                       double* grad_w, hipStream_t s);
 
 // factor.hip
-int factor_blocks(rcp_factors* f, hipStream_t s);
+// Factor B (1..4) geometries of identical shape in the same launches.
+int factor_blocks(rcp_factors* const* fs, int B, hipStream_t s);
 
 // solve.hip
 // u = A^{-1} f (conjop = 0) or conj(A)^{-1} f = A^{-dag} f (conjop = 1), one

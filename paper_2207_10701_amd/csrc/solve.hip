@@ -19,7 +19,7 @@
 namespace {
 using namespace rcp;
 
-constexpr int NPMAX = 2048;   // largest padded block size the vector sweep keeps in LDS
+constexpr int NPMAX = 2048;   // largest padded block size supported
 
 struct SvJob {
   const void* X;
@@ -40,18 +40,24 @@ __device__ __forceinline__ double2 maybe_conj(double2 a, int c) {
   return c ? make_double2(a.x, -a.y) : a;
 }
 
+// One 1024-thread workgroup per (job, half of a 32-row strip): 16 output rows.
+// Lane l accumulates output row o = l % 16 of the half over 8 of the 32 inner
+// indices of each tile (q = l / 16 picks which 8); the 16 waves take the tiles
+// J of the strip round robin.  Stored tiles (I, J <= I) are read along rows,
+// tiles (J > I, I) along columns (their transpose).  Partial sums are combined
+// in a fixed order, so the result does not depend on scheduling.
 template <typename T>
-__global__ __launch_bounds__(256) void k_gemv(SvJobs jobs, int nt, int ny, int conjop) {
+__global__ __launch_bounds__(1024) void k_gemv(SvJobs jobs, int nt, int ny, int conjop) {
   using T2 = typename cplx<T>::t;
   __shared__ double2 g[NPMAX];
-  __shared__ double2 red[TB][TB + 1];
-  __shared__ double2 rowsum[TB];
-  const int ji = blockIdx.x / nt, I = blockIdx.x % nt;
+  __shared__ double2 red[16][16];
+  const int ji = blockIdx.x / (2 * nt), rem = blockIdx.x % (2 * nt);
+  const int I = rem >> 1, half = rem & 1;
   SvJob jb = jobs.j[0];
   if (ji == 1) jb = jobs.j[1];
   const int tid = threadIdx.x;
   const int np = nt * TB;
-  for (int k = tid; k < np; k += 256) {
+  for (int k = tid; k < np; k += 1024) {
     double2 v = make_double2(0.0, 0.0);
     if (k < ny) {
       if (jb.f) v = jb.f[k];
@@ -62,50 +68,43 @@ __global__ __launch_bounds__(256) void k_gemv(SvJobs jobs, int nt, int ny, int c
   }
   __syncthreads();
   const T2* X = static_cast<const T2*>(jb.X);
-  const int r = tid >> 3, c0 = (tid & 7) * 4;
-  const double cs = conjop ? -1.0 : 1.0;
-  double2 arow = make_double2(0.0, 0.0);
-  double2 acol[4];
+  const int wave = tid >> 6, lane = tid & 63;
+  const int o = lane & 15, q = lane >> 4;
+  const int oi = half * 16 + o;          // row (or column) inside the 32-wide strip
+  const double cs_im = conjop ? -1.0 : 1.0;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int J = wave; J < nt; J += 16) {
+    T2 x[8];
+    if (J <= I) {
+      const T2* t = X + tile_index(I, J) * TB * TB + oi * TB + 8 * q;
 #pragma unroll
-  for (int c = 0; c < 4; ++c) acol[c] = make_double2(0.0, 0.0);
-  // tiles (I, J), J <= I: rows of this strip
-  for (int J = 0; J <= I; ++J) {
-    const T2* t = X + tile_index(I, J) * TB * TB + r * TB + c0;
+      for (int c = 0; c < 8; ++c) x[c] = t[c];
+    } else {
+      const T2* t = X + tile_index(J, I) * TB * TB + (8 * q) * TB + oi;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      double2 x = to_c128(t[c]);
-      x.y *= cs;
-      arow = cadd(arow, cmul(x, g[J * TB + c0 + c]));
+      for (int c = 0; c < 8; ++c) x[c] = t[c * TB];
+    }
+    const double2* gg = g + J * TB + 8 * q;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      double2 xv = to_c128(x[c]);
+      xv.y *= cs_im;
+      acc = cadd(acc, cmul(xv, gg[c]));
     }
   }
-  // tiles (J, I), J > I: X(I-rows, J-cols) = tile(J, I)^T
-  for (int J = I + 1; J < nt; ++J) {
-    const T2* t = X + tile_index(J, I) * TB * TB + r * TB + c0;
-    double2 gv = g[J * TB + r];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      double2 x = to_c128(t[c]);
-      x.y *= cs;
-      acol[c] = cadd(acol[c], cmul(x, gv));
-    }
-  }
-  // reduce
-#pragma unroll
-  for (int off = 1; off < 8; off <<= 1) {
-    arow.x += __shfl_xor(arow.x, off, 64);
-    arow.y += __shfl_xor(arow.y, off, 64);
-  }
-  if ((tid & 7) == 0) rowsum[r] = arow;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) red[r][c0 + c] = acol[c];
+  acc.x += __shfl_xor(acc.x, 16, 64);
+  acc.y += __shfl_xor(acc.y, 16, 64);
+  acc.x += __shfl_xor(acc.x, 32, 64);
+  acc.y += __shfl_xor(acc.y, 32, 64);
+  if (lane < 16) red[wave][lane] = acc;
   __syncthreads();
-  if (tid < TB) {
-    double2 s = rowsum[tid];
-    for (int q = 0; q < TB; ++q) s = cadd(s, red[q][tid]);
-    int row = I * TB + tid;
+  if (tid < 16) {
+    double2 sum = red[0][tid];
+    for (int w = 1; w < 16; ++w) sum = cadd(sum, red[w][tid]);
+    const int row = I * TB + half * 16 + tid;
     if (row < ny) {
       double2 b = jb.base ? jb.base[row] : make_double2(0.0, 0.0);
-      jb.out[row] = cadd(b, s);
+      jb.out[row] = cadd(b, sum);
     }
   }
 }
@@ -317,7 +316,8 @@ int run_solve_vec(rcp_factors* f, const double2* rhs, double2* u, int conjop, in
   auto C = [&](int i) { return f->cco + size_t(i) * ny; };
   auto launch = [&](SvJobs& js) -> int {
     if (js.n == 0) return RCP_OK;
-    k_gemv<T><<<nt * js.n, 256, 0, s>>>(js, nt, ny, conjop);
+    KTimer kt(K_GEMV, s, double(js.n) * f->tiles * TB * TB * sizeof(typename cplx<T>::t));
+    k_gemv<T><<<2 * nt * js.n, 1024, 0, s>>>(js, nt, ny, conjop);
     RCP_HIP(hipGetLastError());
     return RCP_OK;
   };
@@ -471,6 +471,7 @@ int solve_multi_fp64(rcp_factors* f, int R, const double2* B, const double2* fli
   const int per_job = ceil_div(R, MT) * ceil_div(nt * TB, MT);
   auto launch = [&](MmJobs& js) -> int {
     if (js.n == 0) return RCP_OK;
+    KTimer kt(K_GEMM, s, 8.0 * js.n * double(R) * ny * ny);
     k_gemm_sweep<<<per_job * js.n, 256, 0, s>>>(js, R, N, ny, nt, rs, jline, conjop);
     RCP_HIP(hipGetLastError());
     return RCP_OK;

@@ -134,3 +134,20 @@ def test_refined_fp32_vs_fp64(rcp, name):
     Fa, ga = rcp.adjoint_grad(f32, p)
     Fb, gb = rcp.adjoint_grad(f64, p)
     assert rel(ga.cpu().numpy(), gb.cpu().numpy()) < 1e-5
+
+
+def test_factor_batch_matches_single_and_oracle(rcp):
+    """Geometries factored side by side give bit-identical results to one at a time."""
+    import torch
+    from dataclasses import replace
+    base = PROBLEMS["conc_cone"]
+    probs = [replace(base, widths=W.seeded_widths(len(base.widths), 300 + g)) for g in range(3)]
+    eps = [rcp.eps_from_widths(p, device="cuda") for p in probs]
+    facs = rcp.factor_batch(probs, eps)
+    Fb = [rcp.reciprocal_average(f, p).item() for f, p in zip(facs, probs)]
+    for p, e, fb in zip(probs, eps, Fb):
+        single = rcp.Factors(p, e)
+        assert rcp.reciprocal_average(single, p).item() == fb
+        ref = ora.reciprocal(oracle_setup(p))
+        assert abs(fb - ref) / ref < 1e-10
+    torch.cuda.synchronize()
