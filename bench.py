@@ -92,6 +92,33 @@ def cpu_baseline(p_full, width_wl=10):
             "sample_seconds": t, "sample_F": g.F}
 
 
+def serving(args):
+    """Poisson mix of concentrator/collimator requests: continuous batching vs sequential."""
+    import torch
+
+    import workloads as W
+    from paper_2207_10701_amd.serve import GpuExecutor, Server, summarize
+    reqs = W.serving_stream(args.serve_requests, rate=200.0, seed=5001, scale=args.serve_scale,
+                            adjoint_frac=0.2)
+    ex = GpuExecutor()
+    # warm the kernels once
+    Server(ex, slots=1, hbm_budget=200 << 30, cache=False).run(reqs[:1], realtime=False)
+    torch.cuda.synchronize()
+    seq = Server(ex, slots=1, hbm_budget=200 << 30, cache=False)
+    s_seq = summarize(seq.run(reqs, realtime=True))
+    conc = Server(ex, slots=4, hbm_budget=200 << 30, cache=True)
+    res = conc.run(reqs, realtime=True)
+    conc.close()
+    s_con = summarize(res)
+    return {"requests": len(reqs), "rate_per_s": 200.0, "scale": args.serve_scale,
+            "slots": 4, "p50_ms": round(s_con["p50_ms"], 2), "p99_ms": round(s_con["p99_ms"], 2),
+            "evals_per_s": round(s_con["evals_per_s"], 3), "max_inflight": conc.max_inflight,
+            "peak_factor_gb": round(conc.peak_bytes / 2 ** 30, 2),
+            "sequential": {"p50_ms": round(s_seq["p50_ms"], 2), "p99_ms": round(s_seq["p99_ms"], 2),
+                           "evals_per_s": round(s_seq["evals_per_s"], 3)},
+            "failed": s_con["failed"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +130,12 @@ def main():
     ap.add_argument("--timing-every", type=int, default=4)
     ap.add_argument("--no-extras", action="store_true", help="time the step only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=24,
+                    help="requests in the serving measurement (0 = skip)")
+    ap.add_argument("--serve-scale", type=float, default=0.25,
+                    help="width/depth scale of the serving mix (1 = widths 20-300, depths 10-60)")
+    ap.add_argument("--batch", type=int, default=1,
+                    help="geometries factored side by side per step (1-4)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -122,18 +155,27 @@ def main():
     stream = torch.cuda.current_stream()
     log(f"bench: {p.name} {p.nx}x{p.ny}, steps={args.steps} warmup={args.warmup}")
 
-    # inputs resident in HBM before timing: one seeded geometry per step
+    # inputs resident in HBM before timing: B seeded geometries per step
+    B = max(1, min(4, args.batch))
     nsteps = args.warmup + args.steps
     widths = [torch.tensor(W.seeded_widths(len(p.pillar_centers), 1002 + 97 * k), dtype=torch.float64,
-                           device=dev) for k in range(nsteps)]
-    buf = torch.empty(rcp.factor_bytes(p, rcp.RCP_FP64), dtype=torch.uint8, device=dev)
+                           device=dev) for k in range(nsteps * B)]
+    bufs = [torch.empty(rcp.factor_bytes(p, rcp.RCP_FP64), dtype=torch.uint8, device=dev)
+            for _ in range(B)]
+    buf = bufs[0]
 
     def step(k):
-        eps = rcp.eps_from_widths(p, widths[k], device=dev)
-        fac = rcp.Factors(p, eps, rcp.RCP_FP64, buffer=buf)
-        F, g = rcp.adjoint_grad(fac, p)
-        gw = rcp.width_grad(p, g, widths[k])
-        return fac, F, gw
+        ws = widths[k * B:(k + 1) * B]
+        eps = [rcp.eps_from_widths(p, w, device=dev) for w in ws]
+        if B == 1:
+            facs = [rcp.Factors(p, eps[0], rcp.RCP_FP64, buffer=bufs[0])]
+        else:
+            facs = rcp.factor_batch([p] * B, eps, rcp.RCP_FP64, buffers=bufs)
+        F = None
+        for fac, w in zip(facs, ws):
+            F, g = rcp.adjoint_grad(fac, p)
+            gw = rcp.width_grad(p, g, w)
+        return facs[-1], F, gw
 
     for k in range(args.warmup):
         fac, F, gw = step(k)
@@ -177,12 +219,13 @@ def main():
                              "rate": round(rate / (1e9 if "gemv" in name or name == "schur" else 1e12), 3),
                              "rate_unit": "GB/s" if ("gemv" in name or name == "schur") else "TFLOP/s"}
 
-    out = {"metric": METRIC, "value": round(args.steps / wall, 5), "unit": "evals/s",
+    out = {"metric": METRIC, "value": round(B * args.steps / wall, 5), "unit": "evals/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"{p.name}: {DESCR[p.name]}", "grid": [p.nx, p.ny],
                       "step": "eps map + assemble + factor + reciprocal F + adjoint dF/dwidths",
+                      "geometries_per_step": B,
                       "precision": "complex FP64"},
            "p50_ms": round(p50, 3), "p99_ms": round(p99, 3),
            "F": Fs[-1].item(), "roofline": roofline, "kernels": kernels}
@@ -191,6 +234,7 @@ def main():
         # factorisation alone
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        del fac
         eps = rcp.eps_from_widths(p, widths[-1], device=dev)
         a.record(stream)
         fac = rcp.Factors(p, eps, rcp.RCP_FP64, buffer=buf)
@@ -257,6 +301,9 @@ def main():
                                "F_rel_err_vs_fp64": abs(F32.item() - F64.item()) / abs(F64.item())}
         log(f"fp32 refined: factor {t_f32 * 1e3:.1f} ms, {it} steps, field err {zerr:.2e}")
         del f32, buf32
+    if args.serve_requests > 0:
+        out["serving"] = serving(args)
+        log(f"serving: {out['serving']}")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(p)

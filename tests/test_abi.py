@@ -1,0 +1,95 @@
+"""The C ABI library loads and exports every declared entry point; host-side
+argument checks return the documented error codes without touching the GPU."""
+import ctypes as C
+import re
+from pathlib import Path
+
+import pytest
+
+ROOT = Path(__file__).resolve().parents[1]
+HEADER = ROOT / "include" / "recip.h"
+
+
+def declared_functions():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rcp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_five_calls():
+    names = declared_functions()
+    for n in ("rcp_factor", "rcp_solve_multi_rhs", "rcp_reciprocal_average",
+              "rcp_brute_force_average", "rcp_adjoint_grad"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2207_10701_amd import _lib
+    lib = C.CDLL(str(_lib.LIB_PATH))
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def grid(nx=100, ny=100, npml=10, eps=None):
+    from paper_2207_10701_amd import _lib
+    return _lib.Grid(nx, ny, npml, 0.05, 6.283185307179586, 1e-8, 3, eps)
+
+
+def test_factor_bytes_and_invalid_grids():
+    from paper_2207_10701_amd import _lib
+    lib = _lib.lib
+    g = grid()
+    n64 = lib.rcp_factor_bytes(C.byref(g), _lib.RCP_FP64)
+    n32 = lib.rcp_factor_bytes(C.byref(g), _lib.RCP_FP32_REFINED)
+    assert n64 > n32 > 0
+    # packed lower tiles: ny = 100 -> 4 tiles of 32 -> 10 tiles per block
+    assert n64 >= 100 * 10 * 32 * 32 * 16
+    for bad in (grid(npml=50), grid(nx=0), grid(ny=3000)):
+        assert lib.rcp_factor_bytes(C.byref(bad), _lib.RCP_FP64) == 0
+    assert lib.rcp_factor_bytes(C.byref(g), 7) == 0
+
+
+def test_factor_argument_errors_on_host():
+    from paper_2207_10701_amd import _lib
+    lib = _lib.lib
+    out = C.c_void_p()
+    g = grid(npml=60)
+    assert lib.rcp_factor(C.byref(g), 0, None, 0, None, C.byref(out)) == _lib.RCP_EINVAL
+    assert b"PML" in lib.rcp_last_error()
+    g = grid(eps=None)
+    assert lib.rcp_factor(C.byref(g), 0, None, 0, None, C.byref(out)) == _lib.RCP_EINVAL
+    fake_eps = C.c_void_p(0x1000)
+    g = grid(eps=fake_eps.value)
+    assert lib.rcp_factor(C.byref(g), 0, C.c_void_p(0x100000), 16, None, C.byref(out)) == \
+        _lib.RCP_ENOMEM
+    assert b"needs" in lib.rcp_last_error()
+    assert lib.rcp_factor(C.byref(g), 5, C.c_void_p(0x100000), 1 << 40, None, C.byref(out)) == \
+        _lib.RCP_EINVAL
+    big = lib.rcp_factor_bytes(C.byref(g), 0)
+    assert lib.rcp_factor(C.byref(g), 0, C.c_void_p(0x100008), big, None, C.byref(out)) == \
+        _lib.RCP_EINVAL       # misaligned buffer
+    assert out.value is None
+
+
+def test_batch_rejects_mismatched_grids_on_host():
+    from paper_2207_10701_amd import _lib
+    lib = _lib.lib
+    grids = (_lib.Grid * 2)(grid(eps=0x1000), grid(nx=120, eps=0x1000))
+    bufs = (C.c_void_p * 2)(0x100000, 0x200000)
+    outs = (C.c_void_p * 2)()
+    rc = lib.rcp_factor_batch(2, grids, 0, bufs, 1 << 40, None, outs)
+    assert rc == _lib.RCP_EINVAL and b"identical" in lib.rcp_last_error()
+    rc = lib.rcp_factor_batch(5, grids, 0, bufs, 1 << 40, None, outs)
+    assert rc == _lib.RCP_EINVAL
+
+
+def test_null_handles_are_rejected():
+    from paper_2207_10701_amd import _lib
+    lib = _lib.lib
+    o = _lib.Objective()
+    lt = _lib.Light()
+    assert lib.rcp_reciprocal_average(None, C.byref(o), C.byref(lt), None, None, None, None) == \
+        _lib.RCP_EINVAL
+    assert lib.rcp_adjoint_grad(None, C.byref(o), C.byref(lt), None, None, None) == _lib.RCP_EINVAL
+    assert lib.rcp_solve_multi_rhs(None, 1, None, None, 0, 0.0, 0, None, None) == _lib.RCP_EINVAL
+    assert lib.rcp_brute_force_work_bytes(None, 10, 10) == 0

@@ -1,0 +1,106 @@
+"""Scheduling logic of the continuous-batching server, on the host (fake executor)."""
+import threading
+import time
+from dataclasses import replace
+
+import pytest
+
+import workloads as W
+from paper_2207_10701_amd.serve import FakeExecutor, Server, geometry_key, summarize
+
+
+def stream(n, **kw):
+    return W.serving_stream(n, rate=2000.0, seed=5001, scale=0.05, **kw)
+
+
+def test_all_requests_served_and_results_deterministic():
+    reqs = stream(24)
+    ex = FakeExecutor()
+    out = Server(ex, slots=3, hbm_budget=10 ** 12).run(reqs)
+    assert [r.rid for r in out] == [q.rid for q in reqs]
+    assert all(r.error is None for r in out)
+    alone = FakeExecutor()
+    for q, r in zip(reqs, out):
+        F, _ = alone.evaluate(None, q.problem, q.adjoint, None)
+        assert r.F == F
+    s = summarize(out)
+    assert s["ok"] == 24 and s["p99_ms"] >= s["p50_ms"] >= 0
+
+
+def test_slots_bound_concurrency_and_overlap():
+    reqs = stream(16)
+    srv = Server(FakeExecutor(factor_seconds=lambda p: 0.02), slots=4, hbm_budget=10 ** 12)
+    srv.run(reqs, realtime=False)
+    assert srv.max_inflight == 4
+
+
+def test_memory_budget_limits_inflight_and_rejects_oversized():
+    reqs = stream(12)
+    ex = FakeExecutor(factor_seconds=lambda p: 0.01)
+    biggest = max(ex.factor_bytes(r.problem) for r in reqs)
+    budget = int(biggest * 1.5)
+    srv = Server(ex, slots=8, hbm_budget=budget, cache=False)
+    out = srv.run(reqs, realtime=False)
+    assert all(r.error is None for r in out)
+    assert srv.peak_bytes <= budget
+    assert ex.peak_live <= budget
+    tiny = Server(FakeExecutor(), slots=2, hbm_budget=biggest // 2, cache=False)
+    out2 = tiny.run(reqs, realtime=False)
+    big = [r for r, q in zip(out2, reqs) if FakeExecutor().factor_bytes(q.problem) > biggest // 2]
+    assert big and all("budget" in r.error for r in big)
+    assert any(r.error is None for r in out2)
+
+
+def test_factor_cache_hits_and_eviction():
+    reqs = W.serving_stream(20, rate=2000.0, seed=7, scale=0.05, geometry_pool=3)
+    ex = FakeExecutor()
+    srv = Server(ex, slots=2, hbm_budget=10 ** 12)
+    out = srv.run(reqs, realtime=False)
+    keys = {geometry_key(q.problem) for q in reqs}
+    assert ex.factor_calls == len(keys)
+    assert sum(r.cache_hit for r in out) == len(reqs) - len(keys)
+    # a budget that holds one factor set at a time forces evictions but still serves all
+    one = max(ex.factor_bytes(q.problem) for q in reqs)
+    ex2 = FakeExecutor()
+    srv2 = Server(ex2, slots=1, hbm_budget=one)
+    out2 = srv2.run(reqs, realtime=False)
+    assert all(r.error is None for r in out2)
+    assert ex2.peak_live <= one
+
+
+def test_failed_request_does_not_poison_others():
+    reqs = stream(10)
+    bad = reqs[3].problem.name
+    ex = FakeExecutor(fail_on=lambda p: p.name == bad)
+    out = Server(ex, slots=3, hbm_budget=10 ** 12).run(reqs, realtime=False)
+    assert out[3].error is not None and "ESINGULAR" in out[3].error
+    assert all(r.error is None for i, r in enumerate(out) if i != 3)
+
+
+def test_cached_factors_are_not_shared_by_concurrent_requests():
+    p = W.small_problem(2, 4, seed=3)
+    reqs = [W.Request(rid=i, arrival=0.0, problem=p, adjoint=False) for i in range(6)]
+    users = {"now": 0, "max": 0}
+    lock = threading.Lock()
+
+    class Probe(FakeExecutor):
+        def evaluate(self, fac, p, adjoint, stream):
+            with lock:
+                users["now"] += 1
+                users["max"] = max(users["max"], users["now"])
+            time.sleep(0.005)
+            with lock:
+                users["now"] -= 1
+            return super().evaluate(fac, p, adjoint, stream)
+
+    out = Server(Probe(), slots=4, hbm_budget=10 ** 12).run(reqs, realtime=False)
+    assert all(r.error is None for r in out)
+    assert users["max"] == 1
+
+
+def test_realtime_replay_respects_arrivals():
+    reqs = [W.Request(rid=i, arrival=0.01 * i, problem=W.small_problem(2, 4, seed=i),
+                      adjoint=False) for i in range(5)]
+    out = Server(FakeExecutor(), slots=2, hbm_budget=10 ** 12).run(reqs)
+    for q, r in zip(reqs, out):
+        assert r.start >= q.arrival - 1e-3
