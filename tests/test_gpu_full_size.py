@@ -1,0 +1,111 @@
+"""GPU path at the benchmark configurations, against the oracle where it is
+affordable (config 1) and against properties that hold at any size (config 2)."""
+import math
+from functools import lru_cache
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import average as ora
+from oracle import light
+
+pytestmark = pytest.mark.gpu
+
+
+@lru_cache(maxsize=None)
+def config1_oracle():
+    p = W.config1()
+    s = ora.setup(p)
+    return p, s, ora.adjoint(s)
+
+
+def test_config1_fp64_and_refined_fp32(rcp):
+    p, s, ref = config1_oracle()
+    eps = rcp.eps_from_widths(p)
+    f64 = rcp.Factors(p, eps)
+    F, v, z = rcp.reciprocal_average(f64, p, want_v=True, want_z=True)
+    zr = ref.z
+    assert np.linalg.norm(z.cpu().numpy().ravel() - zr) / np.linalg.norm(zr) < 1e-10
+    assert abs(F.item() - ref.F) / ref.F < 1e-10
+    # Eq. 6 with 64 Gauss-Legendre nodes on the same factors equals Eq. 7 (converged)
+    Fb = rcp.brute_force_average(f64, 64, p, rhs_chunk=32)
+    assert abs(Fb.item() - ref.F) / ref.F < 1e-10
+    Fa, g = rcp.adjoint_grad(f64, p)
+    gd = g.cpu().numpy()
+    assert np.linalg.norm(gd - ref.grad_eps) / np.linalg.norm(ref.grad_eps) < 1e-9
+    gw = rcp.width_grad(p, g).cpu().numpy()
+    assert np.linalg.norm(gw - ref.grad_widths) / np.linalg.norm(ref.grad_widths) < 1e-9
+    f32 = rcp.Factors(p, eps, rcp.RCP_FP32_REFINED)
+    F32, z32 = rcp.reciprocal_average(f32, p, want_z=True)
+    assert np.linalg.norm(z32.cpu().numpy().ravel() - zr) / np.linalg.norm(zr) < 1e-8
+    assert abs(F32.item() - ref.F) / ref.F < 1e-6
+    F32a, g32 = rcp.adjoint_grad(f32, p)
+    assert np.linalg.norm(g32.cpu().numpy() - ref.grad_eps) / np.linalg.norm(ref.grad_eps) < 1e-5
+
+
+def test_config1_autograd_function(rcp):
+    import torch
+    p, s, ref = config1_oracle()
+    w = torch.tensor(p.widths, dtype=torch.float64, device="cuda", requires_grad=True)
+    F = rcp.IncoherentFOM.apply(w, p)
+    F.backward()
+    assert abs(F.item() - ref.F) / ref.F < 1e-10
+    gw = w.grad.cpu().numpy()
+    assert np.linalg.norm(gw - ref.grad_widths) / np.linalg.norm(ref.grad_widths) < 1e-9
+
+
+def test_symbol_table_light_matches_closed_form(rcp):
+    import torch
+    p = W.small_problem(4, 4, seed=7)
+    eps = rcp.eps_from_widths(p)
+    fac = rcp.Factors(p, eps)
+    F = rcp.reciprocal_average(fac, p).item()
+    M = p.m_aperture
+    d = (np.arange(-(M - 1), M) * p.h)
+    table = light.correlation_closed_form(p, d).astype(np.complex128)
+    Ft = rcp.reciprocal_average(fac, p, symbol=torch.from_numpy(table).cuda()).item()
+    assert abs(F - Ft) / F < 1e-12
+
+
+def test_singular_geometry_reports_esingular(rcp):
+    p = W.small_problem(3, 4, seed=3)
+    eps = rcp.eps_from_widths(p)
+    eps[p.nx // 2, p.ny // 2] = float("nan")
+    with pytest.raises(rcp.RecipError) as e:
+        rcp.Factors(p, eps)
+    assert e.value.code == -3 and "pivot" in str(e.value)
+
+
+def test_refinement_without_steps_reports_enoconv(rcp):
+    import torch
+    p = W.small_problem(3, 4, seed=3)
+    fac = rcp.Factors(p, rcp.eps_from_widths(p), rcp.RCP_FP32_REFINED)
+    b = torch.from_numpy(W.complex_normal((1, p.nx, p.ny), seed=4)).cuda()
+    with pytest.raises(rcp.RecipError) as e:
+        rcp.solve(fac, b, tol=1e-14, max_refine=0)
+    assert e.value.code == -4 and "residual" in str(e.value)
+    X, (it, res) = rcp.solve(fac, b, tol=1e-11, max_refine=8)
+    assert 1 <= it <= 8 and res <= 1e-11
+
+
+def test_config2_reciprocal_equals_converged_brute_force(rcp):
+    """Full benchmark size: Eq. 7 equals Eq. 6 once the quadrature resolves the
+    integrand (N > K c L / 2 = 164 nodes here), and the solve has a tiny residual."""
+    import torch
+    p = W.config2()
+    eps = rcp.eps_from_widths(p)
+    fac = rcp.Factors(p, eps)
+    F = rcp.reciprocal_average(fac, p).item()
+    Fb = rcp.brute_force_average(fac, 256, p, rhs_chunk=128).item()
+    assert abs(F - Fb) / F < 1e-10
+    K = p.n_source * 2 * math.pi
+    assert 256 > K * p.c * (p.m_aperture * p.h) / 2
+    b = torch.from_numpy(W.complex_normal((1, p.nx, p.ny), seed=21)).cuda()
+    X, (it, res) = rcp.solve(fac, b)
+    # computed through the refinement residual kernel (FP64 stencil)
+    fac2 = rcp.Factors(p, eps, rcp.RCP_FP32_REFINED)
+    X32, (it32, res32) = rcp.solve(fac2, b, tol=1e-12, max_refine=10)
+    assert res32 <= 1e-12
+    rel = (torch.linalg.vector_norm(X32 - X) / torch.linalg.vector_norm(X)).item()
+    assert rel < 1e-9
