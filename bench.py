@@ -60,7 +60,7 @@ def nominal_lu_flops(p):
     return 8.0 * p.ny ** 3 * p.nx
 
 
-def cpu_baseline(p_full, width_wl=10):
+def cpu_baseline(p_full, width_wl=40):
     """FP64 oracle (SuperLU + direct Toeplitz sum + adjoint) on a width slice, scaled by width."""
     from dataclasses import replace
 
@@ -88,7 +88,8 @@ def cpu_baseline(p_full, width_wl=10):
     return {"value": scale / t, "unit": "evals/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle factor + reciprocal + adjoint on a {width_wl}-wavelength-wide "
                       f"slice ({ps.nx}x{ps.ny} cells) of the same depth, {t:.1f} s, "
-                      f"scaled by width x{scale:.4f} (SuperLU, 1 thread)",
+                      f"scaled by width x{scale:.4f} (SuperLU/COLAMD, BLAS limited to 1 thread; "
+                      f"SuperLU cost grows faster than width, so this favours the CPU)",
             "sample_seconds": t, "sample_F": g.F}
 
 

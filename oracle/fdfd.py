@@ -135,8 +135,9 @@ def operator(p: Problem, eps=None) -> sp.csc_matrix:
 
 
 def factor(A: sp.spmatrix):
-    """SuperLU factorisation of A (fill-reducing ordering for symmetric structure)."""
-    return spla.splu(sp.csc_matrix(A), permc_spec="MMD_AT_PLUS_A")
+    """SuperLU factorisation of A with partial pivoting and a COLAMD column ordering
+    (the minimum-degree ordering of A + A^T fills these tall grids far more)."""
+    return spla.splu(sp.csc_matrix(A), permc_spec="COLAMD")
 
 
 def point_source(p: Problem, i: int, j: int) -> np.ndarray:

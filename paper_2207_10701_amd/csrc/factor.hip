@@ -515,17 +515,29 @@ __global__ __launch_bounds__(256) void k_gj_update(GJJobs jobs, size_t tiles) {
   update_work<T>(jb, wg, tiles, -1);
 }
 
-// Update k outside column k+1, plus the look-ahead panel k+1.
+// Update k outside column k+1, plus the look-ahead panel k+1.  The look-ahead
+// workgroups of every job come first in the grid so that they are dispatched
+// first: they carry the launch's critical path.
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_gj_fused(GJJobs jobs, int nt, size_t tiles) {
   __shared__ double2 Ps[TB][TB + 1];
   __shared__ double2 xrow[4][TB], xcol[4][TB];
-  int wg = blockIdx.x;
-  GJJob jb = pick(jobs, &wg);
-  if (wg < jb.wgs_upd)
-    update_work<T>(jb, wg, tiles, jb.k + 1);
-  else
-    lookahead_work<T>(jb, wg - jb.wgs_upd, nt, Ps, xrow, xcol);
+  const int look = jobs.j[0].wgs - jobs.j[0].wgs_upd;   // look-ahead workgroups per job
+  const int upd = jobs.j[0].wgs_upd;
+  int w = blockIdx.x;
+  if (w < jobs.n * look) {
+    const int q = w / look;
+    const int g = w - q * look;
+    int tmp = q * jobs.j[0].wgs;          // position of job q in pick()'s numbering
+    GJJob jb = pick(jobs, &tmp);
+    lookahead_work<T>(jb, g, nt, Ps, xrow, xcol);
+  } else {
+    w -= jobs.n * look;
+    const int q = w / upd;
+    int tmp = q * jobs.j[0].wgs + (w - q * upd);
+    GJJob jb = pick(jobs, &tmp);
+    update_work<T>(jb, tmp, tiles, jb.k + 1);
+  }
 }
 
 // dst = D - C1 src1 C1 - C2 src2 C2 on packed tiles (src may be null), with

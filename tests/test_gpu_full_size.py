@@ -109,3 +109,20 @@ def test_config2_reciprocal_equals_converged_brute_force(rcp):
     assert res32 <= 1e-12
     rel = (torch.linalg.vector_norm(X32 - X) / torch.linalg.vector_norm(X)).item()
     assert rel < 1e-9
+
+
+@pytest.mark.timeout(900)
+def test_config2_matches_oracle_at_full_size(rcp):
+    """Benchmark size (2040 x 1080): GPU reciprocal field, F and adjoint against the
+    FP64 oracle (SuperLU, ~75 s on one core)."""
+    p = W.config2()
+    eps = rcp.eps_from_widths(p)
+    fac = rcp.Factors(p, eps)
+    F, z = rcp.reciprocal_average(fac, p, want_z=True)
+    Fa, g = rcp.adjoint_grad(fac, p)
+    zg = z.cpu().numpy().ravel()
+    gg = g.cpu().numpy()
+    ref = ora.adjoint(ora.setup(p))
+    assert np.linalg.norm(zg - ref.z) / np.linalg.norm(ref.z) < 1e-10
+    assert abs(F.item() - ref.F) / ref.F < 1e-10
+    assert np.linalg.norm(gg - ref.grad_eps) / np.linalg.norm(ref.grad_eps) < 1e-9
