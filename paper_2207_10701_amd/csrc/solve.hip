@@ -40,24 +40,51 @@ __device__ __forceinline__ double2 maybe_conj(double2 a, int c) {
   return c ? make_double2(a.x, -a.y) : a;
 }
 
-// One 1024-thread workgroup per (job, half of a 32-row strip): 16 output rows.
-// Lane l accumulates output row o = l % 16 of the half over 8 of the 32 inner
-// indices of each tile (q = l / 16 picks which 8); the 16 waves take the tiles
-// J of the strip round robin.  Stored tiles (I, J <= I) are read along rows,
-// tiles (J > I, I) along columns (their transpose).  Partial sums are combined
-// in a fixed order, so the result does not depend on scheduling.
-template <typename T>
-__global__ __launch_bounds__(1024) void k_gemv(SvJobs jobs, int nt, int ny, int conjop) {
+// One 512-thread workgroup per (job, 8-row quarter of a 32-row strip), so a
+// block is spread over 4 * nt workgroups.  Wave w takes the tiles J = w + 8u
+// of the strip.  Every load instruction of a wave reads whole cache lines:
+//   stored tile (I, J <= I): its rows r0 .. r0+7 are 4 KB contiguous; lane l
+//     of load c holds row 2c + l/32, column l%32, and keeps a partial sum per
+//     c (reduced over the 32 lanes of equal l/32 at the end);
+//   tile (J > I, I), used transposed: columns r0 .. r0+7 of each of its 32
+//     rows (128 B each); lane l of load c holds row 8c + l/8, column r0 + l%8,
+//     and keeps one partial sum for output row l%8 (reduced over l/8).
+// All tile loads are issued before the input vector is formed in LDS, so one
+// memory latency covers the step.  Partial sums are combined in a fixed
+// order: the result does not depend on scheduling.
+// MT = tiles per wave = ceil(nt / 8) (nt <= 64, np <= 2048).
+template <typename T, int MT>
+__global__ __launch_bounds__(512) void k_gemv(SvJobs jobs, int nt, int ny, int conjop) {
   using T2 = typename cplx<T>::t;
   __shared__ double2 g[NPMAX];
-  __shared__ double2 red[16][16];
-  const int ji = blockIdx.x / (2 * nt), rem = blockIdx.x % (2 * nt);
-  const int I = rem >> 1, half = rem & 1;
+  __shared__ double2 redd[8][8];
+  __shared__ double2 redt[8][8];
+  const int per_job = 4 * nt;
+  const int ji = blockIdx.x / per_job, rem = blockIdx.x % per_job;
+  const int I = rem >> 2, r0 = (rem & 3) * 8;
   SvJob jb = jobs.j[0];
   if (ji == 1) jb = jobs.j[1];
   const int tid = threadIdx.x;
+  const T2* X = static_cast<const T2*>(jb.X);
+  const int wave = tid >> 6, lane = tid & 63;
+  T2 x[MT][4];
+#pragma unroll
+  for (int u = 0; u < MT; ++u) {
+    const int J = wave + 8 * u;
+    if (J < nt) {
+      if (J <= I) {
+        const T2* t = X + tile_index(I, J) * TB * TB + r0 * TB + lane;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x[u][c] = t[c * 64];
+      } else {
+        const T2* t = X + tile_index(J, I) * TB * TB + (lane >> 3) * TB + r0 + (lane & 7);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x[u][c] = t[c * 8 * TB];
+      }
+    }
+  }
   const int np = nt * TB;
-  for (int k = tid; k < np; k += 1024) {
+  for (int k = tid; k < np; k += 512) {
     double2 v = make_double2(0.0, 0.0);
     if (k < ny) {
       if (jb.f) v = jb.f[k];
@@ -67,41 +94,55 @@ __global__ __launch_bounds__(1024) void k_gemv(SvJobs jobs, int nt, int ny, int 
     g[k] = v;
   }
   __syncthreads();
-  const T2* X = static_cast<const T2*>(jb.X);
-  const int wave = tid >> 6, lane = tid & 63;
-  const int o = lane & 15, q = lane >> 4;
-  const int oi = half * 16 + o;          // row (or column) inside the 32-wide strip
   const double cs_im = conjop ? -1.0 : 1.0;
-  double2 acc = make_double2(0.0, 0.0);
-  for (int J = wave; J < nt; J += 16) {
-    T2 x[8];
-    if (J <= I) {
-      const T2* t = X + tile_index(I, J) * TB * TB + oi * TB + 8 * q;
+  double2 accd[4], acct = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int c = 0; c < 8; ++c) x[c] = t[c];
-    } else {
-      const T2* t = X + tile_index(J, I) * TB * TB + (8 * q) * TB + oi;
+  for (int c = 0; c < 4; ++c) accd[c] = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int c = 0; c < 8; ++c) x[c] = t[c * TB];
-    }
-    const double2* gg = g + J * TB + 8 * q;
+  for (int u = 0; u < MT; ++u) {
+    const int J = wave + 8 * u;
+    if (J < nt) {
+      if (J <= I) {
+        const double2 gv = g[J * TB + (lane & 31)];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      double2 xv = to_c128(x[c]);
-      xv.y *= cs_im;
-      acc = cadd(acc, cmul(xv, gg[c]));
+        for (int c = 0; c < 4; ++c) {
+          double2 xv = to_c128(x[u][c]);
+          xv.y *= cs_im;
+          accd[c] = cadd(accd[c], cmul(xv, gv));
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          double2 xv = to_c128(x[u][c]);
+          xv.y *= cs_im;
+          acct = cadd(acct, cmul(xv, g[J * TB + 8 * c + (lane >> 3)]));
+        }
+      }
     }
   }
-  acc.x += __shfl_xor(acc.x, 16, 64);
-  acc.y += __shfl_xor(acc.y, 16, 64);
-  acc.x += __shfl_xor(acc.x, 32, 64);
-  acc.y += __shfl_xor(acc.y, 32, 64);
-  if (lane < 16) red[wave][lane] = acc;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+      accd[c].x += __shfl_xor(accd[c].x, d, 64);
+      accd[c].y += __shfl_xor(accd[c].y, d, 64);
+    }
+  }
+#pragma unroll
+  for (int d = 8; d < 64; d <<= 1) {
+    acct.x += __shfl_xor(acct.x, d, 64);
+    acct.y += __shfl_xor(acct.y, d, 64);
+  }
+  if ((lane & 31) == 0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) redd[wave][2 * c + (lane >> 5)] = accd[c];
+  }
+  if (lane < 8) redt[wave][lane] = acct;
   __syncthreads();
-  if (tid < 16) {
-    double2 sum = red[0][tid];
-    for (int w = 1; w < 16; ++w) sum = cadd(sum, red[w][tid]);
-    const int row = I * TB + half * 16 + tid;
+  if (tid < 8) {
+    double2 sum = make_double2(0.0, 0.0);
+    for (int w = 0; w < 8; ++w) sum = cadd(sum, cadd(redd[w][tid], redt[w][tid]));
+    const int row = I * TB + r0 + tid;
     if (row < ny) {
       double2 b = jb.base ? jb.base[row] : make_double2(0.0, 0.0);
       jb.out[row] = cadd(b, sum);
@@ -317,7 +358,17 @@ int run_solve_vec(rcp_factors* f, const double2* rhs, double2* u, int conjop, in
   auto launch = [&](SvJobs& js) -> int {
     if (js.n == 0) return RCP_OK;
     KTimer kt(K_GEMV, s, double(js.n) * f->tiles * TB * TB * sizeof(typename cplx<T>::t));
-    k_gemv<T><<<2 * nt * js.n, 1024, 0, s>>>(js, nt, ny, conjop);
+    const dim3 grid(4 * nt * js.n);
+    switch ((nt + 7) / 8) {
+      case 1: k_gemv<T, 1><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+      case 2: k_gemv<T, 2><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+      case 3: k_gemv<T, 3><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+      case 4: k_gemv<T, 4><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+      case 5: k_gemv<T, 5><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+      case 6: k_gemv<T, 6><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+      case 7: k_gemv<T, 7><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+      default: k_gemv<T, 8><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+    }
     RCP_HIP(hipGetLastError());
     return RCP_OK;
   };

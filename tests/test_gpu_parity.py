@@ -41,6 +41,9 @@ PROBLEMS = {
     "coll_annulus": W.small_problem(5, 4, seed=8, objective=W.COLLIMATOR, light=W.ANNULUS,
                                     th1_deg=6.0, th2_deg=25.0, monitor_y=3.0, phi=0.1),
     "conc_odd": W.small_problem(3, 5, seed=9, npml=8, c_deg=30.0),
+    # 276 rows: nine 32-row tiles with a ragged last one, so each wave of the
+    # vector sweep takes two tiles
+    "conc_tall": W.small_problem(2, 13, seed=10, npml=8, focus_height=9.0),
 }
 
 
