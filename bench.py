@@ -1,10 +1,11 @@
 """Benchmark of the reciprocal incoherent-light average on one MI355X.
 
-One step = one inverse-design evaluation of a fresh seeded geometry: pillar
-widths -> permittivity map -> FDFD assembly -> twisted block factorisation ->
+One step = one inverse-design evaluation of each of B fresh seeded geometries
+(B = 4 by default, factored side by side in the same launches): pillar widths
+-> permittivity map -> FDFD assembly -> twisted block factorisation ->
 reciprocal solve -> Toeplitz/FFT form F = v^dag W v -> adjoint solve ->
 dF/deps -> dF/dwidths, all in librecip's HIP kernels, inputs already on the
-device.  value = evaluations per second.
+device.  value = evaluations per second (B per step).
 
 Beside it, on the factors of the last step: the reciprocal average with cached
 factors, the 1000-node Gauss-Legendre brute force it replaces (the same
@@ -53,6 +54,43 @@ DESCR = {
     "config4_large": "concentrator 100x20 wavelengths (2040x440 cells), 100 seeded pillars, "
                      "cone +-10 deg",
 }
+
+
+# HBM traffic of the dominant kernel, k_gj_fused<double>, per launch, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) over one default step
+# (config2, four geometries per step), scaled by what the same counters read for
+# a 1 GiB copy (python bench.py --calibrate-copy).  Valid only for the kernel
+# source it was measured on: reported when factor.hip still has this hash.
+TRAFFIC = None
+
+
+def factor_source_sha256():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2207_10701_amd", "csrc", "factor.hip")
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic(config, batch):
+    """Bytes per launch of k_gj_fused<double> if measured on this source and workload."""
+    t = TRAFFIC
+    if t is None or t["config"] != config or t["batch"] != batch:
+        return None
+    if t["sha256"] != factor_source_sha256():
+        return None
+    return t["fetch_bytes"] + t["write_bytes"]
+
+
+def calibrate_copy():
+    """A plain 1 GiB device copy, three times: the reference for FETCH_SIZE/WRITE_SIZE."""
+    import torch
+    n = 1 << 30
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": n, "copies": 3}), flush=True)
 
 
 def nominal_lu_flops(p):
@@ -135,9 +173,14 @@ def main():
                     help="requests in the serving measurement (0 = skip)")
     ap.add_argument("--serve-scale", type=float, default=0.25,
                     help="width/depth scale of the serving mix (1 = widths 20-300, depths 10-60)")
-    ap.add_argument("--batch", type=int, default=1,
+    ap.add_argument("--batch", type=int, default=4,
                     help="geometries factored side by side per step (1-4)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy (reference for the HBM counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU; the reciprocal solve of one "
@@ -206,9 +249,10 @@ def main():
 
     upd = kstats["gj_update"]
     achieved = upd["work"] / (upd["ms"] * 1e-3) / 1e12 if upd["ms"] > 0 else 0.0
-    roofline = {"bound": "mfma", "kernel": "k_gj_update<double>", "achieved": round(achieved, 3),
+    roofline = {"bound": "mfma", "kernel": "k_gj_fused<double>", "achieved": round(achieved, 3),
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(args.config, B),
                 "avg_launch_us": round(1e3 * upd["ms"] / max(upd["samples"], 1), 3),
                 "flops_per_launch": upd["work"] / max(upd["samples"], 1)}
     kernels = {}
@@ -244,6 +288,21 @@ def main():
         t_fac = a.elapsed_time(b) * 1e-3
         out["lu_seconds"] = round(t_fac, 5)
         out["lu_tflops_nominal"] = round(nominal_lu_flops(p) / t_fac / 1e12, 3)
+        if B > 1:   # the same B geometries factored side by side, as in the step
+            eps_b = [rcp.eps_from_widths(p, w, device=dev) for w in widths[-B:]]
+            del fac
+            torch.cuda.synchronize()
+            a.record(stream)
+            facs_b = rcp.factor_batch([p] * B, eps_b, rcp.RCP_FP64, buffers=bufs)
+            b.record(stream)
+            torch.cuda.synchronize()
+            t_b = a.elapsed_time(b) * 1e-3
+            out["lu_batch"] = {"geometries": B, "seconds": round(t_b, 5),
+                               "tflops_nominal": round(B * nominal_lu_flops(p) / t_b / 1e12, 3)}
+            log(f"batched factor x{B}: {t_b * 1e3:.1f} ms "
+                f"({out['lu_batch']['tflops_nominal']} TF/s nominal)")
+            fac = facs_b[-1]      # geometry widths[-1] again, now in bufs[-1]
+            del facs_b
         # reciprocal average on cached factors
         reps = 10
         Fr = rcp.reciprocal_average(fac, p)

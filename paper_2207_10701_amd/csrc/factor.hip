@@ -498,11 +498,33 @@ __device__ void lookahead_work(const GJJob& jb, int I, int nt, double2 (*Ps)[TB 
   }
 }
 
+// Workgroup -> (job q, index w within the job).  When the job count divides 8,
+// job q gets the XCDs x with x % n == q (workgroups are dealt to the 8 XCDs
+// round robin), so the panel buffers a chain's workgroups all read stay in the
+// L2 of its own XCDs; the grid is then padded to a multiple of 8 (grid_size)
+// and the surplus workgroups return false.
+__device__ __forceinline__ bool job_of(int n, int per, int* q, int* w) {
+  const int b = blockIdx.x;
+  if (8 % n == 0) {
+    const int x = b & 7, slot = b >> 3;
+    *q = x % n;
+    *w = slot * (8 / n) + x / n;
+  } else {
+    *q = b / per;
+    *w = b - *q * per;
+  }
+  return *w < per;
+}
+
+int grid_size(int n, int per) { return 8 % n == 0 ? 8 * ceil_div(n * per, 8) : n * per; }
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj_panel(GJJobs jobs, int nt) {
   __shared__ double2 Ps[TB][TB + 1];
   __shared__ double2 xrow[4][TB], xcol[4][TB];
-  int wg = blockIdx.x;
+  int q, w;
+  if (!job_of(jobs.n, jobs.j[0].wgs, &q, &w)) return;
+  int wg = q * jobs.j[0].wgs + w;
   GJJob jb = pick(jobs, &wg);
   panel_work<T>(jb, wg, nt, Ps, xrow, xcol);
 }
@@ -510,34 +532,29 @@ __global__ __launch_bounds__(256) void k_gj_panel(GJJobs jobs, int nt) {
 // Update k (all tiles; negated when last) -- the final panel of a block.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj_update(GJJobs jobs, size_t tiles) {
-  int wg = blockIdx.x;
+  int q, w;
+  if (!job_of(jobs.n, jobs.j[0].wgs, &q, &w)) return;
+  int wg = q * jobs.j[0].wgs + w;
   GJJob jb = pick(jobs, &wg);
   update_work<T>(jb, wg, tiles, -1);
 }
 
-// Update k outside column k+1, plus the look-ahead panel k+1.  The look-ahead
-// workgroups of every job come first in the grid so that they are dispatched
-// first: they carry the launch's critical path.
+// Update k outside column k+1, plus the look-ahead panel k+1.  Within each job
+// the look-ahead workgroups come first, so that they are dispatched first:
+// they carry the launch's critical path.
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_gj_fused(GJJobs jobs, int nt, size_t tiles) {
   __shared__ double2 Ps[TB][TB + 1];
   __shared__ double2 xrow[4][TB], xcol[4][TB];
   const int look = jobs.j[0].wgs - jobs.j[0].wgs_upd;   // look-ahead workgroups per job
-  const int upd = jobs.j[0].wgs_upd;
-  int w = blockIdx.x;
-  if (w < jobs.n * look) {
-    const int q = w / look;
-    const int g = w - q * look;
-    int tmp = q * jobs.j[0].wgs;          // position of job q in pick()'s numbering
-    GJJob jb = pick(jobs, &tmp);
-    lookahead_work<T>(jb, g, nt, Ps, xrow, xcol);
-  } else {
-    w -= jobs.n * look;
-    const int q = w / upd;
-    int tmp = q * jobs.j[0].wgs + (w - q * upd);
-    GJJob jb = pick(jobs, &tmp);
-    update_work<T>(jb, tmp, tiles, jb.k + 1);
-  }
+  int q, w;
+  if (!job_of(jobs.n, jobs.j[0].wgs, &q, &w)) return;
+  int tmp = q * jobs.j[0].wgs + w;
+  GJJob jb = pick(jobs, &tmp);
+  if (w < look)
+    lookahead_work<T>(jb, w, nt, Ps, xrow, xcol);
+  else
+    update_work<T>(jb, w - look, tiles, jb.k + 1);
 }
 
 // dst = D - C1 src1 C1 - C2 src2 C2 on packed tiles (src may be null), with
@@ -648,7 +665,7 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s) {
         js.j[js.n++] = b;
       }
       KTimer kt(K_GJ_PANEL, s, nch * cmac * nt);
-      k_gj_panel<T><<<nch * pan_wgs, 256, 0, s>>>(js, nt);
+      k_gj_panel<T><<<grid_size(nch, pan_wgs), 256, 0, s>>>(js, nt);
       RCP_HIP(hipGetLastError());
     }
     for (int k = 0; k + 1 < nt; ++k) {
@@ -660,7 +677,7 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s) {
         js.j[js.n++] = b;
       }
       KTimer kt(K_GJ_UPDATE, s, nch * cmac * double(tiles));
-      k_gj_fused<T><<<nch * (upd_wgs + look_wgs), 256, 0, s>>>(js, nt, tiles);
+      k_gj_fused<T><<<grid_size(nch, upd_wgs + look_wgs), 256, 0, s>>>(js, nt, tiles);
       RCP_HIP(hipGetLastError());
     }
     {   // final update, negated
@@ -673,7 +690,7 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s) {
         js.j[js.n++] = b;
       }
       KTimer kt(K_GJ_LAST, s, nch * cmac * double(tiles - nt));
-      k_gj_update<T><<<nch * upd_wgs, 256, 0, s>>>(js, tiles);
+      k_gj_update<T><<<grid_size(nch, upd_wgs), 256, 0, s>>>(js, tiles);
       RCP_HIP(hipGetLastError());
     }
     return RCP_OK;
