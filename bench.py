@@ -61,7 +61,10 @@ DESCR = {
 # (config2, four geometries per step), scaled by what the same counters read for
 # a 1 GiB copy (python bench.py --calibrate-copy).  Valid only for the kernel
 # source it was measured on: reported when factor.hip still has this hash.
-TRAFFIC = None
+TRAFFIC = {"config": "config2", "batch": 4,
+           "sha256": "e5bb5561e49aeba51d9a453bf21cf3a041130a48489e73f88406a3889a5fb329",
+           "fetch_bytes": 87497373,     # 42724.5 KiB FETCH_SIZE x 1.99995
+           "write_bytes": 82313523}     # 80384.3 KiB WRITE_SIZE x 1.0
 
 
 def factor_source_sha256():
@@ -98,7 +101,7 @@ def nominal_lu_flops(p):
     return 8.0 * p.ny ** 3 * p.nx
 
 
-def cpu_baseline(p_full, width_wl=40):
+def cpu_baseline(p_full, width_wl=48):
     """FP64 oracle (SuperLU + direct Toeplitz sum + adjoint) on a width slice, scaled by width."""
     from dataclasses import replace
 
