@@ -207,6 +207,90 @@ __device__ __forceinline__ void tile_nt_update(typename v4of<T>::t (*cre)[2],
   }
 }
 
+// Trailing-update product of one tile, pipelined: acc = S - A B^T with the
+// loads of S issued first (they arrive while the products run) and the
+// operands A, B (32 x 32 row-major) fetched in four chunks of two k-steps,
+// chunk c+1 in flight while chunk c multiplies into zeroed accumulators.
+template <typename T2>
+__device__ __forceinline__ void load_ksteps(T2 (&av)[2][2], T2 (&bv)[2][2], const T2* A,
+                                            const T2* B, int ch, int lr, int lk) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      av[x][s] = A[(16 * x + lr) * TB + 8 * ch + 4 * s + lk];
+      bv[x][s] = B[(16 * x + lr) * TB + 8 * ch + 4 * s + lk];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void mma_ksteps(typename v4of<T>::t (*cre)[2],
+                                           typename v4of<T>::t (*cim)[2],
+                                           const typename cplx<T>::t (&av)[2][2],
+                                           const typename cplx<T>::t (&bv)[2][2]) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const T nare = -av[a][s].x, aim = av[a][s].y, naim = -av[a][s].y;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cre[a][b] = mfma16(nare, bv[b][s].x, cre[a][b]);
+        cim[a][b] = mfma16(nare, bv[b][s].y, cim[a][b]);
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cre[a][b] = mfma16(aim, bv[b][s].y, cre[a][b]);
+        cim[a][b] = mfma16(naim, bv[b][s].x, cim[a][b]);
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_update_pipelined(typename cplx<T>::t* dst,
+                                                      const typename cplx<T>::t* A,
+                                                      const typename cplx<T>::t* B, T sg,
+                                                      int lr, int lk) {
+  using T2 = typename cplx<T>::t;
+  using V4 = typename v4of<T>::t;
+  T2 sv[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sv[a][b][q] = dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr];
+  V4 cre[2][2], cim[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cre[a][b] = V4{0, 0, 0, 0};
+      cim[a][b] = V4{0, 0, 0, 0};
+    }
+  T2 a0[2][2], b0[2][2], a1[2][2], b1[2][2];
+  load_ksteps(a0, b0, A, B, 0, lr, lk);
+  load_ksteps(a1, b1, A, B, 1, lr, lk);
+  mma_ksteps<T>(cre, cim, a0, b0);
+  load_ksteps(a0, b0, A, B, 2, lr, lk);
+  mma_ksteps<T>(cre, cim, a1, b1);
+  load_ksteps(a1, b1, A, B, 3, lr, lk);
+  mma_ksteps<T>(cre, cim, a0, b0);
+  mma_ksteps<T>(cre, cim, a1, b1);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        T2 v;
+        v.x = (sv[a][b][q].x + cre[a][b][q]) * sg;
+        v.y = (sv[a][b][q].y + cim[a][b][q]) * sg;
+        dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr] = v;
+      }
+}
+
 // Load a stored tile into accumulators, transposed if tr (acc(i, j) = S(j, i)).
 template <typename T>
 __device__ __forceinline__ void tile_load_acc(typename v4of<T>::t (*cre)[2],
@@ -375,16 +459,13 @@ __device__ void update_work(const GJJob& jb, int wg, size_t tiles, int skip) {
     return;
   }
   const int lr = lane & 15, lk = lane >> 4;
-  V4 cre[2][2], cim[2][2];
-  tile_load_acc<T>(cre, cim, dst, false, lr, lk);
-  tile_nt_update<T>(cre, cim, Q + size_t(I) * TB * TB, L + size_t(J) * TB * TB, lr, lk, 0, 2, 0, 2);
-  tile_store_acc<T>(cre, cim, dst, sg, lr, lk);
+  tile_update_pipelined<T>(dst, Q + size_t(I) * TB * TB, L + size_t(J) * TB * TB, sg, lr, lk);
 }
 
 // Look-ahead for panel Kn = k + 1, one workgroup per row tile I, one wave per
 // 16 x 16 quadrant (qa, qb):
-//  1. the two 16 x 16 blocks (a', qa), a' = 0, 1, of L_{Kn}[I]^T after update k,
-//     in accumulator layout:
+//  1. the two 16 x 16 blocks (a', qa), a' = 0, 1, of L_{Kn}[I]^T
+//     after update k, in accumulator layout:
 //       I >  Kn: S(I,Kn)^T - L_k[Kn] Q_k[I]^T
 //       I <  Kn, I != k: S(Kn,I) - Q_k[Kn] L_k[I]^T
 //       I == k: Q_k[Kn]                  (tile (Kn, k) lies in pivot column k)
@@ -394,6 +475,87 @@ __device__ void update_work(const GJJob& jb, int wg, size_t tiles, int skip) {
 //     into LDS; 3. invert it (all waves); 4. quadrant (qa, qb) of
 //     Q_{Kn}[I] = L_{Kn}[I] P.
 template <typename T>
+__device__ __forceinline__ void lt_row(const GJJob& jb, int I, typename v4of<T>::t (*cre)[2],
+                                       typename v4of<T>::t (*cim)[2], int lr, int lk, int qa,
+                                       int qb) {
+  using T2 = typename cplx<T>::t;
+  const T2* X = static_cast<const T2*>(jb.X);
+  const T2* Q = static_cast<const T2*>(jb.Q);
+  const T2* L = static_cast<const T2*>(jb.L);
+  const int k = jb.k, Kn = k + 1;
+  // accumulator init: element (i, j) of block (a', qa) of L^T
+  const T2* src;
+  bool tr;
+  if (I == k) {
+    src = Q + size_t(Kn) * TB * TB;
+    tr = false;
+  } else if (I > Kn) {
+    src = X + tile_index(I, Kn) * TB * TB;
+    tr = true;
+  } else {
+    src = X + tile_index(Kn, I) * TB * TB;
+    tr = false;
+  }
+#pragma unroll
+  for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 16 * a2 + mfma_row<T>(lk, q), j = 16 * qa + lr;
+      T2 v = tr ? src[j * TB + i] : src[i * TB + j];
+      cre[a2][0][q] = v.x;
+      cim[a2][0][q] = v.y;
+    }
+  if (I > Kn)
+    tile_nt_update<T>(cre, cim, L + size_t(Kn) * TB * TB, Q + size_t(I) * TB * TB + 16 * qa * TB,
+                      lr, lk, 0, 2, 0, 1);
+  else if (I != k)
+    tile_nt_update<T>(cre, cim, Q + size_t(Kn) * TB * TB, L + size_t(I) * TB * TB + 16 * qa * TB,
+                      lr, lk, 0, 2, 0, 1);
+  if (qb == 0) {   // rows 16 qa .. of L_{Kn}[I] for the update of panel Kn
+    T2* Lb = static_cast<T2*>(jb.Ln) + size_t(I) * TB * TB;
+#pragma unroll
+    for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        T2 v;
+        v.x = cre[a2][0][q];
+        v.y = cim[a2][0][q];
+        Lb[(16 * qa + lr) * TB + 16 * a2 + mfma_row<T>(lk, q)] = v;
+      }
+  }
+}
+
+// Quadrant (qa, qb) of Q_{Kn}[I]: A fragments (row 16 qa + lr, k-step 4 a' + q)
+// come from the L^T accumulators, B fragments from P with the matching k index.
+template <typename T>
+__device__ __forceinline__ void q_row(const GJJob& jb, int I, const typename v4of<T>::t (*cre)[2],
+                                      const typename v4of<T>::t (*cim)[2], double2 (*Ps)[TB + 1],
+                                      int lr, int lk, int qa, int qb) {
+  using T2 = typename cplx<T>::t;
+  using V4 = typename v4of<T>::t;
+  V4 qre = V4{0, 0, 0, 0}, qim = V4{0, 0, 0, 0};
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int kk = acc_k<T>(s, lk);
+    const double2 pv = Ps[kk][16 * qb + lr];
+    const T bre = static_cast<T>(pv.x), bim = static_cast<T>(pv.y);
+    const T are = cre[s >> 2][0][s & 3], aim = cim[s >> 2][0][s & 3];
+    qre = mfma16(are, bre, qre);
+    qim = mfma16(are, bim, qim);
+    qre = mfma16(-aim, bim, qre);
+    qim = mfma16(aim, bre, qim);
+  }
+  T2* Qb = static_cast<T2*>(jb.Qn) + size_t(I) * TB * TB + (16 * qa) * TB + 16 * qb;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    T2 v;
+    v.x = qre[q];
+    v.y = qim[q];
+    Qb[mfma_row<T>(lk, q) * TB + lr] = v;
+  }
+}
+
+template <typename T>
 __device__ void lookahead_work(const GJJob& jb, int I, int nt, double2 (*Ps)[TB + 1],
                                double2 (*xrow)[TB], double2 (*xcol)[TB]) {
   using T2 = typename cplx<T>::t;
@@ -401,54 +563,13 @@ __device__ void lookahead_work(const GJJob& jb, int I, int nt, double2 (*Ps)[TB 
   const T2* X = static_cast<const T2*>(jb.X);
   const T2* Q = static_cast<const T2*>(jb.Q);
   const T2* L = static_cast<const T2*>(jb.L);
-  const int k = jb.k, Kn = k + 1;
+  const int Kn = jb.k + 1;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 15, lk = lane >> 4;
   const int qa = wave >> 1, qb = wave & 1;
   const bool active = I < nt && I != Kn;
   V4 cre[2][2], cim[2][2];   // [a'][0] used
-  if (active) {
-    // accumulator init: element (i, j) of block (a', qa) of L^T
-    const T2* src;
-    bool tr;
-    if (I == k) {
-      src = Q + size_t(Kn) * TB * TB;
-      tr = false;
-    } else if (I > Kn) {
-      src = X + tile_index(I, Kn) * TB * TB;
-      tr = true;
-    } else {
-      src = X + tile_index(Kn, I) * TB * TB;
-      tr = false;
-    }
-#pragma unroll
-    for (int a2 = 0; a2 < 2; ++a2)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = 16 * a2 + mfma_row<T>(lk, q), j = 16 * qa + lr;
-        T2 v = tr ? src[j * TB + i] : src[i * TB + j];
-        cre[a2][0][q] = v.x;
-        cim[a2][0][q] = v.y;
-      }
-    if (I > Kn)
-      tile_nt_update<T>(cre, cim, L + size_t(Kn) * TB * TB, Q + size_t(I) * TB * TB + 16 * qa * TB,
-                        lr, lk, 0, 2, 0, 1);
-    else if (I != k)
-      tile_nt_update<T>(cre, cim, Q + size_t(Kn) * TB * TB, L + size_t(I) * TB * TB + 16 * qa * TB,
-                        lr, lk, 0, 2, 0, 1);
-    if (qb == 0) {   // rows 16 qa .. of L_{Kn}[I] for the update of panel Kn
-      T2* Lb = static_cast<T2*>(jb.Ln) + size_t(I) * TB * TB;
-#pragma unroll
-      for (int a2 = 0; a2 < 2; ++a2)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          T2 v;
-          v.x = cre[a2][0][q];
-          v.y = cim[a2][0][q];
-          Lb[(16 * qa + lr) * TB + 16 * a2 + mfma_row<T>(lk, q)] = v;
-        }
-    }
-  }
+  if (active) lt_row<T>(jb, I, cre, cim, lr, lk, qa, qb);
   {  // quadrant (qa, qb) of the updated pivot block
     V4 dre[2][2], dim[2][2];
     const T2* S = X + tile_index(Kn, Kn) * TB * TB + (16 * qa) * TB + 16 * qb;
@@ -471,31 +592,7 @@ __device__ void lookahead_work(const GJJob& jb, int I, int nt, double2 (*Ps)[TB 
     for (int e = tid; e < TB * TB; e += 256) jb.Pn[e] = Ps[e / TB][e % TB];
     if (tid == 0) *jb.health = minpiv;
   }
-  if (!active) return;
-  // Q quadrant (qa, qb): A fragments (row 16 qa + lr, k-step 4 a' + q) come from
-  // the L^T accumulators, B fragments from P with the matching k index
-  V4 qre[2][2], qim[2][2];
-  qre[0][0] = V4{0, 0, 0, 0};
-  qim[0][0] = V4{0, 0, 0, 0};
-#pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const int kk = acc_k<T>(s, lk);
-    const double2 pv = Ps[kk][16 * qb + lr];
-    const T bre = static_cast<T>(pv.x), bim = static_cast<T>(pv.y);
-    const T are = cre[s >> 2][0][s & 3], aim = cim[s >> 2][0][s & 3];
-    qre[0][0] = mfma16(are, bre, qre[0][0]);
-    qim[0][0] = mfma16(are, bim, qim[0][0]);
-    qre[0][0] = mfma16(-aim, bim, qre[0][0]);
-    qim[0][0] = mfma16(aim, bre, qim[0][0]);
-  }
-  T2* Qb = static_cast<T2*>(jb.Qn) + size_t(I) * TB * TB + (16 * qa) * TB + 16 * qb;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    T2 v;
-    v.x = qre[0][0][q];
-    v.y = qim[0][0][q];
-    Qb[mfma_row<T>(lk, q) * TB + lr] = v;
-  }
+  if (active) q_row<T>(jb, I, cre, cim, Ps, lr, lk, qa, qb);
 }
 
 // Workgroup -> (job q, index w within the job).  When the job count divides 8,
@@ -632,7 +729,6 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s) {
   };
   const int upd_wgs = static_cast<int>((tiles + 3) / 4);
   const int pan_wgs = ceil_div(nt, 4);   // first panel: four row tiles per workgroup
-  const int look_wgs = nt;               // look-ahead: one row tile per workgroup
   const double cmac = 8.0 * TB * TB * TB;   // flops of one TB^3 complex product
   // Sweep the given blocks (chain c of geometry g) through all panels; the
   // panel buffers of chain c alternate between halves 2c and 2c+1.
@@ -668,6 +764,7 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s) {
       k_gj_panel<T><<<grid_size(nch, pan_wgs), 256, 0, s>>>(js, nt);
       RCP_HIP(hipGetLastError());
     }
+    const int look_wgs = nt;   // look-ahead: one row tile per workgroup
     for (int k = 0; k + 1 < nt; ++k) {
       GJJobs js{};
       for (int q = 0; q < nch; ++q) {
@@ -677,7 +774,8 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s) {
         js.j[js.n++] = b;
       }
       KTimer kt(K_GJ_UPDATE, s, nch * cmac * double(tiles));
-      k_gj_fused<T><<<grid_size(nch, upd_wgs + look_wgs), 256, 0, s>>>(js, nt, tiles);
+      const int grid = grid_size(nch, upd_wgs + look_wgs);
+      k_gj_fused<T><<<grid, 256, 0, s>>>(js, nt, tiles);
       RCP_HIP(hipGetLastError());
     }
     {   // final update, negated
