@@ -62,8 +62,8 @@ DESCR = {
 # a 1 GiB copy (python bench.py --calibrate-copy).  Valid only for the kernel
 # source it was measured on: reported when factor.hip still has this hash.
 TRAFFIC = {"config": "config2", "batch": 4,
-           "sha256": "e5bb5561e49aeba51d9a453bf21cf3a041130a48489e73f88406a3889a5fb329",
-           "fetch_bytes": 87497373,     # 42724.5 KiB FETCH_SIZE x 1.99995
+           "sha256": "32d10f591c412cfb642c450fd6be225b3eb03790828bca8aa7a91b5cf2e98bd6",
+           "fetch_bytes": 85610995,     # 41803.4 KiB FETCH_SIZE x 1.99995
            "write_bytes": 82313523}     # 80384.3 KiB WRITE_SIZE x 1.0
 
 
