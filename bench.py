@@ -208,8 +208,12 @@ def main():
     nsteps = args.warmup + args.steps
     widths = [torch.tensor(W.seeded_widths(len(p.pillar_centers), 1002 + 97 * k), dtype=torch.float64,
                            device=dev) for k in range(nsteps * B)]
-    bufs = [torch.empty(rcp.factor_bytes(p, rcp.RCP_FP64), dtype=torch.uint8, device=dev)
-            for _ in range(B)]
+    # two sets of factor buffers when B > 1: the adjoint evaluations of step k
+    # run while step k+1 is factored (8 x ~20 GB on config 2, within 288 GB)
+    nsets = 2 if B > 1 else 1
+    bufsets = [[torch.empty(rcp.factor_bytes(p, rcp.RCP_FP64), dtype=torch.uint8, device=dev)
+                for _ in range(B)] for _ in range(nsets)]
+    bufs = bufsets[0]
     buf = bufs[0]
 
     # the B adjoint evaluations of a step run concurrently, one stream and one
@@ -220,16 +224,26 @@ def main():
         s = side[j]
         with torch.cuda.stream(s):
             F, g = rcp.adjoint_grad(fac, p, stream=s)
-            out[j] = (F, rcp.width_grad(p, g, w, stream=s))
+            gw = rcp.width_grad(p, g, w, stream=s)
+            done = torch.cuda.Event(enable_timing=True)
+            done.record(s)
+            out[j] = (F, gw, done)
 
-    def step(k):
+    def factor_step(k):
+        """ε maps and factorisation of step k (returns once the factors are complete)."""
         ws = widths[k * B:(k + 1) * B]
         eps = [rcp.eps_from_widths(p, w, device=dev) for w in ws]
         if B == 1:
-            fac = rcp.Factors(p, eps[0], rcp.RCP_FP64, buffer=bufs[0])
-            F, g = rcp.adjoint_grad(fac, p)
-            return fac, F, rcp.width_grad(p, g, ws[0])
-        facs = rcp.factor_batch([p] * B, eps, rcp.RCP_FP64, buffers=bufs)
+            return [rcp.Factors(p, eps[0], rcp.RCP_FP64, buffer=bufs[0])], ws
+        return rcp.factor_batch([p] * B, eps, rcp.RCP_FP64, buffers=bufsets[k % nsets]), ws
+
+    def start_adjoints(facs, ws):
+        if B == 1:
+            F, g = rcp.adjoint_grad(facs[0], p)
+            gw = rcp.width_grad(p, g, ws[0])
+            done = torch.cuda.Event(enable_timing=True)
+            done.record(stream)
+            return None, [(F, gw, done)], facs
         for s in side:
             s.wait_stream(stream)
         out = [None] * B
@@ -237,34 +251,50 @@ def main():
                    for j in range(B)]
         for t in threads:
             t.start()
-        for t in threads:
+        return threads, out, facs
+
+    def finish_adjoints(pending):
+        threads, out, facs = pending
+        for t in threads or []:
             t.join()
         for s in side:
             stream.wait_stream(s)
         if any(o is None for o in out):
             raise RuntimeError("an adjoint evaluation failed")
-        return facs[-1], out[-1][0], out[-1][1]
+        return facs[-1], out
 
-    for k in range(args.warmup):
-        fac, F, gw = step(k)
+    def run(first, count, starts=None):
+        """Steps first .. first+count-1, adjoints of step k overlapping factorisation k+1."""
+        results, pending = [], None
+        if count == 0:
+            return results
+        for k in range(first, first + count):
+            if starts is not None:
+                starts.append(torch.cuda.Event(enable_timing=True))
+                starts[-1].record(stream)
+            facs, ws = factor_step(k)
+            if pending is not None:
+                results.append(finish_adjoints(pending))
+            pending = start_adjoints(facs, ws)
+        results.append(finish_adjoints(pending))
+        return results
+
+    for fac, out in run(0, args.warmup):
         torch.cuda.synchronize()
-        log(f"warmup {k}: F={F.item():.6e}")
+        log(f"warmup: F={out[-1][0].item():.6e}")
 
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
+    starts = []
     rcp.kernel_timing_start(args.timing_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    Fs = []
-    for k in range(args.steps):
-        ev[k][0].record(stream)
-        fac, F, gw = step(args.warmup + k)
-        ev[k][1].record(stream)
-        Fs.append(F)
+    results = run(args.warmup, args.steps, starts)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kstats = rcp.kernel_timing_stop()
-    lat = sorted(a.elapsed_time(b) for a, b in ev)
+    fac = results[-1][0]
+    Fs = [r[1][-1][0] for r in results]
+    # latency of a step: from the start of its factorisation to its last adjoint result
+    lat = sorted(max(a.elapsed_time(o[2]) for o in r[1]) for a, r in zip(starts, results))
     wall = t1 - t0
     ms_per_step = 1e3 * wall / args.steps
     log(f"timed: {ms_per_step:.1f} ms/step, F={[round(f.item(), 8) for f in Fs]}")
@@ -294,7 +324,8 @@ def main():
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"{p.name}: {DESCR[p.name]}", "grid": [p.nx, p.ny],
                       "step": "eps map + assemble + factor (B side by side) + reciprocal F + "
-                              "adjoint dF/dwidths (B concurrent streams)",
+                              "adjoint dF/dwidths (B concurrent streams, overlapping the "
+                              "next step's factorisation)",
                       "geometries_per_step": B,
                       "precision": "complex FP64"},
            "p50_ms": round(p50, 3), "p99_ms": round(p99, 3),
