@@ -169,7 +169,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="config2", choices=sorted(DESCR))
     ap.add_argument("--bf-angles", type=int, default=1000)
-    ap.add_argument("--bf-chunk", type=int, default=500)
+    ap.add_argument("--bf-chunk", type=int, default=1000)
     ap.add_argument("--timing-every", type=int, default=4)
     ap.add_argument("--no-extras", action="store_true", help="time the step only")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -172,11 +172,84 @@ struct MmJobs {
 };
 
 constexpr int MT = 64;   // workgroup tile (rows r) x (columns j)
+constexpr int KC = 16;   // k chunk staged in LDS
 
-__global__ __launch_bounds__(256) void k_gemm_sweep(MmJobs jobs, int R, int nx, int ny, int nt,
-                                                     size_t rstride, int jline, int conjop) {
-  __shared__ double2 As[MT][TB + 1];
-  __shared__ double2 Bs[TB][MT + 1];
+// Staging of one k chunk: every thread fetches 4 elements of the right-hand
+// side tile (formed on the fly: f + line source - C1 v1 - C2 v2) and 4 of the
+// block tile into registers; they are stored to LDS after the previous chunk's
+// products, so the global loads of chunk c+1 overlap the MFMA work of chunk c.
+struct MmStage {
+  double2 a[4], b[4];
+};
+
+__device__ __forceinline__ void mm_fetch(const MmJob& jb, MmStage& st, int kc, int r0, int j0,
+                                         int R, int nx, int ny, int nt, size_t rstride,
+                                         size_t boff, int jline, int conjop) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {   // A: 64 rows x 16 k, contiguous along k
+    const int e = tid + 256 * u, rr = e >> 4, kk = e & 15;
+    const int r = r0 + rr, k = kc * KC + kk;
+    double2 v = make_double2(0.0, 0.0);
+    if (r < R && k < ny) {
+      const size_t q = size_t(r) * rstride + boff + k;
+      if (jb.f) v = jb.f[q];
+      if (jb.fline && k == jline) v = cadd(v, jb.fline[size_t(r) * nx + jb.block]);
+      if (jb.v1) v = csub(v, cmul(maybe_conj(jb.c1[k], conjop), jb.v1[q]));
+      if (jb.v2) v = csub(v, cmul(maybe_conj(jb.c2[k], conjop), jb.v2[q]));
+    }
+    st.a[u] = v;
+  }
+  const int K = (kc * KC) / TB, koff = (kc * KC) % TB;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {   // B: 16 k x 64 j as two 16 x 32 halves of storage tiles
+    const int e = tid + 256 * u, half = e >> 9, idx = e & 511;
+    const int J = j0 / TB + half;
+    double2 x = make_double2(0.0, 0.0);
+    if (J < nt) {
+      if (K >= J) {   // rows koff.. of tile (K, J): contiguous along j
+        x = jb.X[tile_index(K, J) * TB * TB + (koff + (idx >> 5)) * TB + (idx & 31)];
+      } else {        // X(k, j) = X(j, k): columns koff.. of tile (J, K), contiguous along k
+        x = jb.X[tile_index(J, K) * TB * TB + (idx >> 4) * TB + koff + (idx & 15)];
+      }
+    }
+    if (conjop) x.y = -x.y;
+    st.b[u] = x;
+  }
+}
+
+__device__ __forceinline__ void mm_store(const MmStage& st, double2 (*As)[KC + 1],
+                                         double2 (*Bs)[MT + 1], int kc, int j0, int nt) {
+  const int tid = threadIdx.x;
+  const int K = (kc * KC) / TB;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u;
+    As[e >> 4][e & 15] = st.a[u];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = tid + 256 * u, half = e >> 9, idx = e & 511;
+    const int J = j0 / TB + half;
+    int kk, jj;
+    if (J >= nt || K >= J) {
+      kk = idx >> 5;
+      jj = idx & 31;
+    } else {
+      jj = idx >> 4;
+      kk = idx & 15;
+    }
+    Bs[kk][half * TB + jj] = st.b[u];
+  }
+}
+
+// One sweep step of the many-right-hand-side solve: out = base + RHS X_i for
+// every (job, 64-row, 64-column) tile, RHS formed on the fly, X_i read from
+// its packed symmetric tiles; four waves, each a 32 x 32 quarter.
+__global__ __launch_bounds__(256, 3) void k_gemm_sweep(MmJobs jobs, int R, int nx, int ny, int nt,
+                                                        size_t rstride, int jline, int conjop) {
+  __shared__ double2 As[MT][KC + 1];
+  __shared__ double2 Bs[KC][MT + 1];
   const int ntile_r = ceil_div(R, MT), ntile_j = ceil_div(nt * TB, MT);
   const int per_job = ntile_r * ntile_j;
   const int ji = blockIdx.x / per_job;
@@ -197,50 +270,16 @@ __global__ __launch_bounds__(256) void k_gemm_sweep(MmJobs jobs, int R, int nx, 
       cre[a][b] = v4d{0, 0, 0, 0};
       cim[a][b] = v4d{0, 0, 0, 0};
     }
-  for (int kt = 0; kt < nt; ++kt) {
-    // A tile: 64 rows x 32 k
-    for (int e = tid; e < MT * TB; e += 256) {
-      int rr = e / TB, kk = e % TB;
-      int r = r0 + rr, k = kt * TB + kk;
-      double2 v = make_double2(0.0, 0.0);
-      if (r < R && k < ny) {
-        size_t q = size_t(r) * rstride + boff + k;
-        if (jb.f) v = jb.f[q];
-        if (jb.fline && k == jline) v = cadd(v, jb.fline[size_t(r) * nx + jb.block]);
-        if (jb.v1) v = csub(v, cmul(maybe_conj(jb.c1[k], conjop), jb.v1[q]));
-        if (jb.v2) v = csub(v, cmul(maybe_conj(jb.c2[k], conjop), jb.v2[q]));
-      }
-      As[rr][kk] = v;
-    }
-    // B tile: X[kt*TB + kk][j0 + jj], jj < 64 (two storage tiles)
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      int jt2 = (j0 / TB) + half;
-      for (int e = tid; e < TB * TB; e += 256) {
-        int a = e / TB, b = e % TB;   // contiguous in memory order
-        double2 x = make_double2(0.0, 0.0);
-        int kk, jj;
-        if (jt2 < nt) {
-          if (kt >= jt2) {
-            x = jb.X[tile_index(kt, jt2) * TB * TB + e];
-            kk = a;
-            jj = b;
-          } else {
-            x = jb.X[tile_index(jt2, kt) * TB * TB + e];
-            kk = b;
-            jj = a;
-          }
-        } else {
-          kk = a;
-          jj = b;
-        }
-        if (conjop) x.y = -x.y;
-        Bs[kk][half * TB + jj] = x;
-      }
-    }
+  const int nk = nt * TB / KC;
+  MmStage st;
+  mm_fetch(jb, st, 0, r0, j0, R, nx, ny, nt, rstride, boff, jline, conjop);
+  for (int kc = 0; kc < nk; ++kc) {
     __syncthreads();
+    mm_store(st, As, Bs, kc, j0, nt);
+    __syncthreads();
+    if (kc + 1 < nk) mm_fetch(jb, st, kc + 1, r0, j0, R, nx, ny, nt, rstride, boff, jline, conjop);
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
+    for (int s = 0; s < KC / 4; ++s) {
       double2 av[2], bv[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) av[a] = As[32 * wr + 16 * a + lr][4 * s + lk];
@@ -248,7 +287,7 @@ __global__ __launch_bounds__(256) void k_gemm_sweep(MmJobs jobs, int R, int nx, 
       for (int b = 0; b < 2; ++b) bv[b] = Bs[4 * s + lk][32 * wc + 16 * b + lr];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        double naim = -av[a].y;
+        const double naim = -av[a].y;
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           cre[a][b] = mfma16(av[a].x, bv[b].x, cre[a][b]);
@@ -258,7 +297,6 @@ __global__ __launch_bounds__(256) void k_gemm_sweep(MmJobs jobs, int R, int nx, 
         }
       }
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
