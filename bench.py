@@ -1,7 +1,7 @@
 """Benchmark of the reciprocal incoherent-light average on one MI355X.
 
 One step = one inverse-design evaluation of each of B fresh seeded geometries
-(B = 4 by default, factored side by side in the same launches): pillar widths
+(B = 8 by default, factored side by side in the same launches): pillar widths
 -> permittivity map -> FDFD assembly -> twisted block factorisation ->
 reciprocal solve -> Toeplitz/FFT form F = v^dag W v -> adjoint solve ->
 dF/deps -> dF/dwidths, all in librecip's HIP kernels, inputs already on the
@@ -177,8 +177,8 @@ def main():
                     help="requests in the serving measurement (0 = skip)")
     ap.add_argument("--serve-scale", type=float, default=0.25,
                     help="width/depth scale of the serving mix (1 = widths 20-300, depths 10-60)")
-    ap.add_argument("--batch", type=int, default=4,
-                    help="geometries factored side by side per step (1-4)")
+    ap.add_argument("--batch", type=int, default=8,
+                    help="geometries factored side by side per step (1-8)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (reference for the HBM counters)")
     args = ap.parse_args()
@@ -204,30 +204,32 @@ def main():
     log(f"bench: {p.name} {p.nx}x{p.ny}, steps={args.steps} warmup={args.warmup}")
 
     # inputs resident in HBM before timing: B seeded geometries per step
-    B = max(1, min(4, args.batch))
+    B = max(1, min(8, args.batch))
     nsteps = args.warmup + args.steps
     widths = [torch.tensor(W.seeded_widths(len(p.pillar_centers), 1002 + 97 * k), dtype=torch.float64,
                            device=dev) for k in range(nsteps * B)]
-    # two sets of factor buffers when B > 1: the adjoint evaluations of step k
-    # run while step k+1 is factored (8 x ~20 GB on config 2, within 288 GB)
-    nsets = 2 if B > 1 else 1
-    bufsets = [[torch.empty(rcp.factor_bytes(p, rcp.RCP_FP64), dtype=torch.uint8, device=dev)
-                for _ in range(B)] for _ in range(nsets)]
+    # two sets of factor buffers when they fit in 200 GiB (B = 4 on config 2:
+    # 8 x ~20 GB): the adjoint evaluations of step k then run while step k+1 is
+    # factored; with one set (B = 8) they finish before the next factorisation
+    fbytes = rcp.factor_bytes(p, rcp.RCP_FP64)
+    nsets = 2 if B > 1 and 2 * B * fbytes <= (200 << 30) else 1
+    bufsets = [[torch.empty(fbytes, dtype=torch.uint8, device=dev) for _ in range(B)]
+               for _ in range(nsets)]
     bufs = bufsets[0]
     buf = bufs[0]
 
-    # the B adjoint evaluations of a step run concurrently, one stream and one
-    # host thread each (ctypes releases the GIL during the library call)
-    side = [torch.cuda.Stream(device=dev) for _ in range(B)] if B > 1 else []
+    # the B adjoint evaluations of a step: one batched call (their solves share
+    # kernel launches) on a side stream, issued from a worker thread so that it
+    # can overlap the next factorisation (ctypes releases the GIL)
+    side = torch.cuda.Stream(device=dev) if B > 1 else None
 
-    def adjoint_on(j, fac, w, out):
-        s = side[j]
-        with torch.cuda.stream(s):
-            F, g = rcp.adjoint_grad(fac, p, stream=s)
-            gw = rcp.width_grad(p, g, w, stream=s)
+    def adjoint_on(facs, ws, out):
+        with torch.cuda.stream(side):
+            Fb, grads = rcp.adjoint_grad_batch(facs, [p] * B, stream=side)
+            gws = [rcp.width_grad(p, g, w, stream=side) for g, w in zip(grads, ws)]
             done = torch.cuda.Event(enable_timing=True)
-            done.record(s)
-            out[j] = (F, gw, done)
+            done.record(side)
+            out[:] = [(Fb[j], gws[j], done) for j in range(B)]
 
     def factor_step(k):
         """ε maps and factorisation of step k (returns once the factors are complete)."""
@@ -244,22 +246,19 @@ def main():
             done = torch.cuda.Event(enable_timing=True)
             done.record(stream)
             return None, [(F, gw, done)], facs
-        for s in side:
-            s.wait_stream(stream)
-        out = [None] * B
-        threads = [threading.Thread(target=adjoint_on, args=(j, facs[j], ws[j], out))
-                   for j in range(B)]
-        for t in threads:
-            t.start()
+        side.wait_stream(stream)
+        out = []
+        threads = [threading.Thread(target=adjoint_on, args=(facs, ws, out))]
+        threads[0].start()
         return threads, out, facs
 
     def finish_adjoints(pending):
         threads, out, facs = pending
         for t in threads or []:
             t.join()
-        for s in side:
-            stream.wait_stream(s)
-        if any(o is None for o in out):
+        if side is not None:
+            stream.wait_stream(side)
+        if len(out) != len(facs):
             raise RuntimeError("an adjoint evaluation failed")
         return facs[-1], out
 
@@ -272,6 +271,9 @@ def main():
             if starts is not None:
                 starts.append(torch.cuda.Event(enable_timing=True))
                 starts[-1].record(stream)
+            if pending is not None and nsets == 1:   # its factors are about to be overwritten
+                results.append(finish_adjoints(pending))
+                pending = None
             facs, ws = factor_step(k)
             if pending is not None:
                 results.append(finish_adjoints(pending))
@@ -324,8 +326,8 @@ def main():
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"{p.name}: {DESCR[p.name]}", "grid": [p.nx, p.ny],
                       "step": "eps map + assemble + factor (B side by side) + reciprocal F + "
-                              "adjoint dF/dwidths (B concurrent streams, overlapping the "
-                              "next step's factorisation)",
+                              "adjoint dF/dwidths (B batched; overlapping the next step's "
+                              "factorisation when two factor sets fit)",
                       "geometries_per_step": B,
                       "precision": "complex FP64"},
            "p50_ms": round(p50, 3), "p99_ms": round(p99, 3),

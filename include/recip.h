@@ -151,7 +151,7 @@ size_t rcp_factor_bytes(const rcp_grid* grid, int32_t precision);
 int rcp_factor(const rcp_grid* grid, int32_t precision, void* buf_dev, size_t buf_bytes,
                rcp_stream stream, rcp_factors** out);
 
-/* a2 + a3 for `count` (1..4) geometries of identical grid (only eps differs),
+/* a2 + a3 for `count` (1..8) geometries of identical grid (only eps differs),
  * factored in the same kernel launches (their elimination chains run side by
  * side).  grids[g], bufs[g] (each buf_bytes >= rcp_factor_bytes, 256-byte
  * aligned, non-overlapping) and out[g] as for rcp_factor.  On failure no
@@ -198,6 +198,16 @@ int rcp_brute_force_average(const rcp_factors* f, const rcp_objective* obj,
  * grad_eps_dev: nx*ny float64. */
 int rcp_adjoint_grad(const rcp_factors* f, const rcp_objective* obj, const rcp_light* light,
                      double* F_dev, double* grad_eps_dev, rcp_stream stream);
+
+/* a9 for `count` (1..8) factor sets of identical grid and precision, e.g.
+ * from one rcp_factor_batch call: the same computation as rcp_adjoint_grad
+ * for each set g with objs[g] and lights[g], results bit-identical to it.
+ * With RCP_FP64 factors the two solves of all sets advance in the same
+ * kernel launches.  F_dev: count float64 (device); grad_eps_dev: count
+ * device pointers (host array), each nx*ny float64.  A set may appear once. */
+int rcp_adjoint_grad_batch(int32_t count, rcp_factors* const* factors,
+                           const rcp_objective* objs, const rcp_light* lights, double* F_dev,
+                           double* const* grad_eps_dev, rcp_stream stream);
 
 /* a1 backward -- chain rule from dF/deps to dF/dwidth_p: each pillar edge moves
  * by dw/2 and changes the fill of the cell holding it by dw/(2h) in every

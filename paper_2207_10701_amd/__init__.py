@@ -21,7 +21,8 @@ from ._lib import (RCP_ANNULUS, RCP_COLLIMATOR, RCP_CONCENTRATOR, RCP_CONE, RCP_
                    RCP_FP64, RCP_SYMBOL_TABLE, RecipError, check, lib)
 
 __all__ = ["Factors", "factor_batch", "factor_bytes", "eps_from_widths", "reciprocal_average",
-           "brute_force_average", "adjoint_grad", "width_grad", "solve", "IncoherentFOM",
+           "brute_force_average", "adjoint_grad", "adjoint_grad_batch", "width_grad", "solve",
+           "IncoherentFOM",
            "RCP_FP64", "RCP_FP32_REFINED", "RecipError"]
 
 
@@ -133,10 +134,10 @@ class Factors:
 
 
 def factor_batch(problems, eps_list, precision: int = RCP_FP64, buffers=None, stream=None):
-    """Factor 1-4 same-grid geometries in the same kernel launches (chains side by side)."""
+    """Factor 1-8 same-grid geometries in the same kernel launches (chains side by side)."""
     B = len(problems)
-    if B < 1 or B > 4 or len(eps_list) != B:
-        raise ValueError("factor_batch takes 1 to 4 problems with one eps map each")
+    if B < 1 or B > 8 or len(eps_list) != B:
+        raise ValueError("factor_batch takes 1 to 8 problems with one eps map each")
     nbytes = factor_bytes(problems[0], precision)
     dev = eps_list[0].device
     if buffers is None:
@@ -199,6 +200,26 @@ def adjoint_grad(fac: Factors, p: Optional[Problem] = None, stream=None):
     check(lib.rcp_adjoint_grad(fac.handle, C.byref(o), C.byref(lt), F.data_ptr(), g.data_ptr(),
                                _stream(stream)))
     return F, g
+
+
+def adjoint_grad_batch(facs, problems=None, stream=None):
+    """adjoint_grad for 1-8 factor sets of one grid (e.g. from factor_batch), their
+    two solves advancing in the same kernel launches.  Returns (F of shape (B,),
+    list of nx x ny dF/deps maps); each bit-identical to adjoint_grad."""
+    B = len(facs)
+    problems = problems or [f.problem for f in facs]
+    if B < 1 or B > 8 or len(problems) != B:
+        raise ValueError("adjoint_grad_batch takes 1 to 8 factor sets with one problem each")
+    dev = facs[0].buf.device
+    F = torch.empty(B, dtype=torch.float64, device=dev)
+    grads = [torch.empty((p.nx, p.ny), dtype=torch.float64, device=dev) for p in problems]
+    handles = (C.c_void_p * B)(*[f.handle.value for f in facs])
+    objs = (_lib.Objective * B)(*[objective_struct(p) for p in problems])
+    lights = (_lib.Light * B)(*[light_struct(p) for p in problems])
+    gptr = (C.c_void_p * B)(*[g.data_ptr() for g in grads])
+    check(lib.rcp_adjoint_grad_batch(B, handles, objs, lights, F.data_ptr(), gptr,
+                                     _stream(stream)))
+    return F, grads
 
 
 def width_grad(p: Problem, grad_eps: torch.Tensor, widths: Optional[torch.Tensor] = None,

@@ -81,6 +81,7 @@ def _load():
         "rcp_brute_force_average": (C.c_int, [vp, P(Objective), P(Light), i32, i32, vp, sz, vp,
                                               vp, vp]),
         "rcp_adjoint_grad": (C.c_int, [vp, P(Objective), P(Light), vp, vp, vp]),
+        "rcp_adjoint_grad_batch": (C.c_int, [i32, P(vp), P(Objective), P(Light), vp, P(vp), vp]),
         "rcp_width_grad": (C.c_int, [P(Grid), P(Pillars), vp, vp, vp]),
         "rcp_factors_release": (None, [vp]),
         "rcp_last_error": (C.c_char_p, []),

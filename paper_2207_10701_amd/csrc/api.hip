@@ -247,7 +247,7 @@ size_t rcp_factor_bytes(const rcp_grid* grid, int32_t precision) {
 int rcp_factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, void* const* bufs,
                      size_t buf_bytes, rcp_stream stream, rcp_factors** out) {
   if (!out || !grids || !bufs) return fail(RCP_EINVAL, "NULL argument");
-  if (count < 1 || count > 4) return fail(RCP_EINVAL, "count must be 1 to 4");
+  if (count < 1 || count > MAX_BATCH) return fail(RCP_EINVAL, "count must be 1 to 8");
   for (int g = 0; g < count; ++g) out[g] = nullptr;
   if (precision != RCP_FP64 && precision != RCP_FP32_REFINED)
     return fail(RCP_EINVAL, "unknown precision");
@@ -275,7 +275,7 @@ int rcp_factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, vo
       if (x0 < y0 + L.total && y0 < x0 + L.total) return fail(RCP_EINVAL, "factor buffers overlap");
     }
   }
-  rcp_factors* fs[4] = {nullptr, nullptr, nullptr, nullptr};
+  rcp_factors* fs[MAX_BATCH] = {};   // count <= MAX_BATCH checked above
   int rc = RCP_OK;
   for (int g = 0; g < count && !rc; ++g) {
     const rcp_grid* grid = &grids[g];
@@ -442,6 +442,67 @@ int rcp_adjoint_grad(const rcp_factors* fc, const rcp_objective* obj, const rcp_
                          nullptr);
   if (rc) return rc;
   return grad_eps(f, lam, z, grad_eps_dev, stream);
+}
+
+int rcp_adjoint_grad_batch(int32_t count, rcp_factors* const* factors, const rcp_objective* objs,
+                           const rcp_light* lights, double* F_dev, double* const* grad_eps_dev,
+                           rcp_stream stream) {
+  if (count < 1 || count > MAX_BATCH) return fail(RCP_EINVAL, "count must be 1 to 8");
+  if (!factors || !objs || !lights || !F_dev || !grad_eps_dev)
+    return fail(RCP_EINVAL, "NULL argument");
+  rcp_factors* fs[MAX_BATCH] = {};
+  for (int g = 0; g < count; ++g) {
+    fs[g] = factors[g];
+    if (!fs[g]) return fail(RCP_EINVAL, "factors " + std::to_string(g) + " is NULL");
+    const rcp_factors& a = *fs[0];
+    const rcp_factors& c = *fs[g];
+    if (c.nx != a.nx || c.ny != a.ny || c.precision != a.precision)
+      return fail(RCP_EINVAL, "a batch needs factors of identical grid and precision");
+    for (int h = 0; h < g; ++h)
+      if (fs[h] == fs[g]) return fail(RCP_EINVAL, "the same factors appear twice in a batch");
+    int rc = check_objective(fs[g], &objs[g]);
+    if (!rc) rc = check_light(fs[g], &lights[g], false);
+    if (rc) return rc;
+    if (!grad_eps_dev[g]) return fail(RCP_EINVAL, "NULL output");
+  }
+  if (fs[0]->precision != RCP_FP64) {   // refinement runs per factor set
+    for (int g = 0; g < count; ++g) {
+      int rc = rcp_adjoint_grad(fs[g], &objs[g], &lights[g], F_dev + g, grad_eps_dev[g], stream);
+      if (rc) return rc;
+    }
+    return RCP_OK;
+  }
+  // the same steps as rcp_adjoint_grad, the two solves of all sets in lockstep
+  const double2* rhs[MAX_BATCH];
+  double2* sol[MAX_BATCH];
+  int lo[MAX_BATCH], hi[MAX_BATCH];
+  for (int g = 0; g < count; ++g) {
+    double2* w = fs[g]->vec[V_RHS];
+    int rc = objective_rhs(fs[g], &objs[g], w, &lo[g], &hi[g], stream);
+    if (rc) return rc;
+    rhs[g] = w;
+    sol[g] = fs[g]->vec[V_Z];
+  }
+  int rc = solve_vec_batch(fs, count, rhs, sol, 1, lo, hi, stream);
+  if (rc) return rc;
+  for (int g = 0; g < count; ++g) {
+    rcp_factors* f = fs[g];
+    double2* Tv = f->fft[3];
+    rc = toeplitz_form(f, &lights[g], f->vec[V_Z], F_dev + g, nullptr, Tv, stream);
+    if (!rc) rc = scatter_line(f, &lights[g], Tv, f->vec[V_ARHS], stream);
+    if (rc) return rc;
+    rhs[g] = f->vec[V_ARHS];
+    sol[g] = f->vec[V_LAM];
+    lo[g] = lights[g].i0;
+    hi[g] = lights[g].i1 - 1;
+  }
+  rc = solve_vec_batch(fs, count, rhs, sol, 0, lo, hi, stream);
+  if (rc) return rc;
+  for (int g = 0; g < count; ++g) {
+    rc = grad_eps(fs[g], fs[g]->vec[V_LAM], fs[g]->vec[V_Z], grad_eps_dev[g], stream);
+    if (rc) return rc;
+  }
+  return RCP_OK;
 }
 
 int rcp_width_grad(const rcp_grid* grid, const rcp_pillars* pillars, const double* grad_eps_dev,

@@ -47,17 +47,11 @@ struct GJJob {
   double2* Pn;
   double* health;   // min |pivot| slot of the panel this job inverts
 };
-constexpr int MAXJ = 8;   // chains per launch: two per geometry, up to four geometries
+constexpr int MAXJ = 2 * MAX_BATCH;   // chains per launch: two per geometry
 struct GJJobs {
   GJJob j[MAXJ];
   int n;
 };
-
-#define RCP_SEL8(js, q, fld)                                                              \
-  ((q) < 4 ? ((q) < 2 ? ((q) == 0 ? js.j[0].fld : js.j[1].fld)                           \
-                      : ((q) == 2 ? js.j[2].fld : js.j[3].fld))                           \
-           : ((q) < 6 ? ((q) == 4 ? js.j[4].fld : js.j[5].fld)                            \
-                      : ((q) == 6 ? js.j[6].fld : js.j[7].fld)))
 
 // Job of this workgroup: every job of a launch has the same workgroup count;
 // fields are selected one at a time so that the table stays in kernel-argument
@@ -66,7 +60,7 @@ __device__ __forceinline__ GJJob pick(const GJJobs& js, int* wg) {
   const int per = js.j[0].wgs;
   const int q = *wg / per;
   *wg -= q * per;
-#define RCP_SEL(fld) RCP_SEL8(js, q, fld)
+#define RCP_SEL(fld) RCP_SEL16(js, q, fld)
   GJJob jb;
   jb.k = RCP_SEL(k);
   jb.last = RCP_SEL(last);
@@ -595,17 +589,22 @@ __device__ void lookahead_work(const GJJob& jb, int I, int nt, double2 (*Ps)[TB 
   if (active) q_row<T>(jb, I, cre, cim, Ps, lr, lk, qa, qb);
 }
 
-// Workgroup -> (job q, index w within the job).  When the job count divides 8,
-// job q gets the XCDs x with x % n == q (workgroups are dealt to the 8 XCDs
-// round robin), so the panel buffers a chain's workgroups all read stay in the
-// L2 of its own XCDs; the grid is then padded to a multiple of 8 (grid_size)
-// and the surplus workgroups return false.
+// Workgroup -> (job q, index w within the job).  Workgroups are dealt to the 8
+// XCDs round robin.  When the job count n divides 8, job q gets the XCDs x with
+// x % n == q; when 8 divides n, XCD x serves jobs x, x + 8, ...; either way
+// the panel buffers a chain's workgroups all read stay in the L2 of its own
+// XCDs.  For n dividing 8 the grid is padded to a multiple of 8 (grid_size) and
+// the surplus workgroups return false.
 __device__ __forceinline__ bool job_of(int n, int per, int* q, int* w) {
   const int b = blockIdx.x;
+  const int x = b & 7, slot = b >> 3;
   if (8 % n == 0) {
-    const int x = b & 7, slot = b >> 3;
     *q = x % n;
     *w = slot * (8 / n) + x / n;
+  } else if (n % 8 == 0) {
+    const int m = n / 8;
+    *q = x + 8 * (slot % m);
+    *w = slot / m;
   } else {
     *q = b / per;
     *w = b - *q * per;
@@ -675,32 +674,31 @@ __global__ __launch_bounds__(256) void k_schur(SchurJobs jobs, int ny, size_t ti
   using T2 = typename cplx<T>::t;
   const size_t t = blockIdx.x % tiles;
   const int ji = static_cast<int>(blockIdx.x / tiles);
-  SchurJob jb;
-  jb.dst = RCP_SEL8(jobs, ji, dst);
-  jb.src1 = RCP_SEL8(jobs, ji, src1);
-  jb.src2 = RCP_SEL8(jobs, ji, src2);
-  jb.dco = RCP_SEL8(jobs, ji, dco);
-  jb.eco = RCP_SEL8(jobs, ji, eco);
-  jb.c1 = RCP_SEL8(jobs, ji, c1);
-  jb.c2 = RCP_SEL8(jobs, ji, c2);
+  void* const jdst = RCP_SEL16(jobs, ji, dst);
+  const void* const jsrc1 = RCP_SEL16(jobs, ji, src1);
+  const void* const jsrc2 = RCP_SEL16(jobs, ji, src2);
+  const double2* const dco = RCP_SEL16(jobs, ji, dco);
+  const double2* const eco = RCP_SEL16(jobs, ji, eco);
+  const double2* const c1 = RCP_SEL16(jobs, ji, c1);
+  const double2* const c2 = RCP_SEL16(jobs, ji, c2);
   int I, J;
   tile_coords(static_cast<int>(t), &I, &J);
-  T2* dst = static_cast<T2*>(jb.dst) + t * TB * TB;
-  const T2* s1 = jb.src1 ? static_cast<const T2*>(jb.src1) + t * TB * TB : nullptr;
-  const T2* s2 = jb.src2 ? static_cast<const T2*>(jb.src2) + t * TB * TB : nullptr;
+  T2* dst = static_cast<T2*>(jdst) + t * TB * TB;
+  const T2* s1 = jsrc1 ? static_cast<const T2*>(jsrc1) + t * TB * TB : nullptr;
+  const T2* s2 = jsrc2 ? static_cast<const T2*>(jsrc2) + t * TB * TB : nullptr;
   for (int e = threadIdx.x; e < TB * TB; e += 256) {
     int a = I * TB + e / TB, b = J * TB + e % TB;
     double2 v = make_double2(0.0, 0.0);
     if (a == b) {
-      v = (a < ny) ? jb.dco[a] : make_double2(1.0, 0.0);
+      v = (a < ny) ? dco[a] : make_double2(1.0, 0.0);
     } else if (a == b + 1 && a < ny) {
-      v = jb.eco[b];
+      v = eco[b];
     } else if (b == a + 1 && b < ny) {
-      v = jb.eco[a];
+      v = eco[a];
     }
     if (a < ny && b < ny) {
-      if (s1) v = csub(v, cmul(cmul(jb.c1[a], jb.c1[b]), to_c128(s1[e])));
-      if (s2) v = csub(v, cmul(cmul(jb.c2[a], jb.c2[b]), to_c128(s2[e])));
+      if (s1) v = csub(v, cmul(cmul(c1[a], c1[b]), to_c128(s1[e])));
+      if (s2) v = csub(v, cmul(cmul(c2[a], c2[b]), to_c128(s2[e])));
     }
     dst[e] = from_c128<T2>(v);
   }
@@ -859,7 +857,7 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s) {
 namespace rcp {
 
 int factor_blocks(rcp_factors* const* fs, int B, hipStream_t s) {
-  if (B < 1 || B > MAXJ / 2) return fail(RCP_EINVAL, "batch of 1 to 4 geometries");
+  if (B < 1 || B > MAXJ / 2) return fail(RCP_EINVAL, "batch of 1 to 8 geometries");
   const int prec = fs[0]->precision;
   int rc = (prec == RCP_FP64) ? run_factor<double>(fs, B, s) : run_factor<float>(fs, B, s);
   if (rc) return rc;

@@ -19,6 +19,7 @@ namespace rcp {
 // tile (I, J), I >= J, sits at index I (I + 1) / 2 + J, row-major inside.
 constexpr int TB = 32;
 constexpr int NVEC = 8;          // complex128 work vectors of nx*ny in the buffer
+constexpr int MAX_BATCH = 8;     // geometries factored side by side (two chains each)
 
 // Work-vector roles.
 enum { V_Z = 0, V_Y = 1, V_RHS = 2, V_LAM = 3, V_ARHS = 4, V_RES = 5, V_DU = 6, V_TMP = 7 };
@@ -115,8 +116,17 @@ int launch_assemble(rcp_factors* f, const double* eps_src, hipStream_t s);
 int launch_width_grad(const rcp_grid* g, const rcp_pillars* p, const double* grad_eps,
                       double* grad_w, hipStream_t s);
 
+// Field fld of job q (uniform) of a kernel-argument job table, selected one
+// field at a time so that the table stays in kernel-argument registers.
+#define RCP_SEL4(js, q, o, fld)                                                    \
+  ((q) < (o) + 2 ? ((q) == (o) ? js.j[(o)].fld : js.j[(o) + 1].fld)                \
+                 : ((q) == (o) + 2 ? js.j[(o) + 2].fld : js.j[(o) + 3].fld))
+#define RCP_SEL16(js, q, fld)                                                      \
+  ((q) < 8 ? ((q) < 4 ? RCP_SEL4(js, q, 0, fld) : RCP_SEL4(js, q, 4, fld))         \
+           : ((q) < 12 ? RCP_SEL4(js, q, 8, fld) : RCP_SEL4(js, q, 12, fld)))
+
 // factor.hip
-// Factor B (1..4) geometries of identical shape in the same launches.
+// Factor B (1..MAX_BATCH) geometries of identical shape in the same launches.
 int factor_blocks(rcp_factors* const* fs, int B, hipStream_t s);
 
 // solve.hip
@@ -125,6 +135,10 @@ int factor_blocks(rcp_factors* const* fs, int B, hipStream_t s);
 // [nz_lo, nz_hi] of f are known to be zero.
 int solve_vec(rcp_factors* f, const double2* rhs, double2* u, int conjop, int nz_lo, int nz_hi,
               hipStream_t s);
+// The same for B (1..MAX_BATCH) factor sets of identical shape and precision,
+// their sweeps advancing in the same launches: u[g] = A_g^{-1} rhs[g].
+int solve_vec_batch(rcp_factors* const* fs, int B, const double2* const* rhs, double2* const* u,
+                    int conjop, const int* nz_lo, const int* nz_hi, hipStream_t s);
 // Refined (FP32 factors) or plain (FP64) single-RHS solve with statistics.
 int solve_vec_refined(rcp_factors* f, const double2* rhs, double2* u, int conjop, int nz_lo,
                       int nz_hi, double tol, int max_refine, hipStream_t s, rcp_solve_stats* st);

@@ -32,7 +32,7 @@ struct SvJob {
   const double2* c2;
 };
 struct SvJobs {
-  SvJob j[2];
+  SvJob j[2 * MAX_BATCH];   // left and right chain of each factor set
   int n;
 };
 
@@ -62,8 +62,15 @@ __global__ __launch_bounds__(512) void k_gemv(SvJobs jobs, int nt, int ny, int c
   const int per_job = 4 * nt;
   const int ji = blockIdx.x / per_job, rem = blockIdx.x % per_job;
   const int I = rem >> 2, r0 = (rem & 3) * 8;
-  SvJob jb = jobs.j[0];
-  if (ji == 1) jb = jobs.j[1];
+  SvJob jb;
+  jb.X = RCP_SEL16(jobs, ji, X);
+  jb.out = RCP_SEL16(jobs, ji, out);
+  jb.base = RCP_SEL16(jobs, ji, base);
+  jb.f = RCP_SEL16(jobs, ji, f);
+  jb.v1 = RCP_SEL16(jobs, ji, v1);
+  jb.c1 = RCP_SEL16(jobs, ji, c1);
+  jb.v2 = RCP_SEL16(jobs, ji, v2);
+  jb.c2 = RCP_SEL16(jobs, ji, c2);
   const int tid = threadIdx.x;
   const T2* X = static_cast<const T2*>(jb.X);
   const int wave = tid >> 6, lane = tid & 63;
@@ -384,18 +391,21 @@ __global__ void k_axpy(size_t n, const double2* __restrict__ dx, double2* __rest
   if (q < n) x[q] = cadd(x[q], dx[q]);
 }
 
+// Forward and back sweeps of B factor sets of identical shape in lockstep:
+// every launch carries the left and right chain step of each set.
 template <typename T>
-int run_solve_vec(rcp_factors* f, const double2* rhs, double2* u, int conjop, int nz_lo, int nz_hi,
-                  hipStream_t s) {
-  const int N = f->nx, ny = f->ny, nt = f->nt, m = f->m;
-  if (f->np > NPMAX) return fail(RCP_EINVAL, "block size too large for the vector sweep");
+int run_solve_vec(rcp_factors* const* fs, int B, const double2* const* rhs, double2* const* u,
+                  int conjop, const int* nz_lo, const int* nz_hi, hipStream_t s) {
+  const rcp_factors* f0 = fs[0];
+  const int N = f0->nx, ny = f0->ny, nt = f0->nt, m = f0->m;
+  if (f0->np > NPMAX) return fail(RCP_EINVAL, "block size too large for the vector sweep");
   const int lenL = m, lenR = N - 1 - m;
-  auto U = [&](int i) { return u + size_t(i) * ny; };
-  auto Fb = [&](int i) { return rhs + size_t(i) * ny; };
-  auto C = [&](int i) { return f->cco + size_t(i) * ny; };
+  auto U = [&](int g, int i) { return u[g] + size_t(i) * ny; };
+  auto Fb = [&](int g, int i) { return rhs[g] + size_t(i) * ny; };
+  auto C = [&](int g, int i) { return fs[g]->cco + size_t(i) * ny; };
   auto launch = [&](SvJobs& js) -> int {
     if (js.n == 0) return RCP_OK;
-    KTimer kt(K_GEMV, s, double(js.n) * f->tiles * TB * TB * sizeof(typename cplx<T>::t));
+    KTimer kt(K_GEMV, s, double(js.n) * f0->tiles * TB * TB * sizeof(typename cplx<T>::t));
     const dim3 grid(4 * nt * js.n);
     switch ((nt + 7) / 8) {
       case 1: k_gemv<T, 1><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
@@ -411,28 +421,33 @@ int run_solve_vec(rcp_factors* f, const double2* rhs, double2* u, int conjop, in
     return RCP_OK;
   };
   // forward sweeps; g_i is known zero while no source block has been passed
-  std::vector<char> zero(N, 0);
+  std::vector<std::vector<char>> zero(B, std::vector<char>(N, 0));
   const int steps = lenL > lenR ? lenL : lenR;
   for (int st = 0; st < steps; ++st) {
     SvJobs js{};
-    if (st < lenL) {
-      int i = st;
-      bool prevz = (i == 0) || zero[i - 1];
-      if (i < nz_lo && prevz) {
-        zero[i] = 1;
-      } else {
-        js.j[js.n++] = SvJob{block_ptr(f, i), U(i), nullptr, Fb(i), prevz ? nullptr : U(i - 1),
-                             i > 0 ? C(i - 1) : nullptr, nullptr, nullptr};
+    for (int g = 0; g < B; ++g) {
+      std::vector<char>& z = zero[g];
+      if (st < lenL) {
+        int i = st;
+        bool prevz = (i == 0) || z[i - 1];
+        if (i < nz_lo[g] && prevz) {
+          z[i] = 1;
+        } else {
+          js.j[js.n++] = SvJob{block_ptr(fs[g], i), U(g, i), nullptr, Fb(g, i),
+                               prevz ? nullptr : U(g, i - 1), i > 0 ? C(g, i - 1) : nullptr,
+                               nullptr, nullptr};
+        }
       }
-    }
-    if (st < lenR) {
-      int i = N - 1 - st;
-      bool prevz = (i == N - 1) || zero[i + 1];
-      if (i > nz_hi && prevz) {
-        zero[i] = 1;
-      } else {
-        js.j[js.n++] = SvJob{block_ptr(f, i), U(i), nullptr, Fb(i), prevz ? nullptr : U(i + 1),
-                             i < N - 1 ? C(i) : nullptr, nullptr, nullptr};
+      if (st < lenR) {
+        int i = N - 1 - st;
+        bool prevz = (i == N - 1) || z[i + 1];
+        if (i > nz_hi[g] && prevz) {
+          z[i] = 1;
+        } else {
+          js.j[js.n++] = SvJob{block_ptr(fs[g], i), U(g, i), nullptr, Fb(g, i),
+                               prevz ? nullptr : U(g, i + 1), i < N - 1 ? C(g, i) : nullptr,
+                               nullptr, nullptr};
+        }
       }
     }
     int rc = launch(js);
@@ -440,30 +455,34 @@ int run_solve_vec(rcp_factors* f, const double2* rhs, double2* u, int conjop, in
   }
   {
     SvJobs js{};
-    SvJob z{block_ptr(f, m), U(m), nullptr, Fb(m), nullptr, nullptr, nullptr, nullptr};
-    if (m - 1 >= 0 && !zero[m - 1]) {
-      z.v1 = U(m - 1);
-      z.c1 = C(m - 1);
+    for (int g = 0; g < B; ++g) {
+      SvJob z{block_ptr(fs[g], m), U(g, m), nullptr, Fb(g, m), nullptr, nullptr, nullptr, nullptr};
+      if (m - 1 >= 0 && !zero[g][m - 1]) {
+        z.v1 = U(g, m - 1);
+        z.c1 = C(g, m - 1);
+      }
+      if (m + 1 < N && !zero[g][m + 1]) {
+        z.v2 = U(g, m + 1);
+        z.c2 = C(g, m);
+      }
+      js.j[js.n++] = z;
     }
-    if (m + 1 < N && !zero[m + 1]) {
-      z.v2 = U(m + 1);
-      z.c2 = C(m);
-    }
-    js.j[js.n++] = z;
     int rc = launch(js);
     if (rc) return rc;
   }
   for (int st = 0; st < steps; ++st) {
     SvJobs js{};
-    if (st < lenL) {
-      int i = m - 1 - st;
-      js.j[js.n++] = SvJob{block_ptr(f, i), U(i), zero[i] ? nullptr : U(i), nullptr, U(i + 1), C(i),
-                           nullptr, nullptr};
-    }
-    if (st < lenR) {
-      int i = m + 1 + st;
-      js.j[js.n++] = SvJob{block_ptr(f, i), U(i), zero[i] ? nullptr : U(i), nullptr, U(i - 1),
-                           C(i - 1), nullptr, nullptr};
+    for (int g = 0; g < B; ++g) {
+      if (st < lenL) {
+        int i = m - 1 - st;
+        js.j[js.n++] = SvJob{block_ptr(fs[g], i), U(g, i), zero[g][i] ? nullptr : U(g, i), nullptr,
+                             U(g, i + 1), C(g, i), nullptr, nullptr};
+      }
+      if (st < lenR) {
+        int i = m + 1 + st;
+        js.j[js.n++] = SvJob{block_ptr(fs[g], i), U(g, i), zero[g][i] ? nullptr : U(g, i), nullptr,
+                             U(g, i - 1), C(g, i - 1), nullptr, nullptr};
+      }
     }
     int rc = launch(js);
     if (rc) return rc;
@@ -475,10 +494,17 @@ int run_solve_vec(rcp_factors* f, const double2* rhs, double2* u, int conjop, in
 
 namespace rcp {
 
+int solve_vec_batch(rcp_factors* const* fs, int B, const double2* const* rhs, double2* const* u,
+                    int conjop, const int* nz_lo, const int* nz_hi, hipStream_t s) {
+  if (B < 1 || B > MAX_BATCH) return fail(RCP_EINVAL, "batch of 1 to 8 factor sets");
+  if (fs[0]->precision == RCP_FP64)
+    return run_solve_vec<double>(fs, B, rhs, u, conjop, nz_lo, nz_hi, s);
+  return run_solve_vec<float>(fs, B, rhs, u, conjop, nz_lo, nz_hi, s);
+}
+
 int solve_vec(rcp_factors* f, const double2* rhs, double2* u, int conjop, int nz_lo, int nz_hi,
               hipStream_t s) {
-  if (f->precision == RCP_FP64) return run_solve_vec<double>(f, rhs, u, conjop, nz_lo, nz_hi, s);
-  return run_solve_vec<float>(f, rhs, u, conjop, nz_lo, nz_hi, s);
+  return solve_vec_batch(&f, 1, &rhs, &u, conjop, &nz_lo, &nz_hi, s);
 }
 
 int residual_norms(rcp_factors* f, const double2* b, const double2* x, double2* r, int conjop,

@@ -79,7 +79,7 @@ def test_batch_rejects_mismatched_grids_on_host():
     outs = (C.c_void_p * 2)()
     rc = lib.rcp_factor_batch(2, grids, 0, bufs, 1 << 40, None, outs)
     assert rc == _lib.RCP_EINVAL and b"identical" in lib.rcp_last_error()
-    rc = lib.rcp_factor_batch(5, grids, 0, bufs, 1 << 40, None, outs)
+    rc = lib.rcp_factor_batch(9, grids, 0, bufs, 1 << 40, None, outs)   # count checked first
     assert rc == _lib.RCP_EINVAL
 
 
@@ -93,3 +93,16 @@ def test_null_handles_are_rejected():
     assert lib.rcp_adjoint_grad(None, C.byref(o), C.byref(lt), None, None, None) == _lib.RCP_EINVAL
     assert lib.rcp_solve_multi_rhs(None, 1, None, None, 0, 0.0, 0, None, None) == _lib.RCP_EINVAL
     assert lib.rcp_brute_force_work_bytes(None, 10, 10) == 0
+
+
+def test_adjoint_batch_argument_checks():
+    from paper_2207_10701_amd import _lib
+    lib = _lib.lib
+    o = (_lib.Objective * 1)()
+    lt = (_lib.Light * 1)()
+    for count in (0, 9):
+        assert lib.rcp_adjoint_grad_batch(count, None, o, lt, None, None, None) == _lib.RCP_EINVAL
+    handles = (C.c_void_p * 1)(None)
+    grads = (C.c_void_p * 1)(None)
+    rc = lib.rcp_adjoint_grad_batch(1, handles, o, lt, C.c_void_p(0x1000), grads, None)
+    assert rc == _lib.RCP_EINVAL and b"NULL" in lib.rcp_last_error()

@@ -154,3 +154,60 @@ def test_factor_batch_matches_single_and_oracle(rcp):
         ref = ora.reciprocal(oracle_setup(p))
         assert abs(fb - ref) / ref < 1e-10
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("count", [5, 8])
+def test_factor_batch_up_to_eight_geometries(rcp, count):
+    """Ten chains (plain workgroup split) and sixteen (two chains per XCD) in one
+    launch: each geometry bit-identical to its own factorisation."""
+    import torch
+    from dataclasses import replace
+    base = PROBLEMS["conc_cone"]
+    probs = [replace(base, widths=W.seeded_widths(len(base.widths), 400 + g)) for g in range(count)]
+    eps = [rcp.eps_from_widths(p, device="cuda") for p in probs]
+    facs = rcp.factor_batch(probs, eps)
+    Fb = [rcp.reciprocal_average(f, p).item() for f, p in zip(facs, probs)]
+    for g in (0, count // 2, count - 1):
+        single = rcp.Factors(probs[g], eps[g])
+        assert rcp.reciprocal_average(single, probs[g]).item() == Fb[g]
+    ref = ora.reciprocal(oracle_setup(probs[-1]))
+    assert abs(Fb[-1] - ref) / ref < 1e-10
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("count", [3, 8])
+def test_adjoint_batch_matches_single(rcp, count):
+    """Batched adjoint (solves of all sets in the same launches) is bit-identical
+    to one adjoint per factor set; mixed objectives and lights in one batch."""
+    from dataclasses import replace
+    base = PROBLEMS["conc_cone"]
+    probs = [replace(base, widths=W.seeded_widths(len(base.widths), 500 + g),
+                     c=base.c * (1.0 + 0.1 * g)) for g in range(count)]
+    eps = [rcp.eps_from_widths(p, device="cuda") for p in probs]
+    facs = rcp.factor_batch(probs, eps)
+    Fb, gb = rcp.adjoint_grad_batch(facs, probs)
+    for g in range(count):
+        F1, g1 = rcp.adjoint_grad(facs[g], probs[g])
+        assert Fb[g].item() == F1.item()
+        assert torch_equal(gb[g], g1)
+    ref = ora.adjoint(oracle_setup(probs[-1]))
+    assert abs(Fb[-1].item() - ref.F) / abs(ref.F) < 1e-10
+    assert rel(gb[-1].cpu().numpy(), ref.grad_eps) < 1e-9
+
+
+def test_adjoint_batch_refined_fp32_falls_back_per_set(rcp):
+    base = PROBLEMS["coll_annulus"]
+    from dataclasses import replace
+    probs = [replace(base, widths=W.seeded_widths(len(base.widths), 600 + g)) for g in range(2)]
+    eps = [rcp.eps_from_widths(p, device="cuda") for p in probs]
+    facs = rcp.factor_batch(probs, eps, rcp.RCP_FP32_REFINED)
+    Fb, gb = rcp.adjoint_grad_batch(facs, probs)
+    for g in range(2):
+        F1, g1 = rcp.adjoint_grad(facs[g], probs[g])
+        assert Fb[g].item() == F1.item()
+        assert torch_equal(gb[g], g1)
+
+
+def torch_equal(a, b):
+    import torch
+    return bool(torch.equal(a, b))
