@@ -59,13 +59,13 @@ DESCR = {
 
 # HBM traffic of the dominant kernel, k_gj_fused<double>, per launch, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) over one default step
-# (config2, four geometries per step), scaled by what the same counters read for
-# a 1 GiB copy (python bench.py --calibrate-copy).  Valid only for the kernel
-# source it was measured on: reported when factor.hip still has this hash.
-TRAFFIC = {"config": "config2", "batch": 4,
-           "sha256": "32d10f591c412cfb642c450fd6be225b3eb03790828bca8aa7a91b5cf2e98bd6",
-           "fetch_bytes": 85610995,     # 41803.4 KiB FETCH_SIZE x 1.99995
-           "write_bytes": 82313523}     # 80384.3 KiB WRITE_SIZE x 1.0
+# (config2, eight geometries per step), scaled by what the same counters read
+# for a 1 GiB copy (python bench.py --calibrate-copy).  Valid only for the
+# kernel source it was measured on: reported when factor.hip still has this hash.
+TRAFFIC = {"config": "config2", "batch": 8,
+           "sha256": "7c5d1a19ac45a3d1b0455787350a2926430a2c2f69350f916463da59b6899db9",
+           "fetch_bytes": 179057934,     # 87433.0 KiB FETCH_SIZE x 1.99995
+           "write_bytes": 164626944}    # 160768.5 KiB WRITE_SIZE x 1.0
 
 
 def factor_source_sha256():

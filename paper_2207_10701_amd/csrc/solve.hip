@@ -31,8 +31,12 @@ struct SvJob {
   const double2* v2;
   const double2* c2;
 };
+// Job table of a launch: the left and right chain step of each factor set; two
+// entries for one set, 2 MAX_BATCH for batches (the table is a kernel argument,
+// so a single solve does not carry the batch-sized one).
+template <int NJ>
 struct SvJobs {
-  SvJob j[2 * MAX_BATCH];   // left and right chain of each factor set
+  SvJob j[NJ];
   int n;
 };
 
@@ -53,8 +57,8 @@ __device__ __forceinline__ double2 maybe_conj(double2 a, int c) {
 // memory latency covers the step.  Partial sums are combined in a fixed
 // order: the result does not depend on scheduling.
 // MT = tiles per wave = ceil(nt / 8) (nt <= 64, np <= 2048).
-template <typename T, int MT>
-__global__ __launch_bounds__(512) void k_gemv(SvJobs jobs, int nt, int ny, int conjop) {
+template <typename T, int MT, int NJ>
+__global__ __launch_bounds__(512) void k_gemv(SvJobs<NJ> jobs, int nt, int ny, int conjop) {
   using T2 = typename cplx<T>::t;
   __shared__ double2 g[NPMAX];
   __shared__ double2 redd[8][8];
@@ -63,14 +67,20 @@ __global__ __launch_bounds__(512) void k_gemv(SvJobs jobs, int nt, int ny, int c
   const int ji = blockIdx.x / per_job, rem = blockIdx.x % per_job;
   const int I = rem >> 2, r0 = (rem & 3) * 8;
   SvJob jb;
-  jb.X = RCP_SEL16(jobs, ji, X);
-  jb.out = RCP_SEL16(jobs, ji, out);
-  jb.base = RCP_SEL16(jobs, ji, base);
-  jb.f = RCP_SEL16(jobs, ji, f);
-  jb.v1 = RCP_SEL16(jobs, ji, v1);
-  jb.c1 = RCP_SEL16(jobs, ji, c1);
-  jb.v2 = RCP_SEL16(jobs, ji, v2);
-  jb.c2 = RCP_SEL16(jobs, ji, c2);
+  if constexpr (NJ == 2) {
+    jb = jobs.j[0];
+    if (ji == 1) jb = jobs.j[1];
+  } else {
+    static_assert(NJ == 16, "job tables of 2 or 16 entries");
+    jb.X = RCP_SEL16(jobs, ji, X);
+    jb.out = RCP_SEL16(jobs, ji, out);
+    jb.base = RCP_SEL16(jobs, ji, base);
+    jb.f = RCP_SEL16(jobs, ji, f);
+    jb.v1 = RCP_SEL16(jobs, ji, v1);
+    jb.c1 = RCP_SEL16(jobs, ji, c1);
+    jb.v2 = RCP_SEL16(jobs, ji, v2);
+    jb.c2 = RCP_SEL16(jobs, ji, c2);
+  }
   const int tid = threadIdx.x;
   const T2* X = static_cast<const T2*>(jb.X);
   const int wave = tid >> 6, lane = tid & 63;
@@ -393,9 +403,10 @@ __global__ void k_axpy(size_t n, const double2* __restrict__ dx, double2* __rest
 
 // Forward and back sweeps of B factor sets of identical shape in lockstep:
 // every launch carries the left and right chain step of each set.
-template <typename T>
+template <typename T, int NJ>
 int run_solve_vec(rcp_factors* const* fs, int B, const double2* const* rhs, double2* const* u,
                   int conjop, const int* nz_lo, const int* nz_hi, hipStream_t s) {
+  using SvJobs = ::SvJobs<NJ>;
   const rcp_factors* f0 = fs[0];
   const int N = f0->nx, ny = f0->ny, nt = f0->nt, m = f0->m;
   if (f0->np > NPMAX) return fail(RCP_EINVAL, "block size too large for the vector sweep");
@@ -408,14 +419,14 @@ int run_solve_vec(rcp_factors* const* fs, int B, const double2* const* rhs, doub
     KTimer kt(K_GEMV, s, double(js.n) * f0->tiles * TB * TB * sizeof(typename cplx<T>::t));
     const dim3 grid(4 * nt * js.n);
     switch ((nt + 7) / 8) {
-      case 1: k_gemv<T, 1><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
-      case 2: k_gemv<T, 2><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
-      case 3: k_gemv<T, 3><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
-      case 4: k_gemv<T, 4><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
-      case 5: k_gemv<T, 5><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
-      case 6: k_gemv<T, 6><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
-      case 7: k_gemv<T, 7><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
-      default: k_gemv<T, 8><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+      case 1: k_gemv<T, 1, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+      case 2: k_gemv<T, 2, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+      case 3: k_gemv<T, 3, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+      case 4: k_gemv<T, 4, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+      case 5: k_gemv<T, 5, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+      case 6: k_gemv<T, 6, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+      case 7: k_gemv<T, 7, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+      default: k_gemv<T, 8, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
     }
     RCP_HIP(hipGetLastError());
     return RCP_OK;
@@ -497,9 +508,12 @@ namespace rcp {
 int solve_vec_batch(rcp_factors* const* fs, int B, const double2* const* rhs, double2* const* u,
                     int conjop, const int* nz_lo, const int* nz_hi, hipStream_t s) {
   if (B < 1 || B > MAX_BATCH) return fail(RCP_EINVAL, "batch of 1 to 8 factor sets");
-  if (fs[0]->precision == RCP_FP64)
-    return run_solve_vec<double>(fs, B, rhs, u, conjop, nz_lo, nz_hi, s);
-  return run_solve_vec<float>(fs, B, rhs, u, conjop, nz_lo, nz_hi, s);
+  const bool fp64 = fs[0]->precision == RCP_FP64;
+  if (B == 1)
+    return fp64 ? run_solve_vec<double, 2>(fs, B, rhs, u, conjop, nz_lo, nz_hi, s)
+                : run_solve_vec<float, 2>(fs, B, rhs, u, conjop, nz_lo, nz_hi, s);
+  return fp64 ? run_solve_vec<double, 2 * MAX_BATCH>(fs, B, rhs, u, conjop, nz_lo, nz_hi, s)
+              : run_solve_vec<float, 2 * MAX_BATCH>(fs, B, rhs, u, conjop, nz_lo, nz_hi, s);
 }
 
 int solve_vec(rcp_factors* f, const double2* rhs, double2* u, int conjop, int nz_lo, int nz_hi,
