@@ -63,9 +63,9 @@ DESCR = {
 # for a 1 GiB copy (python bench.py --calibrate-copy).  Valid only for the
 # kernel source it was measured on: reported when factor.hip still has this hash.
 TRAFFIC = {"config": "config2", "batch": 8,
-           "sha256": "7c5d1a19ac45a3d1b0455787350a2926430a2c2f69350f916463da59b6899db9",
-           "fetch_bytes": 179057934,     # 87433.0 KiB FETCH_SIZE x 1.99995
-           "write_bytes": 164626944}    # 160768.5 KiB WRITE_SIZE x 1.0
+           "sha256": "95be34a430f2ec042b5d983fb0e56cc1b781aa5d1aee43ea5462e666789f6941",
+           "fetch_bytes": 177578401,     # 86710.8 KiB FETCH_SIZE x 1.99994
+           "write_bytes": 164626944}    # 160768.5 KiB WRITE_SIZE x 1.00000
 
 
 def factor_source_sha256():

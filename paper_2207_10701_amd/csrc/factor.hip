@@ -456,8 +456,8 @@ __device__ void update_work(const GJJob& jb, int wg, size_t tiles, int skip) {
   tile_update_pipelined<T>(dst, Q + size_t(I) * TB * TB, L + size_t(J) * TB * TB, sg, lr, lk);
 }
 
-// Look-ahead for panel Kn = k + 1, one workgroup per row tile I, one wave per
-// 16 x 16 quadrant (qa, qb):
+// Look-ahead for panel Kn = k + 1.  Workgroup g handles the R row tiles
+// I = g R .. g R + R - 1, one wave per 16 x 16 quadrant (qa, qb):
 //  1. the two 16 x 16 blocks (a', qa), a' = 0, 1, of L_{Kn}[I]^T
 //     after update k, in accumulator layout:
 //       I >  Kn: S(I,Kn)^T - L_k[Kn] Q_k[I]^T
@@ -466,8 +466,10 @@ __device__ void update_work(const GJJob& jb, int wg, size_t tiles, int skip) {
 //     these registers are rows 16 qa .. 16 qa + 15 of L_{Kn}[I], i.e. the left
 //     operand of Q = L P, without a transpose;
 //  2. quadrant (qa, qb) of the updated pivot block S(Kn,Kn) - Q_k[Kn] L_k[Kn]^T
-//     into LDS; 3. invert it (all waves); 4. quadrant (qa, qb) of
+//     into LDS; 3. invert it (all waves); 4. per row tile, quadrant (qa, qb) of
 //     Q_{Kn}[I] = L_{Kn}[I] P.
+// Every look-ahead workgroup of a chain inverts the same pivot block: R = 2
+// halves those redundant inversions when sixteen chains share the GPU.
 template <typename T>
 __device__ __forceinline__ void lt_row(const GJJob& jb, int I, typename v4of<T>::t (*cre)[2],
                                        typename v4of<T>::t (*cim)[2], int lr, int lk, int qa,
@@ -549,8 +551,8 @@ __device__ __forceinline__ void q_row(const GJJob& jb, int I, const typename v4o
   }
 }
 
-template <typename T>
-__device__ void lookahead_work(const GJJob& jb, int I, int nt, double2 (*Ps)[TB + 1],
+template <typename T, int R>
+__device__ void lookahead_work(const GJJob& jb, int g, int nt, double2 (*Ps)[TB + 1],
                                double2 (*xrow)[TB], double2 (*xcol)[TB]) {
   using T2 = typename cplx<T>::t;
   using V4 = typename v4of<T>::t;
@@ -561,9 +563,12 @@ __device__ void lookahead_work(const GJJob& jb, int I, int nt, double2 (*Ps)[TB 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 15, lk = lane >> 4;
   const int qa = wave >> 1, qb = wave & 1;
-  const bool active = I < nt && I != Kn;
-  V4 cre[2][2], cim[2][2];   // [a'][0] used
-  if (active) lt_row<T>(jb, I, cre, cim, lr, lk, qa, qb);
+  V4 cre[R][2][2], cim[R][2][2];   // per row tile: [a'][0] used
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int I = g * R + r;
+    if (I < nt && I != Kn) lt_row<T>(jb, I, cre[r], cim[r], lr, lk, qa, qb);
+  }
   {  // quadrant (qa, qb) of the updated pivot block
     V4 dre[2][2], dim[2][2];
     const T2* S = X + tile_index(Kn, Kn) * TB * TB + (16 * qa) * TB + 16 * qb;
@@ -582,11 +587,15 @@ __device__ void lookahead_work(const GJJob& jb, int I, int nt, double2 (*Ps)[TB 
   }
   __syncthreads();
   const double minpiv = invert_pivot_block(Ps, xrow, xcol);
-  if (I == 0) {
+  if (g == 0) {
     for (int e = tid; e < TB * TB; e += 256) jb.Pn[e] = Ps[e / TB][e % TB];
     if (tid == 0) *jb.health = minpiv;
   }
-  if (active) q_row<T>(jb, I, cre, cim, Ps, lr, lk, qa, qb);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int I = g * R + r;
+    if (I < nt && I != Kn) q_row<T>(jb, I, cre[r], cim[r], Ps, lr, lk, qa, qb);
+  }
 }
 
 // Workgroup -> (job q, index w within the job).  Workgroups are dealt to the 8
@@ -635,10 +644,10 @@ __global__ __launch_bounds__(256) void k_gj_update(GJJobs jobs, size_t tiles) {
   update_work<T>(jb, wg, tiles, -1);
 }
 
-// Update k outside column k+1, plus the look-ahead panel k+1.  Within each job
-// the look-ahead workgroups come first, so that they are dispatched first:
-// they carry the launch's critical path.
-template <typename T>
+// Update k outside column k+1, plus the look-ahead panel k+1 (R row tiles per
+// look-ahead workgroup).  Within each job the look-ahead workgroups come first,
+// so that they are dispatched first: they carry the launch's critical path.
+template <typename T, int R>
 __global__ __launch_bounds__(256, 2) void k_gj_fused(GJJobs jobs, int nt, size_t tiles) {
   __shared__ double2 Ps[TB][TB + 1];
   __shared__ double2 xrow[4][TB], xcol[4][TB];
@@ -648,7 +657,7 @@ __global__ __launch_bounds__(256, 2) void k_gj_fused(GJJobs jobs, int nt, size_t
   int tmp = q * jobs.j[0].wgs + w;
   GJJob jb = pick(jobs, &tmp);
   if (w < look)
-    lookahead_work<T>(jb, w, nt, Ps, xrow, xcol);
+    lookahead_work<T, R>(jb, w, nt, Ps, xrow, xcol);
   else
     update_work<T>(jb, w - look, tiles, jb.k + 1);
 }
@@ -762,7 +771,10 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s) {
       k_gj_panel<T><<<grid_size(nch, pan_wgs), 256, 0, s>>>(js, nt);
       RCP_HIP(hipGetLastError());
     }
-    const int look_wgs = nt;   // look-ahead: one row tile per workgroup
+    // look-ahead row tiles per workgroup: two when sixteen chains share the GPU
+    // (84 -> 76 us per launch on 1080-row blocks), otherwise one (shortest chain)
+    const int R = nch >= 16 ? 2 : 1;
+    const int look_wgs = ceil_div(nt, R);
     for (int k = 0; k + 1 < nt; ++k) {
       GJJobs js{};
       for (int q = 0; q < nch; ++q) {
@@ -773,7 +785,10 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s) {
       }
       KTimer kt(K_GJ_UPDATE, s, nch * cmac * double(tiles));
       const int grid = grid_size(nch, upd_wgs + look_wgs);
-      k_gj_fused<T><<<grid, 256, 0, s>>>(js, nt, tiles);
+      if (R == 1)
+        k_gj_fused<T, 1><<<grid, 256, 0, s>>>(js, nt, tiles);
+      else
+        k_gj_fused<T, 2><<<grid, 256, 0, s>>>(js, nt, tiles);
       RCP_HIP(hipGetLastError());
     }
     {   // final update, negated
