@@ -63,7 +63,7 @@ DESCR = {
 # for a 1 GiB copy (python bench.py --calibrate-copy).  Valid only for the
 # kernel source it was measured on: reported when factor.hip still has this hash.
 TRAFFIC = {"config": "config2", "batch": 8,
-           "sha256": "95be34a430f2ec042b5d983fb0e56cc1b781aa5d1aee43ea5462e666789f6941",
+           "sha256": "dcc12a879e35d5b786b8a9aed3bf6a7c05a33cc822517d12aece1de7a857f489",
            "fetch_bytes": 177578401,     # 86710.8 KiB FETCH_SIZE x 1.99994
            "write_bytes": 164626944}    # 160768.5 KiB WRITE_SIZE x 1.00000
 

@@ -285,25 +285,6 @@ __device__ __forceinline__ void tile_update_pipelined(typename cplx<T>::t* dst,
       }
 }
 
-// Load a stored tile into accumulators, transposed if tr (acc(i, j) = S(j, i)).
-template <typename T>
-__device__ __forceinline__ void tile_load_acc(typename v4of<T>::t (*cre)[2],
-                                              typename v4of<T>::t (*cim)[2],
-                                              const typename cplx<T>::t* S, bool tr, int lr,
-                                              int lk) {
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = 16 * a + mfma_row<T>(lk, q), j = 16 * b + lr;
-        typename cplx<T>::t v = tr ? S[j * TB + i] : S[i * TB + j];
-        cre[a][b][q] = v.x;
-        cim[a][b][q] = v.y;
-      }
-}
-
 template <typename T>
 __device__ __forceinline__ void tile_store_acc(typename v4of<T>::t (*cre)[2],
                                                typename v4of<T>::t (*cim)[2],
