@@ -126,3 +126,73 @@ def test_config2_matches_oracle_at_full_size(rcp):
     assert np.linalg.norm(zg - ref.z) / np.linalg.norm(ref.z) < 1e-10
     assert abs(F.item() - ref.F) / ref.F < 1e-10
     assert np.linalg.norm(gg - ref.grad_eps) / np.linalg.norm(ref.grad_eps) < 1e-9
+
+
+@pytest.mark.timeout(900)
+def test_config3_refined_fp32_vs_fp64_and_oracle(rcp):
+    """Collimator, annulus 10-30 deg and mirror (4040 x 440): complex-FP32 factors with
+    FP64 refinement against the FP64 path (field 1e-8, F 1e-6), FP64 F against the
+    oracle (1e-10)."""
+    import torch
+    p = W.config3()
+    eps = rcp.eps_from_widths(p)
+    f64 = rcp.Factors(p, eps)
+    F64, z64 = rcp.reciprocal_average(f64, p, want_z=True)
+    f32 = rcp.Factors(p, eps, rcp.RCP_FP32_REFINED)
+    F32, z32 = rcp.reciprocal_average(f32, p, want_z=True)
+    iters, res = f32.last_solve_stats()
+    assert iters >= 1 and res <= 1e-12
+    zerr = (torch.linalg.vector_norm(z32 - z64) / torch.linalg.vector_norm(z64)).item()
+    assert zerr < 1e-8
+    assert abs(F32.item() - F64.item()) / F64.item() < 1e-6
+    Fo = ora.reciprocal(ora.setup(p))
+    assert abs(F64.item() - Fo) / Fo < 1e-10
+
+
+def test_config4_large_gradients_match_central_differences(rcp):
+    """Adjoint step at scale (2040 x 440): dF/dwidth on 20 seeded pillars and dF/deps
+    on 20 seeded pixels of the 100 x 10 wavelength region above the substrate,
+    against central differences (relative 1e-5); finite-difference geometries are
+    factored eight at a time."""
+    import torch
+    from dataclasses import replace
+    p = W.config4_large()
+    rng = np.random.default_rng(1014)
+    eps0 = rcp.eps_from_widths(p)
+    fac = rcp.Factors(p, eps0)
+    F0, g = rcp.adjoint_grad(fac, p)
+    gw = rcp.width_grad(p, g).cpu().numpy()
+    gd = g.cpu().numpy()
+    del fac
+    # perturbed geometries: +-dw on each of 20 widths, +-de on each of 20 pixels
+    dw, de = 1e-6, 1e-4   # widths: pillar edges stay inside their cells; pixels: smooth in eps
+    wsel = rng.choice(len(p.widths), 20, replace=False)
+    i0, i1 = p.aperture
+    rows = np.arange(p.sub_rows, p.sub_rows + 200)
+    pix = [(int(rng.integers(i0, i1)), int(rng.choice(rows))) for _ in range(20)]
+    cases = []
+    for k in wsel:
+        for sgn in (1, -1):
+            w = np.array(p.widths, dtype=np.float64)
+            w[k] += sgn * dw
+            q = replace(p, widths=tuple(w))
+            cases.append((q, rcp.eps_from_widths(q)))
+    for (i, j) in pix:
+        for sgn in (1, -1):
+            e = eps0.clone()
+            e[i, j] += sgn * de
+            cases.append((p, e))
+    F = []
+    for b in range(0, len(cases), 8):
+        chunk = cases[b:b + 8]
+        facs = rcp.factor_batch([c[0] for c in chunk], [c[1] for c in chunk])
+        F += [rcp.reciprocal_average(f, c[0]).item() for f, c in zip(facs, chunk)]
+        del facs
+        torch.cuda.synchronize()
+    F = np.array(F)
+    fd_w = (F[0:40:2] - F[1:40:2]) / (2 * dw)
+    fd_e = (F[40::2] - F[41::2]) / (2 * de)
+    ad_w = gw[wsel]
+    ad_e = np.array([gd[i, j] for i, j in pix])
+    assert np.linalg.norm(fd_w - ad_w) / np.linalg.norm(ad_w) < 1e-5
+    assert np.linalg.norm(fd_e - ad_e) / np.linalg.norm(ad_e) < 1e-5
