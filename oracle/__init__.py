@@ -14,11 +14,15 @@ large-area metasurfaces for incoherent light"):
                (Sec. "Reciprocal approach": u = A^{-1} b, FOM |w^dag u|^2).
 * ``light``    the mean-square amplitude alpha(theta) and the equivalent-current
                cross-correlation C(Delta) (Sec. "Incoherent light", Eq. 3-4 and
-               the annulus formula of Sec. "Designs").
+               the annulus formula of Sec. "Designs"), and W of a finite
+               ensemble of correlated planewaves (Eq. 1 and 3 as sums).
 * ``average``  the brute-force angle average of Eq. 6 by Gauss-Legendre
                quadrature over forward solves, the reciprocal average of Eq. 7 by
                a direct O(M^2) double sum (no FFT), and the adjoint gradient of
-               Sec. "Reciprocal approach".
+               Sec. "Reciprocal approach"; the same for any (non-Toeplitz)
+               correlation W and several outputs on the same factors, and the
+               forward average of Eq. 5 over a finite ensemble of correlated
+               planewaves.
 
 All arithmetic is float64 / complex128; sparse solves use SciPy's SuperLU.
 """

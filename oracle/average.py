@@ -17,6 +17,12 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
                     line: grad v = -P A^{-dag} (grad A^dag) z.  With
                     lambda = A^{-1} P^T (W v) and dA = k^2 s_x s_y deps e_q e_q^T
                     this gives dF/deps_q = -2 k^2 Re(conj(lambda_q) conj(s_x s_y) z_q).
+* ``reciprocal_dense`` / ``adjoint_dense``
+                    Eq. 7 for any Hermitian W (plain dense product) and K outputs
+                    w_k on the same factors, and the gradient of sum_k F_k.
+* ``brute_force_ensemble``
+                    Eq. 5 for a finite ensemble of planewaves with amplitude
+                    correlation C_qq': one forward solve per planewave.
 
 Because A = A^T, A^{-dag} w = conj(A^{-1} conj(w)): the reciprocal problem is the
 forward problem with the conjugated objective as its source (a point source at
@@ -144,3 +150,87 @@ def width_gradient(p: Problem, grad_eps: np.ndarray, widths=None) -> np.ndarray:
         il, ir = edge_cells(p, xc, w)
         out[k] = d * (grad_eps[il, rows].sum() + grad_eps[ir, rows].sum())
     return out
+
+
+# ---------------------------------------------------------------------------
+# Any correlation W and many outputs
+#
+# Eq. 7 holds for any current correlation W (Sec. "Incoherent light": the
+# reciprocal technique also covers arbitrarily correlated light), with W v a
+# dense product when W is not Toeplitz.  Several outputs w_k (focal spots or
+# output modes, Sec. "Concluding remarks": averages over many spots or modes)
+# take one reciprocal solve each on the same factors; their averages add up to
+# the trace form sum_k v_k^dag W v_k = Tr(V^dag W V).
+# ---------------------------------------------------------------------------
+
+def reciprocal_fields(s: Solved, outputs) -> np.ndarray:
+    """z_k = A^{-dag} w_k for each output (N x K), one reciprocal solve each."""
+    Wo = np.stack([fdfd.objective_vector(o) for o in outputs], axis=1)
+    return np.conj(s.solve(np.conj(Wo)))
+
+
+def reciprocal_dense(s: Solved, outputs, W: np.ndarray):
+    """F_k = v_k^dag W v_k (real part; W Hermitian), v_k = z_k on the line.
+
+    Returns (F, V): F has the K per-output averages, V is M x K.
+    """
+    Z = reciprocal_fields(s, outputs)
+    V = Z[fdfd.aperture_indices(s.p), :]
+    F = np.array([quadratic_form(V[:, k], W).real for k in range(V.shape[1])])
+    return F, V
+
+
+def brute_force_ensemble(s: Solved, outputs, thetas, C) -> np.ndarray:
+    """Eq. 5 for a finite ensemble: F_k = sum_qq' C_qq' (w_k^dag u_q) conj(w_k^dag u_q').
+
+    One forward solve u_q = A^{-1} b0(theta_q) per planewave of the ensemble.
+    """
+    U = forward_fields(s, thetas)
+    C = np.asarray(C, dtype=np.complex128)
+    F = []
+    for o in outputs:
+        g = fdfd.objective_vector(o).conj() @ U
+        F.append(np.sum(C * g[:, None] * np.conj(g)[None, :]).real)
+    return np.array(F)
+
+
+def coherent_superposition(s: Solved, outputs, thetas, a) -> np.ndarray:
+    """|w_k^dag u|^2 for the deterministic field u = A^{-1} sum_q a_q b0(theta_q)."""
+    b = fdfd.planewave_sources(s.p, thetas) @ np.asarray(a, dtype=np.complex128)
+    u = s.solve(b)
+    return np.array([abs(np.vdot(fdfd.objective_vector(o), u)) ** 2 for o in outputs])
+
+
+@dataclass
+class DenseGradient:
+    F: np.ndarray               # per-output averages, K
+    V: np.ndarray               # reciprocal fields on the line, M x K
+    Y: np.ndarray               # W V, M x K
+    grad_eps: np.ndarray        # d(sum_k F_k)/deps, nx x ny
+    grad_widths: np.ndarray
+
+
+def adjoint_dense(s: Solved, outputs, W: np.ndarray) -> DenseGradient:
+    """Gradient of sum_k F_k: the single-output adjoint summed over the outputs.
+
+    Per output lambda_k = A^{-1} P^T (W v_k) and
+    dF_k/deps_q = -2 k^2 Re(conj(lambda_kq) conj(s_x s_y)_q z_kq).
+    """
+    p = s.p
+    Z = reciprocal_fields(s, outputs)
+    idx = fdfd.aperture_indices(p)
+    V = Z[idx, :]
+    Y = W @ V
+    F = np.array([complex(np.vdot(V[:, k], Y[:, k])).real for k in range(V.shape[1])])
+    rhs = np.zeros((p.nx * p.ny, V.shape[1]), dtype=np.complex128)
+    rhs[idx, :] = Y
+    Lam = s.solve(rhs)
+    sxc, _, syc, _ = fdfd.stretches(p)
+    sxsy = (sxc[:, None] * syc[None, :]).ravel()
+    k2 = fdfd.k0(p) ** 2
+    g = np.zeros(p.nx * p.ny)
+    for k in range(V.shape[1]):
+        g += -2.0 * k2 * np.real(np.conj(Lam[:, k]) * np.conj(sxsy) * Z[:, k])
+    grad_eps = g.reshape(p.nx, p.ny)
+    return DenseGradient(F=F, V=V, Y=Y, grad_eps=grad_eps,
+                         grad_widths=width_gradient(p, grad_eps))

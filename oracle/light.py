@@ -137,3 +137,16 @@ def toeplitz_from_quadrature(p: Problem, thetas, weights) -> np.ndarray:
     B = fdfd.planewave_sources(p, thetas)[fdfd.aperture_indices(p), :]
     wa = np.asarray(weights) * alpha(p, thetas)
     return (B * wa[None, :]) @ B.conj().T
+
+
+def ensemble_correlation(p: Problem, thetas, C) -> np.ndarray:
+    """W on the incidence line for a finite ensemble of planewaves (Eq. 1 and 3 as sums).
+
+    Light made of planewaves at angles theta_q with random amplitudes a_q,
+    C_qq' = <a_q conj(a_q')>, has the equivalent current b = sum_q a_q b0_q, so
+    W = <b b^dag> = sum_qq' C_qq' b0_q b0_q'^dag: W_jl = (B C B^dag)_jl with
+    column q of B the unit-power source b0(theta_q) on the line.  Any Hermitian
+    C is allowed; for C diagonal this is the Toeplitz T of a quadrature rule.
+    """
+    B = fdfd.planewave_sources(p, thetas)[fdfd.aperture_indices(p), :]
+    return B @ np.asarray(C, dtype=np.complex128) @ B.conj().T

@@ -3,8 +3,9 @@
 This module holds only *inputs*: grid sizes, cell indices of rows and points,
 pillar centres and seeded widths, light-distribution parameters and seeded
 request streams.  It contains none of the method's arithmetic (no permittivity
-map, no PML, no operator, no sources, no correlation functions); each side
-computes those from these numbers on its own.
+map, no PML, no operator, no sources, no current correlations W); each side
+computes those from these numbers on its own.  The amplitude statistics of a
+light ensemble (which angles, how their random amplitudes correlate) are inputs.
 
 The shapes follow the paper's setting (Sec. "Designs": a single layer of
 dielectric pillars of sub-wavelength period on a substrate, concentrator /
@@ -22,6 +23,10 @@ to the synthetic configurations below:
                 (2040 x 440 cells).
 * ``serving_stream`` Poisson arrivals of concentrator / collimator requests of
                 random width and depth.
+* ``output_set`` / ``ensemble_angles`` / ``gaussian_correlated_amplitudes``
+                many outputs of one evaluation (focal spots and output modes)
+                and a finite ensemble of planewaves with correlated amplitudes
+                (light that is not translation invariant).
 
 Units: vacuum wavelength 1, grid step h = 1/20.  Cell (i, j) has its centre at
 x = (i - npml + 1/2) h, y = (j - npml + 1/2) h, origin at the lower-left corner
@@ -187,6 +192,78 @@ def seeded_cells(p: Problem, count: int, seed: int,
 def complex_normal(shape, seed: int, dtype=np.complex128) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(dtype)
+
+
+# ----------------------------------------------------------------------------
+# Many outputs and correlated light (inputs only)
+# ----------------------------------------------------------------------------
+
+def output_set(p: Problem, n_spots: int, n_modes: int = 0, seed: int = 3001) -> List[Problem]:
+    """Outputs of one evaluation: copies of p that differ only in the objective.
+
+    ``n_spots`` focal spots at distinct seeded columns of p's focal row (middle
+    half of the physical width), then ``n_modes`` planewave output modes on p's
+    monitor row at seeded angles U[-20, 20] deg.
+    """
+    rng = np.random.default_rng(seed)
+    nxp = p.nx - 2 * p.npml
+    lo, hi = p.npml + nxp // 4, p.npml + (3 * nxp) // 4
+    if n_spots > hi - lo:
+        raise ValueError("more focal spots than columns in the middle half")
+    cols = rng.choice(np.arange(lo, hi), size=n_spots, replace=False)
+    fj = p.focus[1]
+    out = [replace(p, objective=CONCENTRATOR, focus=(int(i), fj)) for i in cols]
+    for _ in range(n_modes):
+        phi = math.radians(float(rng.uniform(-20.0, 20.0)))
+        out.append(replace(p, objective=COLLIMATOR, phi=phi))
+    return out
+
+
+def ensemble_angles(p: Problem, n: int) -> np.ndarray:
+    """n evenly spaced incidence angles (cell midpoints) over the light's support.
+
+    Cone: n cells of [-c, c]; annulus: n/2 cells on each of [-th2, -th1] and
+    [th1, th2] (n even).
+    """
+    if p.light == CONE:
+        ivs = [(-p.c, p.c)]
+    else:
+        ivs = [(-p.th2, -p.th1), (p.th1, p.th2)]
+    per = n // len(ivs)
+    if per * len(ivs) != n or per < 1:
+        raise ValueError("angle count must split evenly over the intervals")
+    th = [lo + (np.arange(per) + 0.5) * (hi - lo) / per for lo, hi in ivs]
+    return np.concatenate(th)
+
+
+def gaussian_correlated_amplitudes(thetas: np.ndarray, sigma_deg: float = 2.0,
+                                   tilt: float = 3.0, skew: float = 2.0) -> np.ndarray:
+    """Amplitude correlation <a_q conj(a_q')> of a partially coherent ensemble.
+
+    sqrt(s_q s_q') exp(-(th_q - th_q')^2 / (2 sigma^2)) exp(i tilt (th_q - th_q')) / n
+    with mean-square weight s_q = exp(skew th_q): angles closer than about sigma
+    are correlated (a beam of finite width), the phase tilt makes the matrix
+    complex and the skew makes the light brighter on one side, so that the
+    current correlation it implies is complex as well.  Hermitian and positive
+    semi-definite.
+    """
+    th = np.asarray(thetas, dtype=np.float64)
+    d = th[:, None] - th[None, :]
+    s = math.radians(sigma_deg)
+    amp = np.exp(0.5 * skew * th)
+    return (amp[:, None] * amp[None, :] * np.exp(-d * d / (2 * s * s)) * np.exp(1j * tilt * d)
+            / th.size).astype(np.complex128)
+
+
+def coherent_amplitudes(n: int, seed: int) -> np.ndarray:
+    """Seeded complex amplitudes a_q of a fully coherent superposition."""
+    return complex_normal(n, seed) / math.sqrt(n)
+
+
+def random_hermitian(m: int, seed: int) -> np.ndarray:
+    """A seeded dense Hermitian m x m matrix (X + X^dag) / 2, X complex normal."""
+    x = complex_normal((m, m), seed)
+    return 0.5 * (x + x.conj().T)
 
 
 # ----------------------------------------------------------------------------
