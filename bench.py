@@ -9,7 +9,8 @@ device.  value = evaluations per second (B per step).
 
 Beside it, on the factors of the last step: the reciprocal average with cached
 factors, the 1000-node Gauss-Legendre brute force it replaces (the same
-solver over 1000 planewave right-hand sides), the FP32-factor + FP64-refinement
+solver over 1000 planewave right-hand sides), the average over 16 outputs under
+a non-translation-invariant (dense W) correlated light, the FP32-factor + FP64-refinement
 variant, the factorisation rate (LU TF/s), the live roofline of the dominant
 kernel (HIP events on the launching stream), and the FP64 CPU oracle timed on
 a bounded sample of the same workload.
@@ -169,6 +170,68 @@ def serving(args):
             "failed": s_con["failed"]}
 
 
+def dense_extra(args, rcp, W, p, fac, t_rec, stream):
+    """Any correlation W and many outputs on cached factors.
+
+    Light: a finite ensemble of planewaves at evenly spaced angles of the cone
+    with Gaussian-correlated amplitudes (correlation width 1 deg, phase tilt):
+    not translation invariant, so W is dense.  Outputs: focal spots on the focal
+    row plus planewave output modes.  Times the ensemble W build (two complex
+    matrix products), the K-output average (one multi-RHS reciprocal sweep + the
+    dense form W V) and its gradient, against K single-output reciprocal solves.
+    """
+    import torch
+    dev = fac.buf.device
+    K, N = args.dense_outputs, args.dense_angles
+    outs = W.output_set(p, K - K // 4, K // 4, seed=3700)
+    th = W.ensemble_angles(p, N)
+    Ca = W.gaussian_correlated_amplitudes(th, sigma_deg=1.0, tilt=5.0)
+    th_d = torch.from_numpy(th).to(dev)
+    C_d = torch.from_numpy(Ca).to(dev)
+    M = p.m_aperture
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    Wm = rcp.correlation_matrix(p, th_d, C_d)           # warm
+    need = int(rcp.lib.rcp_dense_work_bytes(fac.handle, K, M))
+    work = torch.empty(need, dtype=torch.uint8, device=dev)
+    F = rcp.reciprocal_average_dense(fac, outs, Wm, work=work)
+    torch.cuda.synchronize()
+    reps = 5
+    a.record(stream)
+    for _ in range(reps):
+        Wm = rcp.correlation_matrix(p, th_d, C_d)
+    b.record(stream)
+    torch.cuda.synchronize()
+    t_w = a.elapsed_time(b) * 1e-3 / reps
+    w_flops = 8.0 * N * N * M + 8.0 * M * M * N
+    rcp.kernel_timing_start(1)
+    a.record(stream)
+    for _ in range(reps):
+        F = rcp.reciprocal_average_dense(fac, outs, Wm, work=work)
+    b.record(stream)
+    torch.cuda.synchronize()
+    kt = rcp.kernel_timing_stop()["dense_zgemm"]
+    t_d = a.elapsed_time(b) * 1e-3 / reps
+    a.record(stream)
+    Fa, g = rcp.adjoint_grad_dense(fac, outs, Wm, work=work)
+    b.record(stream)
+    torch.cuda.synchronize()
+    t_g = a.elapsed_time(b) * 1e-3
+    form_us = 1e3 * kt["ms"] / max(kt["samples"], 1)
+    form_flops = 8.0 * M * M * K
+    form_bytes = 16.0 * M * M + 2 * 16.0 * M * K
+    return {"outputs": K, "angles": N, "line_cells": M,
+            "W_build_ms": round(1e3 * t_w, 3),
+            "W_build_tflops": round(w_flops / t_w / 1e12, 3),
+            "average_ms": round(1e3 * t_d, 3), "adjoint_ms": round(1e3 * t_g, 3),
+            "single_output_reciprocal_ms_x_K": round(1e3 * t_rec * K, 3),
+            "speedup_vs_K_single_solves": round(t_rec * K / t_d, 2),
+            "forward_solves_replaced": N * K,
+            "form_zgemm_us": round(form_us, 3),
+            "form_zgemm_tflops": round(form_flops / (form_us * 1e-6) / 1e12, 3),
+            "form_zgemm_gbs": round(form_bytes / (form_us * 1e-6) / 1e9, 1),
+            "F_total": F[-1].item(), "F_total_adjoint": Fa[-1].item()}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +249,10 @@ def main():
                     help="width/depth scale of the serving mix (1 = widths 20-300, depths 10-60)")
     ap.add_argument("--batch", type=int, default=8,
                     help="geometries factored side by side per step (1-8)")
+    ap.add_argument("--dense-outputs", type=int, default=16,
+                    help="outputs of the dense-correlation extra (0 = skip)")
+    ap.add_argument("--dense-angles", type=int, default=1000,
+                    help="planewaves in the correlated ensemble of the dense extra")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (reference for the HBM counters)")
     args = ap.parse_args()
@@ -407,6 +474,10 @@ def main():
                               "end_to_end": round((t_bf + t_fac) / (t_rec + t_fac), 3)}
             log(f"brute force {args.bf_angles} angles: {t_bf:.3f} s, F={Fb.item():.10e}, "
                 f"rel diff {rel:.2e}")
+        # any correlation W and many outputs on the same factors
+        if args.dense_outputs > 0:
+            out["dense_correlation"] = dense_extra(args, rcp, W, p, fac, t_rec, stream)
+            log(f"dense: {out['dense_correlation']}")
         # FP32 factors + FP64 refinement, error vs FP64
         del fac
         buf32 = torch.empty(rcp.factor_bytes(p, rcp.RCP_FP32_REFINED), dtype=torch.uint8,

@@ -209,6 +209,56 @@ int rcp_adjoint_grad_batch(int32_t count, rcp_factors* const* factors,
                            const rcp_objective* objs, const rcp_light* lights, double* F_dev,
                            double* const* grad_eps_dev, rcp_stream stream);
 
+/* ---- any correlation W and many outputs --------------------------------
+ * Sec. "Incoherent light": the reciprocal identity of Eq. 7 holds for
+ * arbitrarily correlated light, where W is a dense Hermitian M x M matrix on
+ * the incidence line rather than a Toeplitz one.  Sec. "Concluding remarks":
+ * averages over many focal spots or output modes w_k add up to the trace form
+ * sum_k v_k^dag W v_k, one reciprocal solve per output on the same factors.
+ * Only j_s, i0, i1 and n_s of `line` are used here (M = i1 - i0 cells); its
+ * kind and angles are ignored.  W_dev: M x M complex128, row-major,
+ * W[j][l] = W(x_j, x_l) with x_j the centre of column i0 + j; W is taken as
+ * Hermitian (the real part of each form is returned).  work_dev: at least the
+ * bytes reported by the *_work_bytes call, 256-byte aligned, not overlapping
+ * any other argument; its contents are scratch. */
+
+/* Device workspace of the two dense-form calls for nout (1..4096) outputs on an
+ * m-cell line (0 for invalid arguments). */
+size_t rcp_dense_work_bytes(const rcp_factors* f, int32_t nout, int32_t m);
+
+/* F_k = v_k^dag W v_k with v_k = (A^{-dag} w_k) on the line, for the nout
+ * outputs objs[k] (W V on the matrix cores).  F_dev: nout + 1 float64, F_k
+ * then the sum over k.  V_dev (optional, NULL to skip): nout x M complex128,
+ * row k = v_k.  RCP_FP64 factors with nout >= 8 solve all outputs in one
+ * multi-RHS sweep; otherwise one (refined) solve per output. */
+int rcp_reciprocal_average_dense(const rcp_factors* f, int32_t nout, const rcp_objective* objs,
+                                 const rcp_light* line, const void* W_dev, double* F_dev,
+                                 void* V_dev, void* work_dev, size_t work_bytes,
+                                 rcp_stream stream);
+
+/* Gradient of sum_k F_k (Sec. "Reciprocal approach", one adjoint solve per
+ * output): lambda_k = A^{-1} P^T (W v_k),
+ * d(sum F)/deps_q = -2 k0^2 Re(conj(s_x s_y)_q sum_k conj(lambda_kq) z_kq).
+ * F_dev: nout + 1 float64 as above; grad_eps_dev: nx*ny float64. */
+int rcp_adjoint_grad_dense(const rcp_factors* f, int32_t nout, const rcp_objective* objs,
+                           const rcp_light* line, const void* W_dev, double* F_dev,
+                           double* grad_eps_dev, void* work_dev, size_t work_bytes,
+                           rcp_stream stream);
+
+/* Device workspace of rcp_correlation_matrix (0 for invalid arguments). */
+size_t rcp_correlation_work_bytes(int32_t m, int32_t nangles);
+
+/* Eq. 1 and 3 for a finite ensemble: light made of nangles planewaves at
+ * angles theta_dev[q] (float64, radians in the source medium, |theta| < pi/2)
+ * whose random amplitudes have correlation C_dev[q][q'] = <a_q conj(a_q')>
+ * (nangles x nangles complex128, row-major) has the line correlation
+ * W = G C G^dag, G[j][q] = b0(theta_q) at column i0 + j, b0 the unit-power
+ * equivalent source above.  W_dev: M x M complex128, row-major.  Uses nx,
+ * npml, h and k0 of grid (eps_dev is ignored). */
+int rcp_correlation_matrix(const rcp_grid* grid, const rcp_light* line, int32_t nangles,
+                           const double* theta_dev, const void* C_dev, void* W_dev,
+                           void* work_dev, size_t work_bytes, rcp_stream stream);
+
 /* a1 backward -- chain rule from dF/deps to dF/dwidth_p: each pillar edge moves
  * by dw/2 and changes the fill of the cell holding it by dw/(2h) in every
  * pillar row.  grad_w_dev: pillars->n float64. */
@@ -235,8 +285,9 @@ int rcp_last_solve_stats(const rcp_factors* f, rcp_solve_stats* stats);
  *   3 single-RHS block product     work = bytes of factor blocks read
  *   4 multi-RHS block GEMM         work = algorithmic flops (8 per complex MAC)
  *   5 Gauss-Jordan last update of a block            work = algorithmic flops
+ *   6 dense complex product (W V, ensemble W)        work = algorithmic flops
  * launches counts every launch, samples / ms / work only the timed ones. */
-#define RCP_NKCLASS 6
+#define RCP_NKCLASS 7
 typedef struct {
   int64_t launches, samples;
   double ms, work;

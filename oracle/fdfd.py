@@ -160,11 +160,12 @@ def source_amplitude(p: Problem, theta) -> np.ndarray:
     return -2j * k0(p) * np.sqrt(p.n_source * np.cos(theta))
 
 
-def planewave_sources(p: Problem, thetas) -> np.ndarray:
-    """b0(theta) for each angle: N x len(thetas), nonzero on the incidence line.
+def planewave_line(p: Problem, thetas) -> np.ndarray:
+    """b0(theta) on the incidence line only: M x len(thetas).
 
     theta is measured in the source-plane medium (index n_source); the current
-    sits on row source_row over the physical columns.
+    sits on row source_row over the physical columns, and b = -f there (the
+    stretch factors are 1 outside the PML).
     """
     thetas = np.atleast_1d(np.asarray(thetas, dtype=np.float64))
     i0, i1 = p.aperture
@@ -172,8 +173,15 @@ def planewave_sources(p: Problem, thetas) -> np.ndarray:
     K = p.n_source * k0(p)
     J = source_amplitude(p, thetas)                                # (Q,)
     f_line = (J[None, :] / p.h) * np.exp(1j * K * np.outer(x, np.sin(thetas)))
+    return -f_line
+
+
+def planewave_sources(p: Problem, thetas) -> np.ndarray:
+    """b0(theta) for each angle: N x len(thetas), nonzero on the incidence line."""
+    thetas = np.atleast_1d(np.asarray(thetas, dtype=np.float64))
+    i0, i1 = p.aperture
     B = np.zeros((p.nx * p.ny, thetas.size), dtype=np.complex128)
-    B[index(p, np.arange(i0, i1), p.source_row), :] = -f_line     # b = -f (s = 1 here)
+    B[index(p, np.arange(i0, i1), p.source_row), :] = planewave_line(p, thetas)
     return B
 
 

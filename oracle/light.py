@@ -134,7 +134,7 @@ def toeplitz_matrix(p: Problem) -> np.ndarray:
 
 def toeplitz_from_quadrature(p: Problem, thetas, weights) -> np.ndarray:
     """T built from a quadrature rule: sum_q w_q alpha(theta_q) b0_q b0_q^dag on the line."""
-    B = fdfd.planewave_sources(p, thetas)[fdfd.aperture_indices(p), :]
+    B = fdfd.planewave_line(p, thetas)
     wa = np.asarray(weights) * alpha(p, thetas)
     return (B * wa[None, :]) @ B.conj().T
 
@@ -148,5 +148,5 @@ def ensemble_correlation(p: Problem, thetas, C) -> np.ndarray:
     column q of B the unit-power source b0(theta_q) on the line.  Any Hermitian
     C is allowed; for C diagonal this is the Toeplitz T of a quadrature rule.
     """
-    B = fdfd.planewave_sources(p, thetas)[fdfd.aperture_indices(p), :]
+    B = fdfd.planewave_line(p, thetas)
     return B @ np.asarray(C, dtype=np.complex128) @ B.conj().T

@@ -22,7 +22,8 @@ from ._lib import (RCP_ANNULUS, RCP_COLLIMATOR, RCP_CONCENTRATOR, RCP_CONE, RCP_
 
 __all__ = ["Factors", "factor_batch", "factor_bytes", "eps_from_widths", "reciprocal_average",
            "brute_force_average", "adjoint_grad", "adjoint_grad_batch", "width_grad", "solve",
-           "IncoherentFOM",
+           "IncoherentFOM", "correlation_matrix", "reciprocal_average_dense",
+           "adjoint_grad_dense",
            "RCP_FP64", "RCP_FP32_REFINED", "RecipError"]
 
 
@@ -220,6 +221,76 @@ def adjoint_grad_batch(facs, problems=None, stream=None):
     check(lib.rcp_adjoint_grad_batch(B, handles, objs, lights, F.data_ptr(), gptr,
                                      _stream(stream)))
     return F, grads
+
+
+def _work(need: int, device, work: Optional[torch.Tensor]) -> torch.Tensor:
+    if work is None or work.numel() < need:
+        work = torch.empty(need, dtype=torch.uint8, device=device)
+    return work
+
+
+def correlation_matrix(p: Problem, thetas: torch.Tensor, C_amp: torch.Tensor, stream=None,
+                       work: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Line correlation W = G C G^dag (M x M complex128) of a finite ensemble of
+    planewaves at angles thetas with amplitude correlation C_amp (N x N)."""
+    dev = C_amp.device
+    th = thetas.to(device=dev, dtype=torch.float64).contiguous()
+    Ca = C_amp.to(torch.complex128).contiguous()
+    N = th.numel()
+    if Ca.shape != (N, N):
+        raise ValueError("C_amp must be N x N for N angles")
+    M = p.m_aperture
+    need = int(lib.rcp_correlation_work_bytes(M, N))
+    if need == 0:
+        raise RecipError(_lib.RCP_EINVAL, "invalid sizes for correlation_matrix")
+    work = _work(need, dev, work)
+    Wm = torch.empty((M, M), dtype=torch.complex128, device=dev)
+    g, lt = grid_struct(p), light_struct(p)
+    check(lib.rcp_correlation_matrix(C.byref(g), C.byref(lt), N, th.data_ptr(), Ca.data_ptr(),
+                                     Wm.data_ptr(), work.data_ptr(), need, _stream(stream)))
+    return Wm
+
+
+def _dense_args(fac: Factors, outputs, W: torch.Tensor, p: Optional[Problem]):
+    p = p or fac.problem
+    K = len(outputs)
+    Wc = W.to(torch.complex128).contiguous()
+    if Wc.shape != (p.m_aperture, p.m_aperture):
+        raise ValueError("W must be M x M on the incidence line")
+    objs = (_lib.Objective * K)(*[objective_struct(o) for o in outputs])
+    need = int(lib.rcp_dense_work_bytes(fac.handle, K, p.m_aperture))
+    if need == 0:
+        raise RecipError(_lib.RCP_EINVAL, "invalid sizes for the dense form")
+    return p, K, Wc, objs, light_struct(p), need
+
+
+def reciprocal_average_dense(fac: Factors, outputs, W: torch.Tensor, p: Optional[Problem] = None,
+                             want_v: bool = False, stream=None,
+                             work: Optional[torch.Tensor] = None):
+    """F_k = v_k^dag W v_k for each output (a list of problems that differ in the
+    objective) and their sum: returns F of shape (K + 1,) [, V of shape (K, M)]."""
+    p, K, Wc, objs, lt, need = _dense_args(fac, outputs, W, p)
+    dev = fac.buf.device
+    work = _work(need, dev, work)
+    F = torch.empty(K + 1, dtype=torch.float64, device=dev)
+    V = torch.empty((K, p.m_aperture), dtype=torch.complex128, device=dev) if want_v else None
+    check(lib.rcp_reciprocal_average_dense(fac.handle, K, objs, C.byref(lt), Wc.data_ptr(),
+                                           F.data_ptr(), V.data_ptr() if V is not None else None,
+                                           work.data_ptr(), need, _stream(stream)))
+    return (F, V) if want_v else F
+
+
+def adjoint_grad_dense(fac: Factors, outputs, W: torch.Tensor, p: Optional[Problem] = None,
+                       stream=None, work: Optional[torch.Tensor] = None):
+    """(F of shape (K + 1,), d(sum_k F_k)/deps as an nx x ny map)."""
+    p, K, Wc, objs, lt, need = _dense_args(fac, outputs, W, p)
+    dev = fac.buf.device
+    work = _work(need, dev, work)
+    F = torch.empty(K + 1, dtype=torch.float64, device=dev)
+    g = torch.empty((p.nx, p.ny), dtype=torch.float64, device=dev)
+    check(lib.rcp_adjoint_grad_dense(fac.handle, K, objs, C.byref(lt), Wc.data_ptr(), F.data_ptr(),
+                                     g.data_ptr(), work.data_ptr(), need, _stream(stream)))
+    return F, g
 
 
 def width_grad(p: Problem, grad_eps: torch.Tensor, widths: Optional[torch.Tensor] = None,

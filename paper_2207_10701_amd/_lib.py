@@ -53,8 +53,9 @@ class KernelStat(C.Structure):
                 ("work", C.c_double)]
 
 
-NKCLASS = 6
-KCLASS_NAMES = ["gj_panel", "gj_update", "schur", "block_gemv", "block_gemm", "gj_last"]
+NKCLASS = 7
+KCLASS_NAMES = ["gj_panel", "gj_update", "schur", "block_gemv", "block_gemm", "gj_last",
+                "dense_zgemm"]
 
 
 class RecipError(RuntimeError):
@@ -83,6 +84,13 @@ def _load():
         "rcp_adjoint_grad": (C.c_int, [vp, P(Objective), P(Light), vp, vp, vp]),
         "rcp_adjoint_grad_batch": (C.c_int, [i32, P(vp), P(Objective), P(Light), vp, P(vp), vp]),
         "rcp_width_grad": (C.c_int, [P(Grid), P(Pillars), vp, vp, vp]),
+        "rcp_dense_work_bytes": (sz, [vp, i32, i32]),
+        "rcp_reciprocal_average_dense": (C.c_int, [vp, i32, P(Objective), P(Light), vp, vp, vp,
+                                                   vp, sz, vp]),
+        "rcp_adjoint_grad_dense": (C.c_int, [vp, i32, P(Objective), P(Light), vp, vp, vp, vp,
+                                             sz, vp]),
+        "rcp_correlation_work_bytes": (sz, [i32, i32]),
+        "rcp_correlation_matrix": (C.c_int, [P(Grid), P(Light), i32, vp, vp, vp, vp, sz, vp]),
         "rcp_factors_release": (None, [vp]),
         "rcp_last_error": (C.c_char_p, []),
         "rcp_last_solve_stats": (C.c_int, [vp, P(SolveStats)]),

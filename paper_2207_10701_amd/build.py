@@ -15,7 +15,7 @@ CSRC = HERE / "csrc"
 INCLUDE = HERE.parent / "include"
 LIB = HERE / "librecip.so"
 
-SOURCES = ["api.hip", "assembly.hip", "factor.hip", "solve.hip", "form.hip"]
+SOURCES = ["api.hip", "assembly.hip", "factor.hip", "solve.hip", "form.hip", "dense.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

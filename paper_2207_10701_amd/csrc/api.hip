@@ -151,12 +151,18 @@ int check_objective(const rcp_factors* f, const rcp_objective* o) {
   return RCP_OK;
 }
 
-int check_light(const rcp_factors* f, const rcp_light* L, bool need_alpha) {
+int check_line(const rcp_factors* f, const rcp_light* L) {
   if (!L) return fail(RCP_EINVAL, "light is NULL");
   if (!in_phys_y(f, L->j_s)) return fail(RCP_EINVAL, "incidence row outside the physical region");
   if (L->i0 >= L->i1 || !in_phys_x(f, L->i0) || !in_phys_x(f, L->i1 - 1))
     return fail(RCP_EINVAL, "incidence columns empty or outside the physical region");
   if (!(L->n_s > 0)) return fail(RCP_EINVAL, "source medium index must be positive");
+  return RCP_OK;
+}
+
+int check_light(const rcp_factors* f, const rcp_light* L, bool need_alpha) {
+  int rc = check_line(f, L);
+  if (rc) return rc;
   const double half_pi = 1.5707963267948966;
   if (L->kind == RCP_CONE) {
     if (!(L->c > 0 && L->c < half_pi)) return fail(RCP_EINVAL, "cone half-angle must lie in (0, pi/2)");
@@ -170,6 +176,69 @@ int check_light(const rcp_factors* f, const rcp_light* L, bool need_alpha) {
     return fail(RCP_EINVAL, "unknown light kind");
   }
   return RCP_OK;
+}
+
+constexpr int kMaxOutputs = 4096;
+
+// Arguments shared by the dense-form calls; on success *D is the work layout.
+int check_dense(const rcp_factors* f, int32_t nout, const rcp_objective* objs,
+                const rcp_light* line, const void* W_dev, const double* F_dev, const void* work,
+                size_t work_bytes, DenseLayout* D) {
+  if (!f) return fail(RCP_EINVAL, "factors is NULL");
+  if (nout < 1 || nout > kMaxOutputs) return fail(RCP_EINVAL, "nout must be 1 to 4096");
+  if (!objs) return fail(RCP_EINVAL, "objectives are NULL");
+  for (int k = 0; k < nout; ++k) {
+    int rc = check_objective(f, &objs[k]);
+    if (rc) return fail(rc, "output " + std::to_string(k) + ": " + g_err);
+  }
+  int rc = check_line(f, line);
+  if (rc) return rc;
+  if (!W_dev || !F_dev) return fail(RCP_EINVAL, "NULL W or F");
+  *D = dense_layout(f->nx, f->ny, nout, line->i1 - line->i0);
+  if (!work || work_bytes < D->total)
+    return fail(RCP_ENOMEM, "dense-form workspace needs " + std::to_string(D->total) + " bytes");
+  if (reinterpret_cast<uintptr_t>(work) % 256 != 0)
+    return fail(RCP_EINVAL, "workspace must be 256-byte aligned");
+  return RCP_OK;
+}
+
+// z_k = A^{-dag} w_k for every output, into the Z rows of the workspace
+int dense_fields(rcp_factors* f, int K, const rcp_objective* objs, const DenseLayout& D, char* w,
+                 hipStream_t s) {
+  const size_t N = size_t(f->nx) * f->ny;
+  double2* Bf = reinterpret_cast<double2*>(w + D.off_B);
+  double2* Z = reinterpret_cast<double2*>(w + D.off_Z);
+  int lo, hi;
+  if (f->precision == RCP_FP64 && K >= 8) {   // all outputs in one multi-RHS sweep
+    for (int k = 0; k < K; ++k) {
+      int rc = objective_rhs(f, &objs[k], Bf + k * N, &lo, &hi, s);
+      if (rc) return rc;
+    }
+    return solve_multi_fp64(f, K, Bf, nullptr, 0, Z, 1, s);
+  }
+  for (int k = 0; k < K; ++k) {
+    int rc = objective_rhs(f, &objs[k], f->vec[V_RHS], &lo, &hi, s);
+    if (!rc)
+      rc = solve_vec_refined(f, f->vec[V_RHS], Z + k * N, 1, lo, hi, kRefineTol, kRefineMax, s,
+                             nullptr);
+    if (rc) return rc;
+  }
+  return RCP_OK;
+}
+
+// reciprocal fields, their line values and the dense form: F[0..K-1], F[K]
+int dense_average(rcp_factors* f, int K, const rcp_objective* objs, const rcp_light* line,
+                  const double2* W, double* F, const DenseLayout& D, char* w, hipStream_t s) {
+  const int M = line->i1 - line->i0;
+  int rc = dense_fields(f, K, objs, D, w, s);
+  if (rc) return rc;
+  double2* Vt = reinterpret_cast<double2*>(w + D.off_Vt);
+  rc = gather_lines(reinterpret_cast<double2*>(w + D.off_Z), size_t(f->nx) * f->ny, f->ny,
+                    line->j_s, line->i0, M, K, D.Kp, Vt, s);
+  if (rc) return rc;
+  return dense_form(W, M, Vt, K, D, reinterpret_cast<double2*>(w + D.off_part),
+                    reinterpret_cast<double2*>(w + D.off_Y), reinterpret_cast<double*>(w + D.off_red),
+                    F, s);
 }
 
 int reciprocal_field(rcp_factors* f, const rcp_objective* obj, double2* z, hipStream_t s) {
@@ -562,6 +631,89 @@ int rcp_brute_force_average(const rcp_factors* fc, const rcp_objective* obj, con
     if (rc) return rc;
   }
   return bf_sum(wts, pa, nangles, F_dev, stream);
+}
+
+size_t rcp_dense_work_bytes(const rcp_factors* f, int32_t nout, int32_t m) {
+  if (!f || nout < 1 || nout > kMaxOutputs || m < 1 || m > f->nx) return 0;
+  return dense_layout(f->nx, f->ny, nout, m).total;
+}
+
+int rcp_reciprocal_average_dense(const rcp_factors* fc, int32_t nout, const rcp_objective* objs,
+                                 const rcp_light* line, const void* W_dev, double* F_dev,
+                                 void* V_dev, void* work_dev, size_t work_bytes,
+                                 rcp_stream stream) {
+  rcp_factors* f = const_cast<rcp_factors*>(fc);
+  DenseLayout D;
+  int rc = check_dense(f, nout, objs, line, W_dev, F_dev, work_dev, work_bytes, &D);
+  if (rc) return rc;
+  char* w = static_cast<char*>(work_dev);
+  rc = dense_average(f, nout, objs, line, static_cast<const double2*>(W_dev), F_dev, D, w, stream);
+  if (rc || !V_dev) return rc;
+  const int M = line->i1 - line->i0;
+  RCP_HIP(hipMemcpyAsync(V_dev, w + D.off_Vt, size_t(nout) * M * sizeof(double2),
+                         hipMemcpyDeviceToDevice, stream));
+  return RCP_OK;
+}
+
+int rcp_adjoint_grad_dense(const rcp_factors* fc, int32_t nout, const rcp_objective* objs,
+                           const rcp_light* line, const void* W_dev, double* F_dev,
+                           double* grad_eps_dev, void* work_dev, size_t work_bytes,
+                           rcp_stream stream) {
+  rcp_factors* f = const_cast<rcp_factors*>(fc);
+  DenseLayout D;
+  int rc = check_dense(f, nout, objs, line, W_dev, F_dev, work_dev, work_bytes, &D);
+  if (rc) return rc;
+  if (!grad_eps_dev) return fail(RCP_EINVAL, "grad_eps_dev is NULL");
+  char* w = static_cast<char*>(work_dev);
+  rc = dense_average(f, nout, objs, line, static_cast<const double2*>(W_dev), F_dev, D, w, stream);
+  if (rc) return rc;
+  const int K = nout, M = line->i1 - line->i0;
+  const size_t N = size_t(f->nx) * f->ny;
+  double2* Y = reinterpret_cast<double2*>(w + D.off_Y);
+  double2* Lam = reinterpret_cast<double2*>(w + D.off_B);   // the right-hand sides are spent
+  if (f->precision == RCP_FP64 && K >= 8) {
+    double2* fline = reinterpret_cast<double2*>(w + D.off_fline);
+    rc = scatter_lines(Y, M, K, f->nx, line->i0, fline, stream);
+    if (!rc) rc = solve_multi_fp64(f, K, nullptr, fline, line->j_s, Lam, 0, stream);
+    if (rc) return rc;
+  } else {
+    for (int k = 0; k < K; ++k) {
+      rc = scatter_line(f, line, Y + size_t(k) * M, f->vec[V_ARHS], stream);
+      if (!rc)
+        rc = solve_vec_refined(f, f->vec[V_ARHS], Lam + k * N, 0, line->i0, line->i1 - 1,
+                               kRefineTol, kRefineMax, stream, nullptr);
+      if (rc) return rc;
+    }
+  }
+  return grad_eps_many(f, K, Lam, reinterpret_cast<double2*>(w + D.off_Z), grad_eps_dev, stream);
+}
+
+size_t rcp_correlation_work_bytes(int32_t m, int32_t nangles) {
+  if (m < 1 || nangles < 1 || m > (1 << 16) || nangles > (1 << 16)) return 0;
+  return corr_layout(m, nangles).total;
+}
+
+int rcp_correlation_matrix(const rcp_grid* grid, const rcp_light* line, int32_t nangles,
+                           const double* theta_dev, const void* C_dev, void* W_dev,
+                           void* work_dev, size_t work_bytes, rcp_stream stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!line) return fail(RCP_EINVAL, "light is NULL");
+  const int npml = grid->npml;
+  if (line->i0 >= line->i1 || line->i0 < npml || line->i1 > grid->nx - npml)
+    return fail(RCP_EINVAL, "incidence columns empty or outside the physical region");
+  if (!(line->n_s > 0)) return fail(RCP_EINVAL, "source medium index must be positive");
+  const int M = line->i1 - line->i0;
+  if (nangles < 1 || nangles > (1 << 16)) return fail(RCP_EINVAL, "nangles must be 1 to 65536");
+  if (!theta_dev || !C_dev || !W_dev) return fail(RCP_EINVAL, "NULL argument");
+  const size_t need = rcp_correlation_work_bytes(M, nangles);
+  if (!work_dev || work_bytes < need)
+    return fail(RCP_ENOMEM, "correlation workspace needs " + std::to_string(need) + " bytes");
+  if (reinterpret_cast<uintptr_t>(work_dev) % 256 != 0)
+    return fail(RCP_EINVAL, "workspace must be 256-byte aligned");
+  return correlation_matrix(M, nangles, line->i0, npml, grid->h, line->n_s, grid->k0, theta_dev,
+                            static_cast<const double2*>(C_dev), static_cast<double2*>(W_dev),
+                            static_cast<char*>(work_dev), stream);
 }
 
 }  // extern "C"

@@ -96,7 +96,8 @@ enum KClass {
   K_GEMV = 3,
   K_GEMM = 4,
   K_GJ_LAST = 5,
-  K_NCLASS = 6
+  K_ZGEMM = 6,
+  K_NCLASS = 7
 };
 void ktimer_begin(int cls, hipStream_t s, double work, void** token);
 void ktimer_end(void* token, hipStream_t s);
@@ -164,6 +165,45 @@ int planewave_lines(rcp_factors* f, const rcp_light* L, const double* theta, int
                     double2* fline, hipStream_t s);
 int bf_sum(const double* weights, const double* per_angle, int n, double* F_dev, hipStream_t s);
 int fill_zero(void* p, size_t bytes, hipStream_t s);
+
+// dense.hip -- complex FP64 products out[n][m] = sum_l A[m][l] opB(B[n][l]) on
+// MFMA, split over l into S parts of Ls values (partial products at
+// out + z * split_stride), and what the dense form and the ensemble
+// correlation build from them.
+struct ZSplit {
+  int S, Ls;
+};
+ZSplit zgemm_split(int Md, int Nd, int L);
+// Nd_used (> 0): rows of B that carry data (the timer's flop count); the rest
+// are zero padding.
+int zgemm_nt(const double2* A, int lda, const double2* B, int ldb, bool conjb, double2* out,
+             int ldo, size_t split_stride, int Md, int Nd, int L, ZSplit sp, hipStream_t s,
+             int Nd_used = 0);
+// Work of the dense-form calls for K outputs on an M-cell line: objective
+// right-hand sides (K fields, also the adjoint fields), reciprocal fields (K),
+// the line values V^T and W V (Kp = K rounded up to 16 rows), the split
+// partial products, per-block sums and the adjoint line sources.
+struct DenseLayout {
+  int Kp, nmb;
+  ZSplit sp;
+  size_t off_B, off_Z, off_Vt, off_Y, off_part, off_red, off_fline, total;
+};
+DenseLayout dense_layout(int nx, int ny, int K, int M);
+int gather_lines(const double2* Z, size_t N, int ny, int js, int i0, int M, int K, int Kp,
+                 double2* Vt, hipStream_t s);
+// Y = W V (Kp x M, row k = output k), F[k] = Re v_k^dag y_k, F[K] = sum_k F[k]
+int dense_form(const double2* W, int M, const double2* Vt, int K, const DenseLayout& D,
+               double2* part, double2* Y, double* red, double* F, hipStream_t s);
+int scatter_lines(const double2* Y, int M, int K, int nx, int i0, double2* fline, hipStream_t s);
+int grad_eps_many(rcp_factors* f, int K, const double2* lam, const double2* z, double* grad,
+                  hipStream_t s);
+struct CorrLayout {
+  size_t off_G, off_S, off_part, total;
+};
+CorrLayout corr_layout(int M, int N);
+int correlation_matrix(int M, int N, int i0, int npml, double h, double n_s, double k0,
+                       const double* theta, const double2* Cq, double2* W, char* work,
+                       hipStream_t s);
 
 }  // namespace rcp
 

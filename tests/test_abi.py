@@ -106,3 +106,35 @@ def test_adjoint_batch_argument_checks():
     grads = (C.c_void_p * 1)(None)
     rc = lib.rcp_adjoint_grad_batch(1, handles, o, lt, C.c_void_p(0x1000), grads, None)
     assert rc == _lib.RCP_EINVAL and b"NULL" in lib.rcp_last_error()
+
+
+def test_dense_and_correlation_argument_checks():
+    from paper_2207_10701_amd import _lib
+    lib = _lib.lib
+    o = (_lib.Objective * 2)()
+    lt = _lib.Light(30, 20, 80, 1.5, 0, 0.2, 0.0, 0.0, None)
+    assert lib.rcp_dense_work_bytes(None, 4, 100) == 0
+    rc = lib.rcp_reciprocal_average_dense(None, 2, o, C.byref(lt), None, None, None, None, 0, None)
+    assert rc == _lib.RCP_EINVAL and b"factors is NULL" in lib.rcp_last_error()
+    rc = lib.rcp_adjoint_grad_dense(None, 2, o, C.byref(lt), None, None, None, None, 0, None)
+    assert rc == _lib.RCP_EINVAL
+    # correlation matrix: sizes, grid and line checks happen before any GPU work
+    assert lib.rcp_correlation_work_bytes(0, 10) == 0
+    assert lib.rcp_correlation_work_bytes(10, 0) == 0
+    small = lib.rcp_correlation_work_bytes(60, 10)
+    assert small >= 2 * 60 * 10 * 16
+    g = grid()
+    dummy = C.c_void_p(0x1000)
+    bad_grid = grid(npml=60)
+    assert lib.rcp_correlation_matrix(C.byref(bad_grid), C.byref(lt), 10, dummy, dummy, dummy,
+                                      dummy, small, None) == _lib.RCP_EINVAL
+    outside = _lib.Light(30, 5, 80, 1.5, 0, 0.2, 0.0, 0.0, None)
+    assert lib.rcp_correlation_matrix(C.byref(g), C.byref(outside), 10, dummy, dummy, dummy,
+                                      dummy, small, None) == _lib.RCP_EINVAL
+    assert b"outside" in lib.rcp_last_error()
+    assert lib.rcp_correlation_matrix(C.byref(g), C.byref(lt), 10, None, dummy, dummy, dummy,
+                                      small, None) == _lib.RCP_EINVAL
+    assert lib.rcp_correlation_matrix(C.byref(g), C.byref(lt), 10, dummy, dummy, dummy, dummy,
+                                      small - 1, None) == _lib.RCP_ENOMEM
+    assert lib.rcp_correlation_matrix(C.byref(g), C.byref(lt), 10, dummy, dummy, dummy,
+                                      C.c_void_p(0x1010), small, None) == _lib.RCP_EINVAL
