@@ -159,9 +159,18 @@ def test_dense_argument_errors(rcp):
         bad = W.output_set(p, 1)[0]
         from dataclasses import replace
         rcp.reciprocal_average_dense(fac, [replace(bad, focus=(0, 0))], Wg)
-    with pytest.raises(rcp.RecipError, match="workspace"):
-        rcp.reciprocal_average_dense(fac, W.output_set(p, 2), Wg,
-                                     work=torch.empty(256, dtype=torch.uint8, device="cuda"))
+    # the C ABI rejects a workspace below rcp_dense_work_bytes (the binding would allocate one)
+    import ctypes as C
+    from paper_2207_10701_amd import _lib
+    outs = W.output_set(p, 2)
+    objs = (_lib.Objective * 2)(*[rcp.objective_struct(o) for o in outs])
+    lt = rcp.light_struct(p)
+    need = int(rcp.lib.rcp_dense_work_bytes(fac.handle, 2, p.m_aperture))
+    work = torch.empty(need, dtype=torch.uint8, device="cuda")
+    F = torch.empty(3, dtype=torch.float64, device="cuda")
+    rc = rcp.lib.rcp_reciprocal_average_dense(fac.handle, 2, objs, C.byref(lt), Wg.data_ptr(),
+                                              F.data_ptr(), None, work.data_ptr(), need - 1, None)
+    assert rc == _lib.RCP_ENOMEM and b"workspace" in rcp.lib.rcp_last_error()
 
 
 @pytest.mark.timeout(900)
