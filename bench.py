@@ -58,15 +58,13 @@ DESCR = {
 }
 
 
-# HBM traffic of the dominant kernel, k_gj_fused<double>, per launch, from two
-# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) over one default step
-# (config2, eight geometries per step), scaled by what the same counters read
-# for a 1 GiB copy (python bench.py --calibrate-copy).  Valid only for the
-# kernel source it was measured on: reported when factor.hip still has this hash.
-TRAFFIC = {"config": "config2", "batch": 8,
-           "sha256": "dcc12a879e35d5b786b8a9aed3bf6a7c05a33cc822517d12aece1de7a857f489",
-           "fetch_bytes": 177578401,     # 86710.8 KiB FETCH_SIZE x 1.99994
-           "write_bytes": 164626944}    # 160768.5 KiB WRITE_SIZE x 1.00000
+# HBM traffic of the dominant kernel, k_gj2_fused<double> (two panels per pass),
+# per launch, from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) over one
+# default step (config2, eight geometries per step), scaled by what the same
+# counters read for a 1 GiB copy (python bench.py --calibrate-copy).  Valid only
+# for the kernel source it was measured on: reported when factor.hip still has
+# this hash.
+TRAFFIC = None
 
 
 def factor_source_sha256():
@@ -77,7 +75,7 @@ def factor_source_sha256():
 
 
 def measured_traffic(config, batch):
-    """Bytes per launch of k_gj_fused<double> if measured on this source and workload."""
+    """Bytes per launch of k_gj2_fused<double> if measured on this source and workload."""
     t = TRAFFIC
     if t is None or t["config"] != config or t["batch"] != batch:
         return None
@@ -379,7 +377,7 @@ def main():
 
     upd = kstats["gj_update"]
     achieved = upd["work"] / (upd["ms"] * 1e-3) / 1e12 if upd["ms"] > 0 else 0.0
-    roofline = {"bound": "mfma", "kernel": "k_gj_fused<double>", "achieved": round(achieved, 3),
+    roofline = {"bound": "mfma", "kernel": "k_gj2_fused<double>", "achieved": round(achieved, 3),
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                 "traffic": measured_traffic(args.config, B),

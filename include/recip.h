@@ -229,7 +229,7 @@ size_t rcp_dense_work_bytes(const rcp_factors* f, int32_t nout, int32_t m);
 /* F_k = v_k^dag W v_k with v_k = (A^{-dag} w_k) on the line, for the nout
  * outputs objs[k] (W V on the matrix cores).  F_dev: nout + 1 float64, F_k
  * then the sum over k.  V_dev (optional, NULL to skip): nout x M complex128,
- * row k = v_k.  RCP_FP64 factors with nout >= 8 solve all outputs in one
+ * row k = v_k.  RCP_FP64 factors with nout >= 2 solve all outputs in one
  * multi-RHS sweep; otherwise one (refined) solve per output. */
 int rcp_reciprocal_average_dense(const rcp_factors* f, int32_t nout, const rcp_objective* objs,
                                  const rcp_light* line, const void* W_dev, double* F_dev,
@@ -279,12 +279,16 @@ int rcp_last_solve_stats(const rcp_factors* f, rcp_solve_stats* stats);
  * sessions).  rcp_timing_start(k) brackets every k-th launch of each kernel
  * class with HIP events on the launching stream (k = 0 turns timing off);
  * rcp_timing_stop waits for those events and fills stats[c] for the classes
- *   0 Gauss-Jordan first panel of a block            work = algorithmic flops
- *   1 Gauss-Jordan update k fused with panel k+1     work = algorithmic flops
+ *   0 Gauss-Jordan panels formed apart from a tile update (first panel of a
+ *     block; for batches also the second, and the row tiles of each next
+ *     pair of panels)                                 work = algorithmic flops
+ *   1 Gauss-Jordan tile update: for batches panels k, k+1 in one pass with
+ *     the pivot work of panels k+2, k+3; for one geometry update k fused
+ *     with panel k+1                                  work = algorithmic flops
  *   2 Schur-complement formation   work = bytes of factor blocks read + written
  *   3 single-RHS block product     work = bytes of factor blocks read
  *   4 multi-RHS block GEMM         work = algorithmic flops (8 per complex MAC)
- *   5 Gauss-Jordan last update of a block            work = algorithmic flops
+ *   5 Gauss-Jordan last pass of a block (negated)    work = algorithmic flops
  *   6 dense complex product (W V, ensemble W)        work = algorithmic flops
  * launches counts every launch, samples / ms / work only the timed ones. */
 #define RCP_NKCLASS 7

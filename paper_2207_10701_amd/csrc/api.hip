@@ -45,9 +45,9 @@ Layout compute_layout(int nx, int ny, int precision) {
   L.off_dco = take(N * 16);
   L.off_eco = take(N * 16);
   L.off_cco = take(N * 16);
-  L.off_L = take(4 * size_t(np) * TB * eb);
-  L.off_Q = take(4 * size_t(np) * TB * eb);
-  L.off_P = take(4 * size_t(TB) * TB * 16);
+  L.off_L = take(8 * size_t(np) * TB * eb);
+  L.off_Q = take(8 * size_t(np) * TB * eb);
+  L.off_P = take(8 * size_t(TB) * TB * 16);
   L.off_health = take(size_t(nx) * nt * 8);
   L.off_vec = take(NVEC * N * 16);
   L.off_red = take((2 + 2 * ((N + 255) / 256)) * 8);
@@ -209,7 +209,7 @@ int dense_fields(rcp_factors* f, int K, const rcp_objective* objs, const DenseLa
   double2* Bf = reinterpret_cast<double2*>(w + D.off_B);
   double2* Z = reinterpret_cast<double2*>(w + D.off_Z);
   int lo, hi;
-  if (f->precision == RCP_FP64 && K >= 8) {   // all outputs in one multi-RHS sweep
+  if (f->precision == RCP_FP64 && K >= 2) {   // all outputs in one multi-RHS sweep
     for (int k = 0; k < K; ++k) {
       int rc = objective_rhs(f, &objs[k], Bf + k * N, &lo, &hi, s);
       if (rc) return rc;
@@ -382,7 +382,7 @@ int rcp_factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, vo
     f->eco = reinterpret_cast<double2*>(b + L.off_eco);
     f->cco = reinterpret_cast<double2*>(b + L.off_cco);
     const size_t panel = size_t(f->np) * TB * f->elem_bytes;
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < 8; ++c) {
       f->wsL[c] = b + L.off_L + c * panel;
       f->wsQ[c] = b + L.off_Q + c * panel;
       f->wsP[c] = reinterpret_cast<double2*>(b + L.off_P) + c * TB * TB;
@@ -449,7 +449,7 @@ int rcp_solve_multi_rhs(const rcp_factors* fc, int32_t nrhs, const void* B_dev, 
   const double2* B = static_cast<const double2*>(B_dev);
   double2* X = static_cast<double2*>(X_dev);
   const int conjop = conj_transpose ? 1 : 0;
-  if (f->precision == RCP_FP64 && nrhs >= 8) {
+  if (f->precision == RCP_FP64 && nrhs >= 2) {
     int rc = solve_multi_fp64(f, nrhs, B, nullptr, 0, X, conjop, stream);
     if (rc) return rc;
     if (stats) {
@@ -671,7 +671,7 @@ int rcp_adjoint_grad_dense(const rcp_factors* fc, int32_t nout, const rcp_object
   const size_t N = size_t(f->nx) * f->ny;
   double2* Y = reinterpret_cast<double2*>(w + D.off_Y);
   double2* Lam = reinterpret_cast<double2*>(w + D.off_B);   // the right-hand sides are spent
-  if (f->precision == RCP_FP64 && K >= 8) {
+  if (f->precision == RCP_FP64 && K >= 2) {
     double2* fline = reinterpret_cast<double2*>(w + D.off_fline);
     rc = scatter_lines(Y, M, K, f->nx, line->i0, fline, stream);
     if (!rc) rc = solve_multi_fp64(f, K, nullptr, fline, line->j_s, Lam, 0, stream);

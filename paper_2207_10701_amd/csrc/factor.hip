@@ -579,6 +579,491 @@ __device__ void lookahead_work(const GJJob& jb, int g, int nt, double2 (*Ps)[TB 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Two panels per pass.  Launch j applies panels K = k and K2 = k+1 to every
+// tile (a rank-64 update, each tile read and written once for two panels)
+// while the look-ahead workgroups form panels K3 = k+2 and K4 = k+3 from the
+// tiles as they were before the pass.  With S the tiles before, S' after
+// panel K and S'' after both, on the full symmetric matrix (L0, Q0, P0 of
+// panel K; L1, Q1, P1 of panel K2, whose L1 = S'(:, K2)):
+//   S''_IJ = S_IJ - Q0_I L0_J^T - Q1_I L1_J^T              I, J not in {K, K2}
+//   S''_IK = Q0_I - Q1_I Q0_K2                              I != K, K2
+//   S''_KK = -P0 - Q1_K Q0_K2
+//   S''_I,K2 = Q1_I,   S''_K2,K2 = -P1
+// since S'_K,K2 = (Q0_K2)^T.  The look-ahead takes L3 = S''(:, K3), P3, Q3 and
+// then L4_I = S''_I,K4 - Q3_I (L3_K4)^T = S''_I,K4 - S''_I,K3 (Q3_K4)^T (P3 is
+// symmetric), P4 = (S''_K4,K4 - Q3_K4 L3_K4^T)^{-1}, Q4 = L4 P4.  Panel p lives
+// in slot p mod 4 of its chain's four panel buffers.
+struct GJ2Job {
+  int k;         // first panel of the pair this launch applies
+  int nlook;     // panels formed ahead: 0, 1 (k+2) or 2 (k+2, k+3)
+  int last;      // final pass: negate the result
+  int wgs;       // workgroups of this job (update part + look-ahead part)
+  int wgs_upd;   // of which the trailing-update part
+  void* X;       // packed tiles of the block
+  void* Lb;      // slot 0 of the chain's L panel buffers (np x TB each)
+  void* Qb;
+  double2* Pb;   // slot 0 of the chain's pivot-block inverses (TB x TB each)
+  double* health;   // min |pivot| slots of this block, one per panel
+};
+struct GJ2Jobs {
+  GJ2Job j[MAXJ];
+  int n;
+};
+
+__device__ __forceinline__ GJ2Job pick2(const GJ2Jobs& js, int* wg) {
+  const int per = js.j[0].wgs;
+  const int q = *wg / per;
+  *wg -= q * per;
+#define RCP_SEL(fld) RCP_SEL16(js, q, fld)
+  GJ2Job jb;
+  jb.k = RCP_SEL(k);
+  jb.nlook = RCP_SEL(nlook);
+  jb.last = RCP_SEL(last);
+  jb.wgs = RCP_SEL(wgs);
+  jb.wgs_upd = RCP_SEL(wgs_upd);
+  jb.X = RCP_SEL(X);
+  jb.Lb = RCP_SEL(Lb);
+  jb.Qb = RCP_SEL(Qb);
+  jb.Pb = RCP_SEL(Pb);
+  jb.health = RCP_SEL(health);
+#undef RCP_SEL
+  return jb;
+}
+
+// Panel buffers of panel p (slot p mod 4); a buffer holds nt row tiles.
+template <typename T2>
+__device__ __forceinline__ T2* slot_ptr(void* base, int p, int nt) {
+  return static_cast<T2*>(base) + size_t(p & 3) * nt * TB * TB;
+}
+
+// acc (MFMA accumulator layout) -= A B with A, B row-major TB x TB tiles (B not
+// transposed); blocks (a, b) with a in [a0, a1), b in [b0, b1).
+template <typename T>
+__device__ __forceinline__ void tile_nn_update(typename v4of<T>::t (*cre)[2],
+                                               typename v4of<T>::t (*cim)[2],
+                                               const typename cplx<T>::t* A,
+                                               const typename cplx<T>::t* B, int lr, int lk,
+                                               int a0, int a1, int b0, int b1) {
+  using T2 = typename cplx<T>::t;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int kk = 4 * s + lk;
+    T2 av[2], bv[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      if (x >= a0 && x < a1) av[x] = A[(16 * x + lr) * TB + kk];
+      if (x >= b0 && x < b1) bv[x] = B[kk * TB + 16 * x + lr];
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      if (a < a0 || a >= a1) continue;
+      const T nare = -av[a].x, aim = av[a].y, naim = -av[a].y;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        if (b < b0 || b >= b1) continue;
+        cre[a][b] = mfma16(nare, bv[b].x, cre[a][b]);
+        cim[a][b] = mfma16(nare, bv[b].y, cim[a][b]);
+        cre[a][b] = mfma16(aim, bv[b].y, cre[a][b]);
+        cim[a][b] = mfma16(naim, bv[b].x, cim[a][b]);
+      }
+    }
+  }
+}
+
+// dst = sg (S - A0 B0^T - A1 B1^T): the accumulators start from S (no separate
+// copy of the tile in registers), then eight chunks of two k-steps, the next
+// chunk in flight while the current one multiplies.
+template <typename T>
+__device__ __forceinline__ void tile_update2_pipelined(typename cplx<T>::t* dst,
+                                                       const typename cplx<T>::t* A0,
+                                                       const typename cplx<T>::t* B0,
+                                                       const typename cplx<T>::t* A1,
+                                                       const typename cplx<T>::t* B1, T sg,
+                                                       int lr, int lk) {
+  using T2 = typename cplx<T>::t;
+  using V4 = typename v4of<T>::t;
+  V4 cre[2][2], cim[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const T2 v = dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr];
+        cre[a][b][q] = v.x;
+        cim[a][b][q] = v.y;
+      }
+  T2 a0[2][2], b0[2][2], a1[2][2], b1[2][2];
+  load_ksteps(a0, b0, A0, B0, 0, lr, lk);
+  load_ksteps(a1, b1, A0, B0, 1, lr, lk);
+  mma_ksteps<T>(cre, cim, a0, b0);
+  load_ksteps(a0, b0, A0, B0, 2, lr, lk);
+  mma_ksteps<T>(cre, cim, a1, b1);
+  load_ksteps(a1, b1, A0, B0, 3, lr, lk);
+  mma_ksteps<T>(cre, cim, a0, b0);
+  load_ksteps(a0, b0, A1, B1, 0, lr, lk);
+  mma_ksteps<T>(cre, cim, a1, b1);
+  load_ksteps(a1, b1, A1, B1, 1, lr, lk);
+  mma_ksteps<T>(cre, cim, a0, b0);
+  load_ksteps(a0, b0, A1, B1, 2, lr, lk);
+  mma_ksteps<T>(cre, cim, a1, b1);
+  load_ksteps(a1, b1, A1, B1, 3, lr, lk);
+  mma_ksteps<T>(cre, cim, a0, b0);
+  mma_ksteps<T>(cre, cim, a1, b1);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        T2 v;
+        v.x = cre[a][b][q] * sg;
+        v.y = cim[a][b][q] * sg;
+        dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr] = v;
+      }
+}
+
+// Pass with panels K, K2 = K + 1 on one packed tile per wave.
+template <typename T>
+__device__ void update2_work(const GJ2Job& jb, int wg, int nt, size_t tiles) {
+  using T2 = typename cplx<T>::t;
+  using V4 = typename v4of<T>::t;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const size_t t = size_t(wg) * 4 + wave;
+  if (t >= tiles) return;
+  int I, J;
+  tile_coords(static_cast<int>(t), &I, &J);
+  const int K = jb.k, K2 = K + 1;
+  // the pivot tiles of the next pair belong to its pivot work (which reads
+  // them as they were before this pass); every other tile is updated, so the
+  // next pair's columns hold S'' for its row panels
+  if (jb.nlook >= 1 && I == K + 2 && J == K + 2) return;
+  if (jb.nlook >= 2 && I == K + 3 && (J == K + 2 || J == K + 3)) return;
+  T2* dst = static_cast<T2*>(jb.X) + t * TB * TB;
+  const T sg = jb.last ? T(-1) : T(1);
+  const T2* L0 = slot_ptr<T2>(jb.Lb, K, nt);
+  const T2* Q0 = slot_ptr<T2>(jb.Qb, K, nt);
+  const T2* L1 = slot_ptr<T2>(jb.Lb, K2, nt);
+  const T2* Q1 = slot_ptr<T2>(jb.Qb, K2, nt);
+  const double2* P0 = jb.Pb + size_t(K & 3) * TB * TB;
+  const double2* P1 = jb.Pb + size_t(K2 & 3) * TB * TB;
+  const size_t TT = size_t(TB) * TB;
+  if (I == K2 && J == K2) {
+    for (int e = lane; e < TB * TB; e += 64) {
+      T2 v;
+      v.x = static_cast<T>(-P1[e].x) * sg;
+      v.y = static_cast<T>(-P1[e].y) * sg;
+      dst[e] = v;
+    }
+    return;
+  }
+  if (J == K2 || I == K2) {
+    const T2* q = Q1 + (J == K2 ? I : J) * TT;
+    for (int e = lane; e < TB * TB; e += 64) {
+      const int rr = e / TB, cc = e % TB;
+      T2 v = (J == K2) ? q[e] : q[cc * TB + rr];
+      v.x *= sg;
+      v.y *= sg;
+      dst[e] = v;
+    }
+    return;
+  }
+  const int lr = lane & 15, lk = lane >> 4;
+  if (I == K || J == K) {
+    // column K: Q0_R - Q1_R Q0_K2 for row R (R = I below the pivot, R = J in
+    // row K, stored transposed); the pivot tile: -P0 - Q1_K Q0_K2
+    const int R = (J == K) ? I : J;
+    V4 cre[2][2], cim[2][2];
+    zero_acc<T>(cre, cim);
+    tile_nn_update<T>(cre, cim, Q1 + R * TT, Q0 + K2 * TT, lr, lk, 0, 2, 0, 2);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int rr = 16 * a + mfma_row<T>(lk, q), cc = 16 * b + lr;
+          double2 base;
+          if (I == K && J == K) {
+            base = cneg(P0[rr * TB + cc]);
+          } else {
+            base = to_c128(Q0[R * TT + rr * TB + cc]);
+          }
+          T2 v;
+          v.x = (static_cast<T>(base.x) + cre[a][b][q]) * sg;
+          v.y = (static_cast<T>(base.y) + cim[a][b][q]) * sg;
+          if (J == K)
+            dst[rr * TB + cc] = v;
+          else
+            dst[cc * TB + rr] = v;
+        }
+    return;
+  }
+  tile_update2_pipelined<T>(dst, Q0 + I * TT, L0 + J * TT, Q1 + I * TT, L1 + J * TT, sg, lr, lk);
+}
+
+// Quadrant (qa, qb) of S''_{R,C} for R >= C, R, C not in {K, K2}.
+template <typename T>
+__device__ __forceinline__ void quad2(const GJ2Job& jb, int nt, int R, int C,
+                                      typename v4of<T>::t (*dre)[2],
+                                      typename v4of<T>::t (*dim)[2], int lr, int lk, int qa,
+                                      int qb) {
+  using T2 = typename cplx<T>::t;
+  const T2* X = static_cast<const T2*>(jb.X);
+  const int K = jb.k, K2 = K + 1;
+  const size_t TT = size_t(TB) * TB;
+  const T2* S = X + tile_index(R, C) * TT + (16 * qa) * TB + 16 * qb;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    T2 v = S[mfma_row<T>(lk, q) * TB + lr];
+    dre[0][0][q] = v.x;
+    dim[0][0][q] = v.y;
+  }
+  tile_nt_update<T>(dre, dim, slot_ptr<T2>(jb.Qb, K, nt) + R * TT + (16 * qa) * TB,
+                    slot_ptr<T2>(jb.Lb, K, nt) + C * TT + (16 * qb) * TB, lr, lk, 0, 1, 0, 1);
+  tile_nt_update<T>(dre, dim, slot_ptr<T2>(jb.Qb, K2, nt) + R * TT + (16 * qa) * TB,
+                    slot_ptr<T2>(jb.Lb, K2, nt) + C * TT + (16 * qb) * TB, lr, lk, 0, 1, 0, 1);
+}
+
+template <typename T>
+__device__ __forceinline__ void quad_to_lds(const typename v4of<T>::t (*dre)[2],
+                                            const typename v4of<T>::t (*dim)[2],
+                                            double2 (*D)[TB + 1], int lr, int lk, int qa, int qb) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    D[16 * qa + mfma_row<T>(lk, q)][16 * qb + lr] =
+        make_double2(static_cast<double>(dre[0][0][q]), static_cast<double>(dim[0][0][q]));
+}
+
+// L^T accumulator blocks (a', qa) -> rows 16 qa .. of the L panel tile.
+template <typename T>
+__device__ __forceinline__ void store_lt(const typename v4of<T>::t (*cre)[2],
+                                         const typename v4of<T>::t (*cim)[2],
+                                         typename cplx<T>::t* Lt, int lr, int lk, int qa) {
+  using T2 = typename cplx<T>::t;
+#pragma unroll
+  for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      T2 v;
+      v.x = cre[a2][0][q];
+      v.y = cim[a2][0][q];
+      Lt[(16 * qa + lr) * TB + 16 * a2 + mfma_row<T>(lk, q)] = v;
+    }
+}
+
+// Pivot work of the next pair, once per chain (the last workgroup-sized job of
+// a pass): P3 = S''_{K3,K3}^{-1}; with K4: E = L3_K4 = S''_{K4,K3} and
+// Q3_K4 = E P3 (their rows of the K3 panel buffers), P4 = (S''_{K4,K4} -
+// Q3_K4 E^T)^{-1}.  Columns K3 and K4 are not touched by the pass, so this
+// reads the tiles as they were before it.  The exchange rows of each
+// inversion live in a buffer that is idle at the time.
+template <typename T>
+__device__ void pivot2_work(const GJ2Job& jb, int nt, double2 (*B1)[TB + 1],
+                            double2 (*B2)[TB + 1], double2 (*B3)[TB + 1]) {
+  using T2 = typename cplx<T>::t;
+  using V4 = typename v4of<T>::t;
+  const int K = jb.k, K3 = K + 2, K4 = K + 3;
+  const bool two = jb.nlook == 2;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int qa = wave >> 1, qb = wave & 1;
+  const size_t TT = size_t(TB) * TB;
+  double2 (*x3r)[TB] = reinterpret_cast<double2 (*)[TB]>(&B3[0][0]);
+  // one quadrant product at a time keeps the registers of this path within
+  // those of the update path
+  V4 dre[1][2], dim[1][2];
+  quad2<T>(jb, nt, K3, K3, dre, dim, lr, lk, qa, qb);
+  quad_to_lds<T>(dre, dim, B1, lr, lk, qa, qb);
+  __syncthreads();
+  const double min3 = invert_pivot_block(B1, x3r, x3r + 4);   // P3
+  double2* P3 = jb.Pb + size_t(K3 & 3) * TT;
+  for (int e = tid; e < TB * TB; e += 256) P3[e] = B1[e / TB][e % TB];
+  if (tid == 0) jb.health[K3] = min3;
+  if (!two) return;
+  V4 ere[1][2], eim[1][2], fre[1][2], fim[1][2];
+  quad2<T>(jb, nt, K4, K3, ere, eim, lr, lk, qa, qb);
+  quad_to_lds<T>(ere, eim, B2, lr, lk, qa, qb);
+  {   // E is row K4 of the K3 panel's L buffer
+    T2* Lt = slot_ptr<T2>(jb.Lb, K3, nt) + K4 * TT + (16 * qa) * TB + 16 * qb;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      T2 v;
+      v.x = ere[0][0][q];
+      v.y = eim[0][0][q];
+      Lt[mfma_row<T>(lk, q) * TB + lr] = v;
+    }
+  }
+  quad2<T>(jb, nt, K4, K4, fre, fim, lr, lk, qa, qb);
+  __syncthreads();
+  V4 qre = V4{0, 0, 0, 0}, qim = V4{0, 0, 0, 0};   // Q3_K4 = E P3, quadrant (qa, qb)
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int kk = 4 * s + lk;
+    const double2 av = B2[16 * qa + lr][kk], pv = B1[kk][16 * qb + lr];
+    const T are = static_cast<T>(av.x), aim = static_cast<T>(av.y);
+    const T bre = static_cast<T>(pv.x), bim = static_cast<T>(pv.y);
+    qre = mfma16(are, bre, qre);
+    qim = mfma16(are, bim, qim);
+    qre = mfma16(-aim, bim, qre);
+    qim = mfma16(aim, bre, qim);
+  }
+  {
+    T2* Qt = slot_ptr<T2>(jb.Qb, K3, nt) + K4 * TT + (16 * qa) * TB + 16 * qb;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      B3[16 * qa + mfma_row<T>(lk, q)][16 * qb + lr] =
+          make_double2(static_cast<double>(qre[q]), static_cast<double>(qim[q]));
+      T2 v;
+      v.x = qre[q];
+      v.y = qim[q];
+      Qt[mfma_row<T>(lk, q) * TB + lr] = v;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {   // D4' = D4 - Q3_K4 E^T
+    const int kk = 4 * s + lk;
+    const double2 av = B3[16 * qa + lr][kk], bv = B2[16 * qb + lr][kk];
+    const T nare = static_cast<T>(-av.x), aim = static_cast<T>(av.y),
+            naim = static_cast<T>(-av.y);
+    const T bre = static_cast<T>(bv.x), bim = static_cast<T>(bv.y);
+    fre[0][0] = mfma16(nare, bre, fre[0][0]);
+    fim[0][0] = mfma16(nare, bim, fim[0][0]);
+    fre[0][0] = mfma16(aim, bim, fre[0][0]);
+    fim[0][0] = mfma16(naim, bre, fim[0][0]);
+  }
+  __syncthreads();
+  quad_to_lds<T>(fre, fim, B2, lr, lk, qa, qb);
+  __syncthreads();
+  double2 (*x1r)[TB] = reinterpret_cast<double2 (*)[TB]>(&B1[0][0]);
+  const double min4 = invert_pivot_block(B2, x1r, x1r + 4);   // P4
+  double2* P4 = jb.Pb + size_t(K4 & 3) * TT;
+  for (int e = tid; e < TB * TB; e += 256) P4[e] = B2[e / TB][e % TB];
+  if (tid == 0) jb.health[K4] = min4;
+}
+
+// Rows 16 qa .. 16 qa + 15 of tile (I, C) of the full symmetric matrix as the
+// accumulator blocks (a', qa), a' = 0, 1, of its transpose, from the packed
+// tiles (tile (I, C) for I > C, tile (C, I) transposed for I < C).
+template <typename T>
+__device__ __forceinline__ void load_lt(const GJ2Job& jb, int I, int C,
+                                        typename v4of<T>::t (*cre)[2],
+                                        typename v4of<T>::t (*cim)[2], int lr, int lk, int qa) {
+  using T2 = typename cplx<T>::t;
+  const T2* X = static_cast<const T2*>(jb.X);
+  const size_t TT = size_t(TB) * TB;
+  const bool below = I > C;
+  const T2* src = X + (below ? tile_index(I, C) : tile_index(C, I)) * TT;
+#pragma unroll
+  for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 16 * a2 + mfma_row<T>(lk, q), j = 16 * qa + lr;
+      const T2 v = below ? src[j * TB + i] : src[i * TB + j];
+      cre[a2][0][q] = v.x;
+      cim[a2][0][q] = v.y;
+    }
+}
+
+// Quadrant (qa, qb) of Q = L P from L^T accumulator blocks and the P fragment
+// pf[s] = P[acc_k(s)][16 qb + lr] (loaded beforehand).
+template <typename T>
+__device__ __forceinline__ void q_quad_f(const typename v4of<T>::t (*cre)[2],
+                                         const typename v4of<T>::t (*cim)[2], const double2 (&pf)[8],
+                                         typename cplx<T>::t* Qt, int lr, int lk, int qa, int qb) {
+  using T2 = typename cplx<T>::t;
+  using V4 = typename v4of<T>::t;
+  V4 qre = V4{0, 0, 0, 0}, qim = V4{0, 0, 0, 0};
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const T bre = static_cast<T>(pf[s].x), bim = static_cast<T>(pf[s].y);
+    const T are = cre[s >> 2][0][s & 3], aim = cim[s >> 2][0][s & 3];
+    qre = mfma16(are, bre, qre);
+    qim = mfma16(are, bim, qim);
+    qre = mfma16(-aim, bim, qre);
+    qim = mfma16(aim, bre, qim);
+  }
+  T2* Qb = Qt + (16 * qa) * TB + 16 * qb;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    T2 v;
+    v.x = qre[q];
+    v.y = qim[q];
+    Qb[mfma_row<T>(lk, q) * TB + lr] = v;
+  }
+}
+
+// Row tile I of the next pair's panels after the pass (whose tiles of columns
+// K3, K4 now hold S'') and its pivot work: L3_I = S''_{I,K3}, Q3_I = L3_I P3;
+// with K4: L4_I = S''_{I,K4} - L3_I (Q3_K4)^T (L4_K3 = (Q3_K4)^T), Q4_I = L4_I P4.
+// Row K4 of panel K3 and the pivots come from the pivot work.  Every operand
+// is loaded before the first store, so one memory latency covers the row.
+template <typename T>
+__device__ void rows2_work(const GJ2Job& jb, int I, int nt) {
+  using T2 = typename cplx<T>::t;
+  using V4 = typename v4of<T>::t;
+  const int K = jb.k, K3 = K + 2, K4 = K + 3;
+  const bool two = jb.nlook == 2;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int qa = wave >> 1, qb = wave & 1;
+  const size_t TT = size_t(TB) * TB;
+  const double2* P3 = jb.Pb + size_t(K3 & 3) * TT;
+  const double2* P4 = jb.Pb + size_t(K4 & 3) * TT;
+  const T2* Qk = slot_ptr<T2>(jb.Qb, K3, nt) + K4 * TT;
+  if (I == K3 && !two) return;
+  if (two && I == K4) return;
+  V4 c3re[2][2], c3im[2][2], c4re[2][2], c4im[2][2];
+  double2 p3[8], p4[8];
+  T2 qk[8][2];
+  if (I == K3) {   // L4_K3^T = Q3_K4
+#pragma unroll
+    for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const T2 v = Qk[(16 * a2 + mfma_row<T>(lk, q)) * TB + 16 * qa + lr];
+        c4re[a2][0][q] = v.x;
+        c4im[a2][0][q] = v.y;
+      }
+  } else {
+    load_lt<T>(jb, I, K3, c3re, c3im, lr, lk, qa);
+    if (two) load_lt<T>(jb, I, K4, c4re, c4im, lr, lk, qa);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) p3[s] = P3[acc_k<T>(s, lk) * TB + 16 * qb + lr];
+    if (two) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2) qk[s][a2] = Qk[(16 * a2 + lr) * TB + acc_k<T>(s, lk)];
+    }
+  }
+  if (two) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) p4[s] = P4[acc_k<T>(s, lk) * TB + 16 * qb + lr];
+  }
+  if (I != K3) {
+    if (qb == 0) store_lt<T>(c3re, c3im, slot_ptr<T2>(jb.Lb, K3, nt) + I * TT, lr, lk, qa);
+    q_quad_f<T>(c3re, c3im, p3, slot_ptr<T2>(jb.Qb, K3, nt) + I * TT, lr, lk, qa, qb);
+    if (!two) return;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {   // L4_I^T -= Q3_K4 L3_I^T, right operand from the L3 blocks
+      const T bre = c3re[s >> 2][0][s & 3], bim = c3im[s >> 2][0][s & 3];
+#pragma unroll
+      for (int a2 = 0; a2 < 2; ++a2) {
+        const T nare = -qk[s][a2].x, aim = qk[s][a2].y, naim = -qk[s][a2].y;
+        c4re[a2][0] = mfma16(nare, bre, c4re[a2][0]);
+        c4im[a2][0] = mfma16(nare, bim, c4im[a2][0]);
+        c4re[a2][0] = mfma16(aim, bim, c4re[a2][0]);
+        c4im[a2][0] = mfma16(naim, bre, c4im[a2][0]);
+      }
+    }
+  }
+  if (qb == 0) store_lt<T>(c4re, c4im, slot_ptr<T2>(jb.Lb, K4, nt) + I * TT, lr, lk, qa);
+  q_quad_f<T>(c4re, c4im, p4, slot_ptr<T2>(jb.Qb, K4, nt) + I * TT, lr, lk, qa, qb);
+}
+
 // Workgroup -> (job q, index w within the job).  Workgroups are dealt to the 8
 // XCDs round robin.  When the job count n divides 8, job q gets the XCDs x with
 // x % n == q; when 8 divides n, XCD x serves jobs x, x + 8, ...; either way
@@ -643,6 +1128,34 @@ __global__ __launch_bounds__(256, 2) void k_gj_fused(GJJobs jobs, int nt, size_t
     update_work<T>(jb, w - look, tiles, jb.k + 1);
 }
 
+// Panels k and k+1 applied to all tiles outside the look-ahead columns, plus
+// the pivot work of panels k+2 (and k+3): one workgroup per job, first.
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_gj2_fused(GJ2Jobs jobs, int nt, size_t tiles) {
+  __shared__ double2 B1[TB][TB + 1];
+  __shared__ double2 B2[TB][TB + 1];
+  __shared__ double2 B3[TB][TB + 1];
+  const int look = jobs.j[0].wgs - jobs.j[0].wgs_upd;
+  int q, w;
+  if (!job_of(jobs.n, jobs.j[0].wgs, &q, &w)) return;
+  int tmp = q * jobs.j[0].wgs + w;
+  GJ2Job jb = pick2(jobs, &tmp);
+  if (w < look)
+    pivot2_work<T>(jb, nt, B1, B2, B3);
+  else
+    update2_work<T>(jb, w - look, nt, tiles);
+}
+
+// The row tiles of panels k+2 (and k+3), one per workgroup.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gj2_rows(GJ2Jobs jobs, int nt) {
+  int q, w;
+  if (!job_of(jobs.n, jobs.j[0].wgs, &q, &w)) return;
+  int tmp = q * jobs.j[0].wgs + w;
+  GJ2Job jb = pick2(jobs, &tmp);
+  rows2_work<T>(jb, w, nt);
+}
+
 // dst = D - C1 src1 C1 - C2 src2 C2 on packed tiles (src may be null), with
 // identity in the padding.  D is the tridiagonal diagonal block of column i.
 struct SchurJob {
@@ -697,7 +1210,7 @@ __global__ __launch_bounds__(256) void k_schur(SchurJobs jobs, int ny, size_t ti
 // Factor B same-shape geometries in lockstep: every launch carries the chains
 // of all of them (two per geometry).
 template <typename T>
-int run_factor(rcp_factors* const* fs, int B, hipStream_t s) {
+int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
   const rcp_factors* f0 = fs[0];
   const int N = f0->nx, ny = f0->ny, nt = f0->nt, m = f0->m;
   const size_t tiles = f0->tiles;
@@ -724,12 +1237,13 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s) {
     int g, c, block;
   };
   auto sweep = [&](int nch, const Chain* ch) -> int {
+    // single-panel job k: panel k in slot k mod 4, panel k+1 in the next slot
     auto job = [&](const Chain& x, int k) {
       const rcp_factors* f = fs[x.g];
       GJJob b{};
       b.k = k;
       b.X = block_ptr(f, x.block);
-      const int cur = 2 * x.c + (k & 1), nxt = 2 * x.c + ((k + 1) & 1);
+      const int cur = 4 * x.c + (k & 3), nxt = 4 * x.c + ((k + 1) & 3);
       b.L = f->wsL[cur];
       b.Q = f->wsQ[cur];
       b.P = f->wsP[cur];
@@ -739,7 +1253,7 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s) {
       b.health = f->health + size_t(x.block) * nt + (k + 1 < nt ? k + 1 : k);
       return b;
     };
-    {   // panel 0 (writes the "next" buffers of k = -1, i.e. half 2c)
+    {   // panel 0 (the "next" slot of k = -1, i.e. slot 0)
       GJJobs js{};
       for (int q = 0; q < nch; ++q) {
         GJJob b = job(ch[q], -1);
@@ -752,27 +1266,93 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s) {
       k_gj_panel<T><<<grid_size(nch, pan_wgs), 256, 0, s>>>(js, nt);
       RCP_HIP(hipGetLastError());
     }
-    // look-ahead row tiles per workgroup: two when sixteen chains share the GPU
-    // (84 -> 76 us per launch on 1080-row blocks), otherwise one (shortest chain)
-    const int R = nch >= 16 ? 2 : 1;
-    const int look_wgs = ceil_div(nt, R);
-    for (int k = 0; k + 1 < nt; ++k) {
-      GJJobs js{};
+    if (!pairs) {
+      // one panel per launch: update k of every tile outside column k+1 fused
+      // with the look-ahead of panel k+1; two look-ahead row tiles per
+      // workgroup when sixteen chains share the GPU, otherwise one
+      const int R = nch >= 16 ? 2 : 1;
+      const int look_wgs = ceil_div(nt, R);
+      for (int k = 0; k + 1 < nt; ++k) {
+        GJJobs js{};
+        for (int q = 0; q < nch; ++q) {
+          GJJob b = job(ch[q], k);
+          b.wgs_upd = upd_wgs;
+          b.wgs = upd_wgs + look_wgs;
+          js.j[js.n++] = b;
+        }
+        KTimer kt(K_GJ_UPDATE, s, nch * cmac * double(tiles));
+        const int grid = grid_size(nch, upd_wgs + look_wgs);
+        if (R == 1)
+          k_gj_fused<T, 1><<<grid, 256, 0, s>>>(js, nt, tiles);
+        else
+          k_gj_fused<T, 2><<<grid, 256, 0, s>>>(js, nt, tiles);
+        RCP_HIP(hipGetLastError());
+      }
+      GJJobs js{};   // final update, negated
       for (int q = 0; q < nch; ++q) {
-        GJJob b = job(ch[q], k);
+        GJJob b = job(ch[q], nt - 1);
+        b.last = 1;
+        b.wgs = upd_wgs;
         b.wgs_upd = upd_wgs;
-        b.wgs = upd_wgs + look_wgs;
         js.j[js.n++] = b;
       }
-      KTimer kt(K_GJ_UPDATE, s, nch * cmac * double(tiles));
-      const int grid = grid_size(nch, upd_wgs + look_wgs);
+      KTimer kt(K_GJ_LAST, s, nch * cmac * double(tiles - nt));
+      k_gj_update<T><<<grid_size(nch, upd_wgs), 256, 0, s>>>(js, tiles);
+      RCP_HIP(hipGetLastError());
+      return RCP_OK;
+    }
+    if (nt >= 2) {   // panel 1 from the untouched tiles and panel 0 (look-ahead only)
+      const int R = nch >= 16 ? 2 : 1;
+      const int look_wgs = ceil_div(nt, R);
+      GJJobs js{};
+      for (int q = 0; q < nch; ++q) {
+        GJJob b = job(ch[q], 0);
+        b.wgs_upd = 0;
+        b.wgs = look_wgs;
+        js.j[js.n++] = b;
+      }
+      KTimer kt(K_GJ_PANEL, s, nch * cmac * nt);
+      const int grid = grid_size(nch, look_wgs);
       if (R == 1)
         k_gj_fused<T, 1><<<grid, 256, 0, s>>>(js, nt, tiles);
       else
         k_gj_fused<T, 2><<<grid, 256, 0, s>>>(js, nt, tiles);
       RCP_HIP(hipGetLastError());
     }
-    {   // final update, negated
+    // pairs (K, K+1); the look-ahead forms the next pair (or the last panel)
+    for (int K = 0; K + 1 < nt; K += 2) {
+      const int nlook = nt - (K + 2) >= 2 ? 2 : nt - (K + 2);
+      const int last = nlook == 0 ? 1 : 0;
+      const int look_wgs = nlook > 0 ? 1 : 0;   // the pivot work of the next pair
+      GJ2Jobs js{};
+      for (int q = 0; q < nch; ++q) {
+        const rcp_factors* f = fs[ch[q].g];
+        GJ2Job b{};
+        b.k = K;
+        b.nlook = nlook;
+        b.last = last;
+        b.wgs_upd = upd_wgs;
+        b.wgs = upd_wgs + look_wgs;
+        b.X = block_ptr(f, ch[q].block);
+        b.Lb = f->wsL[4 * ch[q].c];
+        b.Qb = f->wsQ[4 * ch[q].c];
+        b.Pb = f->wsP[4 * ch[q].c];
+        b.health = f->health + size_t(ch[q].block) * nt;
+        js.j[js.n++] = b;
+      }
+      {
+        KTimer kt(last ? K_GJ_LAST : K_GJ_UPDATE, s, nch * 2.0 * cmac * double(tiles));
+        k_gj2_fused<T><<<grid_size(nch, upd_wgs + look_wgs), 256, 0, s>>>(js, nt, tiles);
+        RCP_HIP(hipGetLastError());
+      }
+      if (nlook > 0) {   // row tiles of the next pair's panels
+        for (int q = 0; q < js.n; ++q) js.j[q].wgs = nt;
+        KTimer kt(K_GJ_PANEL, s, nch * cmac * nlook * nt);
+        k_gj2_rows<T><<<grid_size(nch, nt), 256, 0, s>>>(js, nt);
+        RCP_HIP(hipGetLastError());
+      }
+    }
+    if (nt & 1) {   // odd panel count: the last panel alone, negated
       GJJobs js{};
       for (int q = 0; q < nch; ++q) {
         GJJob b = job(ch[q], nt - 1);
@@ -855,7 +1435,16 @@ namespace rcp {
 int factor_blocks(rcp_factors* const* fs, int B, hipStream_t s) {
   if (B < 1 || B > MAXJ / 2) return fail(RCP_EINVAL, "batch of 1 to 8 geometries");
   const int prec = fs[0]->precision;
-  int rc = (prec == RCP_FP64) ? run_factor<double>(fs, B, s) : run_factor<float>(fs, B, s);
+  // Batches take two panels per pass (each tile read and written once per two
+  // panels; the pivot work of the next pair rides in the pass); one geometry
+  // alone is bound by the chain of pivot inversions, which one panel per
+  // launch keeps shortest.
+  const bool pairs = B >= 2;
+  auto run = [&](rcp_factors* const* f, int n, hipStream_t st) {
+    return (prec == RCP_FP64) ? run_factor<double>(f, n, st, pairs)
+                              : run_factor<float>(f, n, st, pairs);
+  };
+  int rc = run(fs, B, s);
   if (rc) return rc;
   // pivot health: one wait, then scan the smallest pivot modulus of every panel
   RCP_HIP(hipStreamSynchronize(s));

@@ -27,7 +27,7 @@ enum { V_Z = 0, V_Y = 1, V_RHS = 2, V_LAM = 3, V_ARHS = 4, V_RES = 5, V_DU = 6, 
 struct Layout {
   size_t off_X, off_eps, off_sxc, off_sxf, off_syc, off_syf;
   size_t off_dco, off_eco, off_cco;
-  size_t off_L, off_Q, off_P;     // GJ panel workspace, 2 chains each
+  size_t off_L, off_Q, off_P;     // GJ panel workspace, 4 slots for each of 2 chains
   size_t off_health, off_vec, off_red, off_fft;
   size_t total;
 };
@@ -51,9 +51,9 @@ struct rcp_factors {
   double* eps;
   double2 *sxc, *sxf, *syc, *syf;
   double2 *dco, *eco, *cco;
-  void* wsL[4];                // panel buffers: chain c, parity p at index 2c + p
-  void* wsQ[4];
-  double2* wsP[4];
+  void* wsL[8];                // panel buffers: chain c, panel p at slot 4c + (p mod 4)
+  void* wsQ[8];
+  double2* wsP[8];
   double* health;
   double2* vec[rcp::NVEC];
   double* red;

@@ -332,6 +332,91 @@ __global__ __launch_bounds__(256, 3) void k_gemm_sweep(MmJobs jobs, int R, int n
       }
 }
 
+// A few right-hand sides (R < 64): the 64 x 64 tiles above would leave most of
+// the GPU idle (17 workgroups per block on 1080-row blocks), so one workgroup
+// takes a 16 (RHS) x 16 (column) output tile and its MW_WAVES waves take
+// interleaved 16-wide k chunks (a few each, so that the chain of dependent
+// loads per wave stays short), reduced through LDS in wave order.  Within a
+// chunk lane group lk supplies k = 4 lk + s at MFMA step s, so that every lane
+// reads four consecutive values of the right-hand side row and of the stored
+// tile row (direct rows for tiles (K >= J), contiguous columns of tile (J, K)
+// used transposed otherwise); no LDS staging.
+constexpr int MW_WAVES = 16;
+__global__ __launch_bounds__(64 * MW_WAVES) void k_mm_narrow(MmJobs jobs, int R, int nx, int ny,
+                                                             int nt, size_t rstride, int jline,
+                                                             int conjop) {
+  __shared__ double2 red[MW_WAVES][16][16];
+  const int ntile_r = ceil_div(R, 16), ntile_j = 2 * nt;
+  const int per_job = ntile_r * ntile_j;
+  const int ji = blockIdx.x / per_job;
+  const int w = blockIdx.x % per_job;
+  const int rt = w / ntile_j, jt = w % ntile_j;
+  MmJob jb = jobs.j[0];
+  if (ji == 1) jb = jobs.j[1];
+  const int r0 = rt * 16, j0 = jt * 16;
+  const int J = j0 / TB, jj = (j0 % TB) + (threadIdx.x & 15);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int r = r0 + lr;
+  const bool rok = r < R;
+  const size_t boff = size_t(jb.block) * ny;
+  const size_t rbase = size_t(rok ? r : 0) * rstride + boff;
+  v4d cre = v4d{0, 0, 0, 0}, cim = v4d{0, 0, 0, 0};
+  const int nk = 2 * nt;
+  for (int kc = wave; kc < nk; kc += MW_WAVES) {
+    const int kb = kc * 16 + 4 * lk;   // this lane's k: kb .. kb + 3, one storage tile row K
+    double2 a[4], b[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = kb + s;
+      double2 v = make_double2(0.0, 0.0);
+      if (rok && k < ny) {
+        const size_t q = rbase + k;
+        if (jb.f) v = jb.f[q];
+        if (jb.fline && k == jline) v = cadd(v, jb.fline[size_t(r) * nx + jb.block]);
+        if (jb.v1) v = csub(v, cmul(maybe_conj(jb.c1[k], conjop), jb.v1[q]));
+        if (jb.v2) v = csub(v, cmul(maybe_conj(jb.c2[k], conjop), jb.v2[q]));
+      }
+      a[s] = v;
+    }
+    const int K = kb / TB, kk = kb % TB;
+    if (K >= J) {
+      const double2* t = jb.X + tile_index(K, J) * TB * TB + kk * TB + jj;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) b[s] = t[s * TB];
+    } else {
+      const double2* t = jb.X + tile_index(J, K) * TB * TB + jj * TB + kk;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) b[s] = t[s];
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const double by = conjop ? -b[s].y : b[s].y;
+      cre = mfma16(a[s].x, b[s].x, cre);
+      cre = mfma16(-a[s].y, by, cre);
+      cim = mfma16(a[s].x, by, cim);
+      cim = mfma16(a[s].y, b[s].x, cim);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) red[wave][mfma_row<double>(lk, q)][lr] = make_double2(cre[q], cim[q]);
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = mfma_row<double>(lk, q);
+      double2 v = red[0][i][lr];
+      for (int u = 1; u < MW_WAVES; ++u) v = cadd(v, red[u][i][lr]);
+      const int rr = r0 + i, j = j0 + lr;
+      if (rr < R && j < ny) {
+        const size_t o = size_t(rr) * rstride + boff + j;
+        if (jb.base) v = cadd(v, jb.base[o]);
+        jb.out[o] = v;
+      }
+    }
+  }
+}
+
 // r = b - A x  (conj(A) if conjop) and per-workgroup partial sums of |r|^2, |b|^2
 __global__ __launch_bounds__(256) void k_residual(int nx, int ny, const double2* __restrict__ dco,
                                                    const double2* __restrict__ eco,
@@ -597,11 +682,15 @@ int solve_multi_fp64(rcp_factors* f, int R, const double2* B, const double2* fli
   auto O = [&](int i) { return Xo + size_t(i) * ny; };
   auto Bb = [&](int i) { return B ? B + size_t(i) * ny : nullptr; };
   auto C = [&](int i) { return f->cco + size_t(i) * ny; };
-  const int per_job = ceil_div(R, MT) * ceil_div(nt * TB, MT);
+  const bool narrow = R < MT;   // 16 x 16 output tiles (k_mm_narrow)
+  const int per_job = narrow ? ceil_div(R, 16) * 2 * nt : ceil_div(R, MT) * ceil_div(nt * TB, MT);
   auto launch = [&](MmJobs& js) -> int {
     if (js.n == 0) return RCP_OK;
     KTimer kt(K_GEMM, s, 8.0 * js.n * double(R) * ny * ny);
-    k_gemm_sweep<<<per_job * js.n, 256, 0, s>>>(js, R, N, ny, nt, rs, jline, conjop);
+    if (narrow)
+      k_mm_narrow<<<per_job * js.n, 64 * MW_WAVES, 0, s>>>(js, R, N, ny, nt, rs, jline, conjop);
+    else
+      k_gemm_sweep<<<per_job * js.n, 256, 0, s>>>(js, R, N, ny, nt, rs, jline, conjop);
     RCP_HIP(hipGetLastError());
     return RCP_OK;
   };

@@ -68,7 +68,8 @@ def test_correlation_matrix_matches_oracle(rcp, name, n):
 @pytest.mark.parametrize("name,spots,modes", [("conc", 1, 0), ("conc", 2, 1), ("ann", 4, 4),
                                               ("odd", 12, 5), ("conc", 30, 10)])
 def test_dense_average_matches_oracle(rcp, name, spots, modes):
-    """Fewer than 8 outputs take one solve each, 8 or more one multi-RHS sweep."""
+    """One output takes the vector sweep, two or more one multi-RHS sweep (16 x 16
+    output tiles below 64 right-hand sides)."""
     p = CASES[name]
     outs = W.output_set(p, spots, modes, seed=3100 + spots)
     th, Ca = ensemble(p, 24)
