@@ -153,7 +153,8 @@ int rcp_factor(const rcp_grid* grid, int32_t precision, void* buf_dev, size_t bu
 
 /* a2 + a3 for `count` (1..8) geometries of identical grid (only eps differs),
  * factored in the same kernel launches (their elimination chains run side by
- * side).  grids[g], bufs[g] (each buf_bytes >= rcp_factor_bytes, 256-byte
+ * side, two Gauss-Jordan panels per pass over the tiles; a lone geometry takes
+ * one panel per launch, so its factors agree with a batch's to rounding).  grids[g], bufs[g] (each buf_bytes >= rcp_factor_bytes, 256-byte
  * aligned, non-overlapping) and out[g] as for rcp_factor.  On failure no
  * handle is returned and the message names the geometry. */
 int rcp_factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, void* const* bufs,
