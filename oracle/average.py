@@ -23,6 +23,8 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 * ``brute_force_ensemble``
                     Eq. 5 for a finite ensemble of planewaves with amplitude
                     correlation C_qq': one forward solve per planewave.
+* ``broadband``     a weighted sum of single-wavelength averages over a
+                    spectral rule, and its gradient.
 
 Because A = A^T, A^{-dag} w = conj(A^{-1} conj(w)): the reciprocal problem is the
 forward problem with the conjugated objective as its source (a point source at
@@ -31,7 +33,7 @@ collimator, Sec. "Reciprocal approach").
 """
 from __future__ import annotations
 
-from dataclasses import dataclass
+from dataclasses import dataclass, replace
 
 import numpy as np
 
@@ -234,3 +236,38 @@ def adjoint_dense(s: Solved, outputs, W: np.ndarray) -> DenseGradient:
     grad_eps = g.reshape(p.nx, p.ny)
     return DenseGradient(F=F, V=V, Y=Y, grad_eps=grad_eps,
                          grad_widths=width_gradient(p, grad_eps))
+
+
+# ---------------------------------------------------------------------------
+# Broadband
+#
+# Sec. "Method" notes that the single-wavelength calculation can be repeated at
+# several wavelengths for broadband problems, and Sec. "Concluding remarks" that
+# the frequency integral is a weighted quadrature over the spectrum.  With a
+# rule (lambda_l, w_l) the broadband average is sum_l w_l F(lambda_l), each term
+# the reciprocal average of Eq. 7 at that wavelength (k0 = 2 pi / lambda_l in
+# the operator, the PML, the sources and the correlation; permittivities do not
+# depend on the wavelength), and its gradient is sum_l w_l dF(lambda_l)/deps.
+# ---------------------------------------------------------------------------
+
+def at_wavelength(p: Problem, lam: float) -> Problem:
+    return replace(p, wavelength=float(lam))
+
+
+@dataclass
+class Broadband:
+    F: np.ndarray            # per-wavelength averages
+    total: float             # sum_l w_l F_l
+    grad_eps: np.ndarray     # sum_l w_l dF_l/deps
+    grad_widths: np.ndarray
+
+
+def broadband(p: Problem, wavelengths, weights) -> Broadband:
+    F, g = [], np.zeros((p.nx, p.ny))
+    for lam, w in zip(wavelengths, weights):
+        gl = adjoint(setup(at_wavelength(p, lam)))
+        F.append(gl.F)
+        g += w * gl.grad_eps
+    F = np.array(F)
+    return Broadband(F=F, total=float(np.dot(weights, F)), grad_eps=g,
+                     grad_widths=width_gradient(p, g))

@@ -27,6 +27,7 @@ to the synthetic configurations below:
                 many outputs of one evaluation (focal spots and output modes)
                 and a finite ensemble of planewaves with correlated amplitudes
                 (light that is not translation invariant).
+* ``spectral_rule`` a flat spectrum sampled at n wavelengths (broadband).
 
 Units: vacuum wavelength 1, grid step h = 1/20.  Cell (i, j) has its centre at
 x = (i - npml + 1/2) h, y = (j - npml + 1/2) h, origin at the lower-left corner
@@ -258,6 +259,18 @@ def gaussian_correlated_amplitudes(thetas: np.ndarray, sigma_deg: float = 2.0,
 def coherent_amplitudes(n: int, seed: int) -> np.ndarray:
     """Seeded complex amplitudes a_q of a fully coherent superposition."""
     return complex_normal(n, seed) / math.sqrt(n)
+
+
+def spectral_rule(n: int, lam_lo: float = 0.9, lam_hi: float = 1.1):
+    """A flat spectrum over vacuum wavelengths [lam_lo, lam_hi] as n frequency samples.
+
+    Midpoints of n equal cells in frequency 1/lam, each of weight 1/n (the
+    weights sum to one).  Returns (wavelengths, weights), longest wavelength
+    first.
+    """
+    f_lo, f_hi = 1.0 / lam_hi, 1.0 / lam_lo
+    f = f_lo + (np.arange(n) + 0.5) * (f_hi - f_lo) / n
+    return 1.0 / f, np.full(n, 1.0 / n)
 
 
 def random_hermitian(m: int, seed: int) -> np.ndarray:
