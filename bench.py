@@ -10,7 +10,8 @@ device.  value = evaluations per second (B per step).
 Beside it, on the factors of the last step: the reciprocal average with cached
 factors, the 1000-node Gauss-Legendre brute force it replaces (the same
 solver over 1000 planewave right-hand sides), the average over 16 outputs under
-a non-translation-invariant (dense W) correlated light, the FP32-factor + FP64-refinement
+a non-translation-invariant (dense W) correlated light, a broadband evaluation
+(the geometry at 8 wavelengths, factored side by side), the FP32-factor + FP64-refinement
 variant, the factorisation rate (LU TF/s), the live roofline of the dominant
 kernel (HIP events on the launching stream), and the FP64 CPU oracle timed on
 a bounded sample of the same workload.
@@ -233,6 +234,31 @@ def dense_extra(args, rcp, W, p, fac, t_rec, stream):
             "F_total": F[-1].item(), "F_total_adjoint": Fa[-1].item()}
 
 
+def broadband_extra(args, rcp, W, p, widths, bufs, stream):
+    """One broadband evaluation: the geometry factored at n wavelengths of a flat
+    spectral rule over [0.9, 1.1] side by side, then the weighted average and its
+    gradient (the batched reciprocal and adjoint solves of all wavelengths)."""
+    import torch
+    from dataclasses import replace
+    n = args.broadband
+    lams, wts = W.spectral_rule(n, 0.9, 1.1)
+    probs = [replace(p, wavelength=float(lam)) for lam in lams]
+    dev = bufs[0].device
+    eps = rcp.eps_from_widths(p, widths, device=dev)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    facs = rcp.factor_batch(probs, [eps] * n, rcp.RCP_FP64, buffers=bufs[:n])
+    F, g = rcp.broadband_grad(facs, wts, probs)
+    b.record(stream)
+    torch.cuda.synchronize()
+    t = a.elapsed_time(b) * 1e-3
+    del facs
+    return {"wavelengths": n, "band": [0.9, 1.1], "seconds": round(t, 4),
+            "evals_per_s": round(1.0 / t, 4), "F_broadband": F[-1].item(),
+            "F_min": F[:-1].min().item(), "F_max": F[:-1].max().item()}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +278,8 @@ def main():
                     help="geometries factored side by side per step (1-8)")
     ap.add_argument("--dense-outputs", type=int, default=16,
                     help="outputs of the dense-correlation extra (0 = skip)")
+    ap.add_argument("--broadband", type=int, default=8,
+                    help="wavelengths of the broadband extra (0 = skip; at most --batch)")
     ap.add_argument("--dense-angles", type=int, default=1000,
                     help="planewaves in the correlated ensemble of the dense extra")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -505,6 +533,11 @@ def main():
                                "F_rel_err_vs_fp64": abs(F32.item() - F64.item()) / abs(F64.item())}
         log(f"fp32 refined: factor {t_f32 * 1e3:.1f} ms, {it} steps, field err {zerr:.2e}")
         del f32, buf32
+        # broadband: the geometry at the eight wavelengths of a flat spectral rule
+        if args.broadband > 0 and B >= args.broadband:
+            del fac
+            out["broadband"] = broadband_extra(args, rcp, W, p, widths[-1], bufs, stream)
+            log(f"broadband: {out['broadband']}")
     if args.serve_requests > 0:
         out["serving"] = serving(args)
         log(f"serving: {out['serving']}")

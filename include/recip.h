@@ -151,11 +151,13 @@ size_t rcp_factor_bytes(const rcp_grid* grid, int32_t precision);
 int rcp_factor(const rcp_grid* grid, int32_t precision, void* buf_dev, size_t buf_bytes,
                rcp_stream stream, rcp_factors** out);
 
-/* a2 + a3 for `count` (1..8) geometries of identical grid (only eps differs),
+/* a2 + a3 for `count` (1..8) geometries of identical grid shape (eps and k0 may
+ * differ: several wavelengths of one geometry factor side by side),
  * factored in the same kernel launches (their elimination chains run side by
  * side, two Gauss-Jordan panels per pass over the tiles; a lone geometry takes
- * one panel per launch, so its factors agree with a batch's to rounding).  grids[g], bufs[g] (each buf_bytes >= rcp_factor_bytes, 256-byte
- * aligned, non-overlapping) and out[g] as for rcp_factor.  On failure no
+ * one panel per launch, so its factors agree with a batch's to rounding).
+ * grids[g], bufs[g] (each buf_bytes >= rcp_factor_bytes, 256-byte aligned,
+ * non-overlapping) and out[g] as for rcp_factor.  On failure no
  * handle is returned and the message names the geometry. */
 int rcp_factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, void* const* bufs,
                      size_t buf_bytes, rcp_stream stream, rcp_factors** out);
@@ -259,6 +261,20 @@ size_t rcp_correlation_work_bytes(int32_t m, int32_t nangles);
 int rcp_correlation_matrix(const rcp_grid* grid, const rcp_light* line, int32_t nangles,
                            const double* theta_dev, const void* C_dev, void* W_dev,
                            void* work_dev, size_t work_bytes, rcp_stream stream);
+
+/* Broadband (Sec. "Method": the single-wavelength calculation repeated at
+ * several wavelengths; Sec. "Concluding remarks": the frequency integral as a
+ * weighted quadrature over the spectrum).  count (1..8) factor sets of one
+ * grid shape and precision, typically one rcp_factor_batch call whose grids
+ * differ in k0 (the wavelengths of the rule; eps too if the material is
+ * dispersive), with objs[g] and lights[g] at that wavelength and host weights
+ * weights[g]: F_dev (count + 1 float64) receives F_g then sum_g weights[g] F_g;
+ * grad_eps_dev (nx*ny float64) receives sum_g weights[g] dF_g/deps.  Uses each
+ * set's work vectors as scratch (calls on a set must be ordered on one
+ * stream). */
+int rcp_broadband_grad(int32_t count, rcp_factors* const* factors, const rcp_objective* objs,
+                       const rcp_light* lights, const double* weights, double* F_dev,
+                       double* grad_eps_dev, rcp_stream stream);
 
 /* a1 backward -- chain rule from dF/deps to dF/dwidth_p: each pillar edge moves
  * by dw/2 and changes the fill of the cell holding it by dw/(2h) in every

@@ -23,7 +23,7 @@ from ._lib import (RCP_ANNULUS, RCP_COLLIMATOR, RCP_CONCENTRATOR, RCP_CONE, RCP_
 __all__ = ["Factors", "factor_batch", "factor_bytes", "eps_from_widths", "reciprocal_average",
            "brute_force_average", "adjoint_grad", "adjoint_grad_batch", "width_grad", "solve",
            "IncoherentFOM", "correlation_matrix", "reciprocal_average_dense",
-           "adjoint_grad_dense",
+           "adjoint_grad_dense", "broadband_grad",
            "RCP_FP64", "RCP_FP32_REFINED", "RecipError"]
 
 
@@ -221,6 +221,27 @@ def adjoint_grad_batch(facs, problems=None, stream=None):
     check(lib.rcp_adjoint_grad_batch(B, handles, objs, lights, F.data_ptr(), gptr,
                                      _stream(stream)))
     return F, grads
+
+
+def broadband_grad(facs, weights, problems=None, stream=None):
+    """Weighted sum over 1-8 factor sets (one geometry at the wavelengths of a
+    spectral rule, e.g. from factor_batch): returns (F of shape (B + 1,) with the
+    per-wavelength averages then the weighted sum, d(sum)/deps as nx x ny)."""
+    B = len(facs)
+    problems = problems or [f.problem for f in facs]
+    if B < 1 or B > 8 or len(problems) != B or len(weights) != B:
+        raise ValueError("broadband_grad takes 1 to 8 factor sets with one problem and weight each")
+    dev = facs[0].buf.device
+    p = problems[0]
+    F = torch.empty(B + 1, dtype=torch.float64, device=dev)
+    g = torch.empty((p.nx, p.ny), dtype=torch.float64, device=dev)
+    handles = (C.c_void_p * B)(*[f.handle.value for f in facs])
+    objs = (_lib.Objective * B)(*[objective_struct(q) for q in problems])
+    lights = (_lib.Light * B)(*[light_struct(q) for q in problems])
+    w = (C.c_double * B)(*[float(x) for x in weights])
+    check(lib.rcp_broadband_grad(B, handles, objs, lights, w, F.data_ptr(), g.data_ptr(),
+                                 _stream(stream)))
+    return F, g
 
 
 def _work(need: int, device, work: Optional[torch.Tensor]) -> torch.Tensor:

@@ -326,9 +326,9 @@ int rcp_factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, vo
     if (!grids[g].eps_dev) return fail(RCP_EINVAL, "eps_dev is NULL");
     const rcp_grid& a = grids[0];
     const rcp_grid& c = grids[g];
-    if (c.nx != a.nx || c.ny != a.ny || c.npml != a.npml || c.h != a.h || c.k0 != a.k0 ||
-        c.pml_R != a.pml_R || c.pml_m != a.pml_m)
-      return fail(RCP_EINVAL, "a batch needs identical grids (only eps may differ)");
+    if (c.nx != a.nx || c.ny != a.ny || c.npml != a.npml || c.h != a.h || c.pml_R != a.pml_R ||
+        c.pml_m != a.pml_m)
+      return fail(RCP_EINVAL, "a batch needs identical grids (only eps and k0 may differ)");
   }
   Layout L = compute_layout(grids[0].nx, grids[0].ny, precision);
   if (buf_bytes < L.total)
@@ -572,6 +572,25 @@ int rcp_adjoint_grad_batch(int32_t count, rcp_factors* const* factors, const rcp
     if (rc) return rc;
   }
   return RCP_OK;
+}
+
+int rcp_broadband_grad(int32_t count, rcp_factors* const* factors, const rcp_objective* objs,
+                       const rcp_light* lights, const double* weights, double* F_dev,
+                       double* grad_eps_dev, rcp_stream stream) {
+  if (count < 1 || count > MAX_BATCH) return fail(RCP_EINVAL, "count must be 1 to 8");
+  if (!factors || !weights || !F_dev || !grad_eps_dev) return fail(RCP_EINVAL, "NULL argument");
+  for (int g = 0; g < count; ++g)
+    if (!std::isfinite(weights[g])) return fail(RCP_EINVAL, "weights must be finite");
+  // each set's gradient goes to its own scratch vector, then the weighted sum
+  double* grads[MAX_BATCH];
+  for (int g = 0; g < count; ++g) {
+    if (!factors[g]) return fail(RCP_EINVAL, "factors " + std::to_string(g) + " is NULL");
+    grads[g] = reinterpret_cast<double*>(factors[g]->vec[V_TMP]);
+  }
+  int rc = rcp_adjoint_grad_batch(count, factors, objs, lights, F_dev, grads, stream);
+  if (rc) return rc;
+  return weighted_sum(count, weights, grads, size_t(factors[0]->nx) * factors[0]->ny, F_dev,
+                      grad_eps_dev, stream);
 }
 
 int rcp_width_grad(const rcp_grid* grid, const rcp_pillars* pillars, const double* grad_eps_dev,

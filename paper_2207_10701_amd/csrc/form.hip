@@ -279,6 +279,26 @@ __global__ void k_gl_nodes(int n, int nint, double lo0, double hi0, double lo1, 
   wts[q] = 0.5 * (hi - lo) * w * alpha;
 }
 
+// out[q] = sum_g w_g x_g[q] (g in order); thread 0 of block 0 also sets
+// F[count] = sum_g w_g F[g]
+struct WSum {
+  const double* x[MAX_BATCH];
+  double w[MAX_BATCH];
+};
+__global__ void k_weighted_fields(WSum a, int count, size_t n, double* __restrict__ F,
+                               double* __restrict__ out) {
+  size_t q = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q == 0) {
+    double t = 0.0;
+    for (int g = 0; g < count; ++g) t += a.w[g] * F[g];
+    F[count] = t;
+  }
+  if (q >= n) return;
+  double acc = 0.0;
+  for (int g = 0; g < count; ++g) acc += a.w[g] * a.x[g][q];
+  out[q] = acc;
+}
+
 int fft_inplace(rcp_factors* f, double2* buf, int P, double sign, hipStream_t s) {
   int logP = 0;
   while ((1 << logP) < P) ++logP;
@@ -418,6 +438,18 @@ int gl_nodes(const rcp_light* L, int n, double* theta, double* wts, hipStream_t 
     alpha = 1.0 / (2.0 * (L->th2 - L->th1));
   }
   k_gl_nodes<<<ceil_div(n, 64), 64, 0, s>>>(per, nint, lo0, hi0, lo1, hi1, alpha, theta, wts);
+  RCP_HIP(hipGetLastError());
+  return RCP_OK;
+}
+
+int weighted_sum(int count, const double* w, double* const* x, size_t n, double* F, double* out,
+                 hipStream_t s) {
+  WSum a{};
+  for (int g = 0; g < count; ++g) {
+    a.x[g] = x[g];
+    a.w[g] = w[g];
+  }
+  k_weighted_fields<<<static_cast<int>((n + 255) / 256), 256, 0, s>>>(a, count, n, F, out);
   RCP_HIP(hipGetLastError());
   return RCP_OK;
 }

@@ -165,6 +165,10 @@ int planewave_lines(rcp_factors* f, const rcp_light* L, const double* theta, int
                     double2* fline, hipStream_t s);
 int bf_sum(const double* weights, const double* per_angle, int n, double* F_dev, hipStream_t s);
 int fill_zero(void* p, size_t bytes, hipStream_t s);
+// out[q] = sum_g w[g] x_g[q] over n values, and F[count] = sum_g w[g] F[g]
+// (fixed order; count <= MAX_BATCH)
+int weighted_sum(int count, const double* w, double* const* x, size_t n, double* F, double* out,
+                 hipStream_t s);
 
 // dense.hip -- complex FP64 products out[n][m] = sum_l A[m][l] opB(B[n][l]) on
 // MFMA, split over l into S parts of Ls values (partial products at

@@ -138,3 +138,19 @@ def test_dense_and_correlation_argument_checks():
                                       small - 1, None) == _lib.RCP_ENOMEM
     assert lib.rcp_correlation_matrix(C.byref(g), C.byref(lt), 10, dummy, dummy, dummy,
                                       C.c_void_p(0x1010), small, None) == _lib.RCP_EINVAL
+
+
+def test_broadband_argument_checks():
+    from paper_2207_10701_amd import _lib
+    lib = _lib.lib
+    o = (_lib.Objective * 1)()
+    lt = (_lib.Light * 1)()
+    w = (C.c_double * 1)(1.0)
+    for count in (0, 9):
+        assert lib.rcp_broadband_grad(count, None, o, lt, w, None, None, None) == _lib.RCP_EINVAL
+    handles = (C.c_void_p * 1)(None)
+    rc = lib.rcp_broadband_grad(1, handles, o, lt, None, C.c_void_p(0x1000), C.c_void_p(0x1000), None)
+    assert rc == _lib.RCP_EINVAL and b"NULL" in lib.rcp_last_error()
+    bad = (C.c_double * 1)(float("inf"))
+    rc = lib.rcp_broadband_grad(1, handles, o, lt, bad, C.c_void_p(0x1000), C.c_void_p(0x1000), None)
+    assert rc == _lib.RCP_EINVAL and b"finite" in lib.rcp_last_error()
