@@ -11,7 +11,8 @@ Beside it, on the factors of the last step: the reciprocal average with cached
 factors, the 1000-node Gauss-Legendre brute force it replaces (the same
 solver over 1000 planewave right-hand sides), the average over 16 outputs under
 a non-translation-invariant (dense W) correlated light, a broadband evaluation
-(the geometry at 8 wavelengths, factored side by side), the FP32-factor + FP64-refinement
+(the geometry at 8 wavelengths, factored side by side), a few batched L-BFGS-B
+iterations of inverse design, the FP32-factor + FP64-refinement
 variant, the factorisation rate (LU TF/s), the live roofline of the dominant
 kernel (HIP events on the launching stream), and the FP64 CPU oracle timed on
 a bounded sample of the same workload.
@@ -259,6 +260,25 @@ def broadband_extra(args, rcp, W, p, widths, bufs, stream):
             "F_min": F[:-1].min().item(), "F_max": F[:-1].max().item()}
 
 
+def design_extra(args, W, p, B, bufs):
+    """A few L-BFGS-B iterations of B seeded designs of the workload, every round
+    of evaluations one batched factorisation + batched adjoint."""
+    import torch
+    from dataclasses import replace
+    from paper_2207_10701_amd.design import gpu_batch_fn, maximize
+    probs = [replace(p, name=f"design{k}", widths=W.seeded_widths(len(p.widths), 9000 + k))
+             for k in range(B)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, lock = maximize(probs, gpu_batch_fn(buffers=bufs), iters=args.design_iters)
+    t = time.perf_counter() - t0
+    return {"designs": B, "iters": args.design_iters, "seconds": round(t, 3),
+            "rounds": lock.rounds, "evaluations": lock.evaluations,
+            "evaluations_per_s": round(lock.evaluations / t, 3),
+            "gain_min": round(min(r.F / r.F0 for r in res), 3),
+            "gain_max": round(max(r.F / r.F0 for r in res), 3)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,6 +298,8 @@ def main():
                     help="geometries factored side by side per step (1-8)")
     ap.add_argument("--dense-outputs", type=int, default=16,
                     help="outputs of the dense-correlation extra (0 = skip)")
+    ap.add_argument("--design-iters", type=int, default=2,
+                    help="L-BFGS-B iterations of the inverse-design extra (0 = skip)")
     ap.add_argument("--broadband", type=int, default=8,
                     help="wavelengths of the broadband extra (0 = skip; at most --batch)")
     ap.add_argument("--dense-angles", type=int, default=1000,
@@ -538,6 +560,10 @@ def main():
             del fac
             out["broadband"] = broadband_extra(args, rcp, W, p, widths[-1], bufs, stream)
             log(f"broadband: {out['broadband']}")
+        # inverse design: B seeded designs, L-BFGS-B each, evaluations batched
+        if args.design_iters > 0:
+            out["design"] = design_extra(args, W, p, B, bufs)
+            log(f"design: {out['design']}")
     if args.serve_requests > 0:
         out["serving"] = serving(args)
         log(f"serving: {out['serving']}")

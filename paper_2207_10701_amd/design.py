@@ -1,0 +1,190 @@
+"""Inverse design of the pillar widths for the angle-averaged figure of merit.
+
+Sec. "Reciprocal approach": the average F(p) of Eq. 7 and its gradient
+2 Re(v^dag W dv/dp), from one reciprocal and one adjoint solve, drive a
+gradient-based optimizer over the design parameters p -- here the pillar
+widths of Sec. "Designs", bounded to [lo, hi].  Each of B designs (starting
+points, or different problems of one grid) runs its own L-BFGS-B; their
+evaluations are gathered round by round so that one batched factorisation and
+one batched adjoint on the GPU serve all of them (at most eight per batch).
+
+Host logic only (the optimizer's bookkeeping on ~10^2 variables); every
+evaluation runs in librecip's kernels.
+"""
+from __future__ import annotations
+
+import threading
+import time
+from dataclasses import dataclass, field, replace
+from typing import Callable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from workloads import Problem
+
+# evaluate_batch([(problem, widths), ...]) -> [(F, dF/dwidths), ...]
+BatchFn = Callable[[Sequence[Tuple[Problem, np.ndarray]]], List[Tuple[float, np.ndarray]]]
+
+
+class Lockstep:
+    """Gathers the evaluations of n concurrent optimizers into batches.
+
+    Each optimizer thread calls ``evaluate(i, x)``; once every optimizer that
+    is still running has a request pending, the batch function runs once on
+    all of them and every caller gets its own result.  ``finish(i)`` retires an
+    optimizer (a finished one no longer holds the others back).
+    """
+
+    def __init__(self, problems: Sequence[Problem], batch_fn: BatchFn):
+        self.problems = list(problems)
+        self.batch_fn = batch_fn
+        self.active = len(self.problems)
+        self.pending = {}
+        self.results = {}
+        self.rounds = 0
+        self.evaluations = 0
+        self.error: Optional[BaseException] = None
+        self.cv = threading.Condition()
+
+    def _run_if_complete(self):
+        if not self.pending or len(self.pending) < self.active:
+            return
+        batch = sorted(self.pending.items())
+        self.pending = {}
+        try:
+            out = self.batch_fn([(self.problems[i], x) for i, x in batch])
+            for (i, _), r in zip(batch, out):
+                self.results[i] = r
+        except BaseException as e:   # handed to every waiting optimizer
+            self.error = e
+        self.evaluations += len(batch)
+        self.rounds += 1
+        self.cv.notify_all()
+
+    def evaluate(self, i: int, x: np.ndarray) -> Tuple[float, np.ndarray]:
+        with self.cv:
+            if self.error is not None:
+                raise RuntimeError("batched evaluation failed") from self.error
+            self.pending[i] = np.array(x, dtype=np.float64)
+            rnd = self.rounds
+            self._run_if_complete()
+            while self.rounds == rnd:
+                self.cv.wait()
+            if self.error is not None:
+                raise RuntimeError("batched evaluation failed") from self.error
+            return self.results.pop(i)
+
+    def finish(self, i: int):
+        with self.cv:
+            self.active -= 1
+            self._run_if_complete()
+
+
+@dataclass
+class DesignResult:
+    widths: np.ndarray
+    F0: float
+    F: float
+    history: List[float] = field(default_factory=list)
+    iterations: int = 0
+    message: str = ""
+
+
+def maximize(problems: Sequence[Problem], batch_fn: BatchFn, iters: int = 20,
+             lo: float = 0.1, hi: float = 0.9, starts: Optional[Sequence[np.ndarray]] = None
+             ) -> Tuple[List[DesignResult], Lockstep]:
+    """L-BFGS-B on -F for every problem (start: its widths, or ``starts``)."""
+    from scipy.optimize import minimize
+
+    starts = [np.array(p.widths if starts is None else starts[k], dtype=np.float64)
+              for k, p in enumerate(problems)]
+    lock = Lockstep(problems, batch_fn)
+    results: List[Optional[DesignResult]] = [None] * len(problems)
+    errors: List[BaseException] = []
+
+    def run(k: int):
+        hist: List[float] = []
+
+        def fun(x):
+            F, g = lock.evaluate(k, x)
+            hist.append(float(F))
+            return -float(F), -np.asarray(g, dtype=np.float64)
+
+        try:
+            res = minimize(fun, starts[k], jac=True, method="L-BFGS-B",
+                           bounds=[(lo, hi)] * len(starts[k]),
+                           options={"maxiter": iters, "maxfun": 3 * iters + 5})
+            results[k] = DesignResult(widths=np.asarray(res.x), F0=hist[0], F=-float(res.fun),
+                                      history=hist, iterations=int(res.nit),
+                                      message=str(res.message))
+        except BaseException as e:
+            errors.append(e)
+        finally:
+            lock.finish(k)
+
+    threads = [threading.Thread(target=run, args=(k,), daemon=True) for k in range(len(problems))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    if errors:
+        raise errors[0]
+    return results, lock
+
+
+def gpu_batch_fn(device="cuda", precision: int = 0, buffers=None) -> BatchFn:
+    """Evaluations on the GPU: permittivity maps, one batched factorisation and
+    one batched adjoint (chunks of eight), width gradients.  ``buffers``: up to
+    eight factor buffers to reuse (allocated per call otherwise)."""
+    import torch
+    import paper_2207_10701_amd as rcp
+
+    def fn(batch):
+        out = []
+        for c0 in range(0, len(batch), 8):
+            chunk = batch[c0:c0 + 8]
+            probs = [replace(p, widths=tuple(float(v) for v in x)) for p, x in chunk]
+            wts = [torch.tensor(x, dtype=torch.float64, device=device) for _, x in chunk]
+            eps = [rcp.eps_from_widths(q, w, device=device) for q, w in zip(probs, wts)]
+            facs = rcp.factor_batch(probs, eps, precision,
+                                    buffers=buffers[:len(chunk)] if buffers else None)
+            F, grads = rcp.adjoint_grad_batch(facs, probs)
+            gw = [rcp.width_grad(q, g, w) for q, g, w in zip(probs, grads, wts)]
+            torch.cuda.synchronize()
+            Fh = F.cpu().numpy()
+            out.extend((float(Fh[k]), gw[k].cpu().numpy()) for k in range(len(chunk)))
+            del facs
+        return out
+
+    return fn
+
+
+def _main():
+    import argparse
+    import json
+
+    import torch
+    import workloads as W
+
+    ap = argparse.ArgumentParser(description="batched inverse design of pillar widths")
+    ap.add_argument("--config", default="config4_large",
+                    choices=["config1", "config2", "config3", "config4_large"])
+    ap.add_argument("--designs", type=int, default=8)
+    ap.add_argument("--iters", type=int, default=10)
+    args = ap.parse_args()
+    base = getattr(W, args.config)()
+    problems = [replace(base, widths=W.seeded_widths(len(base.widths), 9000 + k))
+                for k in range(args.designs)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, lock = maximize(problems, gpu_batch_fn(), iters=args.iters)
+    t = time.perf_counter() - t0
+    print(json.dumps({"config": args.config, "designs": args.designs, "iters": args.iters,
+                      "seconds": round(t, 3), "rounds": lock.rounds,
+                      "evaluations": lock.evaluations,
+                      "evaluations_per_s": round(lock.evaluations / t, 3),
+                      "gain": [round(r.F / r.F0, 3) for r in res]}))
+
+
+if __name__ == "__main__":
+    _main()

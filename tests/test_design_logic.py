@@ -1,0 +1,52 @@
+"""Host logic of the batched inverse-design loop (no GPU): lockstep batching of
+several L-BFGS-B runs on known objectives."""
+from dataclasses import replace
+
+import numpy as np
+
+import workloads as W
+from paper_2207_10701_amd.design import Lockstep, maximize
+
+
+def quad_batch(targets, calls):
+    def fn(batch):
+        calls.append(len(batch))
+        out = []
+        for p, x in batch:
+            t = targets[p.name]
+            F = -float(np.sum((x - t) ** 2))
+            out.append((F, -2.0 * (x - t)))
+        return out
+    return fn
+
+
+def test_lockstep_batches_every_running_optimizer_and_finds_the_bounded_optimum():
+    base = W.small_problem(3, 3, seed=1)
+    probs = [replace(base, name=f"d{k}", widths=W.seeded_widths(3, 50 + k)) for k in range(5)]
+    targets = {p.name: np.array([0.2 + 0.1 * k, 0.95, 0.05 + 0.5 * (k % 2)])
+               for k, p in enumerate(probs)}
+    calls = []
+    res, lock = maximize(probs, quad_batch(targets, calls), iters=50, lo=0.1, hi=0.9)
+    for k, r in enumerate(res):
+        want = np.clip(targets[probs[k].name], 0.1, 0.9)
+        np.testing.assert_allclose(r.widths, want, atol=1e-6)
+        assert r.F >= r.F0
+    # every round carried all optimizers still running, never more than there are
+    assert max(calls) == len(probs) and min(calls) >= 1
+    assert sum(calls) == lock.evaluations and len(calls) == lock.rounds
+    assert lock.rounds < lock.evaluations
+
+
+def test_lockstep_reports_a_failing_batch_to_every_optimizer():
+    base = W.small_problem(3, 3, seed=1)
+    probs = [replace(base, name=f"d{k}") for k in range(3)]
+
+    def bad(batch):
+        raise ValueError("boom")
+
+    try:
+        maximize(probs, bad, iters=3)
+    except RuntimeError as e:
+        assert "batched evaluation failed" in str(e)
+    else:
+        raise AssertionError("no error raised")
