@@ -217,6 +217,19 @@ __device__ __forceinline__ void load_ksteps(T2 (&av)[2][2], T2 (&bv)[2][2], cons
     }
 }
 
+// The same chunk from k-major panel tiles (element (r, k) at k TB + r).
+template <typename T2>
+__device__ __forceinline__ void load_ksteps_t(T2 (&av)[2][2], T2 (&bv)[2][2], const T2* A,
+                                              const T2* B, int ch, int lr, int lk) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      av[x][s] = A[(8 * ch + 4 * s + lk) * TB + 16 * x + lr];
+      bv[x][s] = B[(8 * ch + 4 * s + lk) * TB + 16 * x + lr];
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void mma_ksteps(typename v4of<T>::t (*cre)[2],
                                            typename v4of<T>::t (*cim)[2],
@@ -593,7 +606,11 @@ __device__ void lookahead_work(const GJJob& jb, int g, int nt, double2 (*Ps)[TB 
 // since S'_K,K2 = (Q0_K2)^T.  The look-ahead takes L3 = S''(:, K3), P3, Q3 and
 // then L4_I = S''_I,K4 - Q3_I (L3_K4)^T = S''_I,K4 - S''_I,K3 (Q3_K4)^T (P3 is
 // symmetric), P4 = (S''_K4,K4 - Q3_K4 L3_K4^T)^{-1}, Q4 = L4 P4.  Panel p lives
-// in slot p mod 4 of its chain's four panel buffers.
+// in slot p mod 4 of its chain's four panel buffers, each 32 x 32 panel tile
+// stored k-major (element (r, k) at k TB + r): the sixteen lanes that supply
+// one MFMA operand column then read 256 contiguous bytes instead of sixteen
+// rows.  The first two panels of a block come from the one-panel kernels
+// (row-major) and are transposed in place before the first pass.
 struct GJ2Job {
   int k;         // first panel of the pair this launch applies
   int nlook;     // panels formed ahead: 0, 1 (k+2) or 2 (k+2, k+3)
@@ -637,8 +654,9 @@ __device__ __forceinline__ T2* slot_ptr(void* base, int p, int nt) {
   return static_cast<T2*>(base) + size_t(p & 3) * nt * TB * TB;
 }
 
-// acc (MFMA accumulator layout) -= A B with A, B row-major TB x TB tiles (B not
-// transposed); blocks (a, b) with a in [a0, a1), b in [b0, b1).
+// acc (MFMA accumulator layout) -= A B with A, B k-major TB x TB panel tiles
+// (element (r, k) at k TB + r; B not transposed); blocks (a, b) with a in
+// [a0, a1), b in [b0, b1).
 template <typename T>
 __device__ __forceinline__ void tile_nn_update(typename v4of<T>::t (*cre)[2],
                                                typename v4of<T>::t (*cim)[2],
@@ -652,8 +670,8 @@ __device__ __forceinline__ void tile_nn_update(typename v4of<T>::t (*cre)[2],
     T2 av[2], bv[2];
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
-      if (x >= a0 && x < a1) av[x] = A[(16 * x + lr) * TB + kk];
-      if (x >= b0 && x < b1) bv[x] = B[kk * TB + 16 * x + lr];
+      if (x >= a0 && x < a1) av[x] = A[kk * TB + 16 * x + lr];
+      if (x >= b0 && x < b1) bv[x] = B[(16 * x + lr) * TB + kk];
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
@@ -671,9 +689,10 @@ __device__ __forceinline__ void tile_nn_update(typename v4of<T>::t (*cre)[2],
   }
 }
 
-// dst = sg (S - A0 B0^T - A1 B1^T): the accumulators start from S (no separate
-// copy of the tile in registers), then eight chunks of two k-steps, the next
-// chunk in flight while the current one multiplies.
+// dst = sg (S - A0 B0^T - A1 B1^T) with k-major panel tiles A0, B0, A1, B1:
+// the accumulators start from S (no separate copy of the tile in registers),
+// then eight chunks of two k-steps, the next chunk in flight while the
+// current one multiplies.
 template <typename T>
 __device__ __forceinline__ void tile_update2_pipelined(typename cplx<T>::t* dst,
                                                        const typename cplx<T>::t* A0,
@@ -695,20 +714,20 @@ __device__ __forceinline__ void tile_update2_pipelined(typename cplx<T>::t* dst,
         cim[a][b][q] = v.y;
       }
   T2 a0[2][2], b0[2][2], a1[2][2], b1[2][2];
-  load_ksteps(a0, b0, A0, B0, 0, lr, lk);
-  load_ksteps(a1, b1, A0, B0, 1, lr, lk);
+  load_ksteps_t(a0, b0, A0, B0, 0, lr, lk);
+  load_ksteps_t(a1, b1, A0, B0, 1, lr, lk);
   mma_ksteps<T>(cre, cim, a0, b0);
-  load_ksteps(a0, b0, A0, B0, 2, lr, lk);
+  load_ksteps_t(a0, b0, A0, B0, 2, lr, lk);
   mma_ksteps<T>(cre, cim, a1, b1);
-  load_ksteps(a1, b1, A0, B0, 3, lr, lk);
+  load_ksteps_t(a1, b1, A0, B0, 3, lr, lk);
   mma_ksteps<T>(cre, cim, a0, b0);
-  load_ksteps(a0, b0, A1, B1, 0, lr, lk);
+  load_ksteps_t(a0, b0, A1, B1, 0, lr, lk);
   mma_ksteps<T>(cre, cim, a1, b1);
-  load_ksteps(a1, b1, A1, B1, 1, lr, lk);
+  load_ksteps_t(a1, b1, A1, B1, 1, lr, lk);
   mma_ksteps<T>(cre, cim, a0, b0);
-  load_ksteps(a0, b0, A1, B1, 2, lr, lk);
+  load_ksteps_t(a0, b0, A1, B1, 2, lr, lk);
   mma_ksteps<T>(cre, cim, a1, b1);
-  load_ksteps(a1, b1, A1, B1, 3, lr, lk);
+  load_ksteps_t(a1, b1, A1, B1, 3, lr, lk);
   mma_ksteps<T>(cre, cim, a0, b0);
   mma_ksteps<T>(cre, cim, a1, b1);
 #pragma unroll
@@ -762,7 +781,7 @@ __device__ void update2_work(const GJ2Job& jb, int wg, int nt, size_t tiles) {
     const T2* q = Q1 + (J == K2 ? I : J) * TT;
     for (int e = lane; e < TB * TB; e += 64) {
       const int rr = e / TB, cc = e % TB;
-      T2 v = (J == K2) ? q[e] : q[cc * TB + rr];
+      T2 v = (J == K2) ? q[cc * TB + rr] : q[e];
       v.x *= sg;
       v.y *= sg;
       dst[e] = v;
@@ -788,7 +807,7 @@ __device__ void update2_work(const GJ2Job& jb, int wg, int nt, size_t tiles) {
           if (I == K && J == K) {
             base = cneg(P0[rr * TB + cc]);
           } else {
-            base = to_c128(Q0[R * TT + rr * TB + cc]);
+            base = to_c128(Q0[R * TT + cc * TB + rr]);
           }
           T2 v;
           v.x = (static_cast<T>(base.x) + cre[a][b][q]) * sg;
@@ -801,6 +820,29 @@ __device__ void update2_work(const GJ2Job& jb, int wg, int nt, size_t tiles) {
     return;
   }
   tile_update2_pipelined<T>(dst, Q0 + I * TT, L0 + J * TT, Q1 + I * TT, L1 + J * TT, sg, lr, lk);
+}
+
+// acc (one 16 x 16 block) -= A B^T over the 32 k of k-major panel tiles, A and
+// B offset to the block's first row (element (r, k) at k TB + r).
+template <typename T>
+__device__ __forceinline__ void quad_nt_update_t(typename v4of<T>::t& cre, typename v4of<T>::t& cim,
+                                                 const typename cplx<T>::t* A,
+                                                 const typename cplx<T>::t* B, int lr, int lk) {
+  using T2 = typename cplx<T>::t;
+  T2 av[8], bv[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    av[s] = A[(4 * s + lk) * TB + lr];
+    bv[s] = B[(4 * s + lk) * TB + lr];
+  }
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const T nare = -av[s].x, aim = av[s].y, naim = -av[s].y;
+    cre = mfma16(nare, bv[s].x, cre);
+    cim = mfma16(nare, bv[s].y, cim);
+    cre = mfma16(aim, bv[s].y, cre);
+    cim = mfma16(naim, bv[s].x, cim);
+  }
 }
 
 // Quadrant (qa, qb) of S''_{R,C} for R >= C, R, C not in {K, K2}.
@@ -820,10 +862,10 @@ __device__ __forceinline__ void quad2(const GJ2Job& jb, int nt, int R, int C,
     dre[0][0][q] = v.x;
     dim[0][0][q] = v.y;
   }
-  tile_nt_update<T>(dre, dim, slot_ptr<T2>(jb.Qb, K, nt) + R * TT + (16 * qa) * TB,
-                    slot_ptr<T2>(jb.Lb, K, nt) + C * TT + (16 * qb) * TB, lr, lk, 0, 1, 0, 1);
-  tile_nt_update<T>(dre, dim, slot_ptr<T2>(jb.Qb, K2, nt) + R * TT + (16 * qa) * TB,
-                    slot_ptr<T2>(jb.Lb, K2, nt) + C * TT + (16 * qb) * TB, lr, lk, 0, 1, 0, 1);
+  quad_nt_update_t<T>(dre[0][0], dim[0][0], slot_ptr<T2>(jb.Qb, K, nt) + R * TT + 16 * qa,
+                      slot_ptr<T2>(jb.Lb, K, nt) + C * TT + 16 * qb, lr, lk);
+  quad_nt_update_t<T>(dre[0][0], dim[0][0], slot_ptr<T2>(jb.Qb, K2, nt) + R * TT + 16 * qa,
+                      slot_ptr<T2>(jb.Lb, K2, nt) + C * TT + 16 * qb, lr, lk);
 }
 
 template <typename T>
@@ -849,7 +891,7 @@ __device__ __forceinline__ void store_lt(const typename v4of<T>::t (*cre)[2],
       T2 v;
       v.x = cre[a2][0][q];
       v.y = cim[a2][0][q];
-      Lt[(16 * qa + lr) * TB + 16 * a2 + mfma_row<T>(lk, q)] = v;
+      Lt[(16 * a2 + mfma_row<T>(lk, q)) * TB + 16 * qa + lr] = v;
     }
 }
 
@@ -886,13 +928,13 @@ __device__ void pivot2_work(const GJ2Job& jb, int nt, double2 (*B1)[TB + 1],
   quad2<T>(jb, nt, K4, K3, ere, eim, lr, lk, qa, qb);
   quad_to_lds<T>(ere, eim, B2, lr, lk, qa, qb);
   {   // E is row K4 of the K3 panel's L buffer
-    T2* Lt = slot_ptr<T2>(jb.Lb, K3, nt) + K4 * TT + (16 * qa) * TB + 16 * qb;
+    T2* Lt = slot_ptr<T2>(jb.Lb, K3, nt) + K4 * TT + (16 * qb) * TB + 16 * qa;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       T2 v;
       v.x = ere[0][0][q];
       v.y = eim[0][0][q];
-      Lt[mfma_row<T>(lk, q) * TB + lr] = v;
+      Lt[lr * TB + mfma_row<T>(lk, q)] = v;
     }
   }
   quad2<T>(jb, nt, K4, K4, fre, fim, lr, lk, qa, qb);
@@ -910,7 +952,7 @@ __device__ void pivot2_work(const GJ2Job& jb, int nt, double2 (*B1)[TB + 1],
     qim = mfma16(aim, bre, qim);
   }
   {
-    T2* Qt = slot_ptr<T2>(jb.Qb, K3, nt) + K4 * TT + (16 * qa) * TB + 16 * qb;
+    T2* Qt = slot_ptr<T2>(jb.Qb, K3, nt) + K4 * TT + (16 * qb) * TB + 16 * qa;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       B3[16 * qa + mfma_row<T>(lk, q)][16 * qb + lr] =
@@ -918,7 +960,7 @@ __device__ void pivot2_work(const GJ2Job& jb, int nt, double2 (*B1)[TB + 1],
       T2 v;
       v.x = qre[q];
       v.y = qim[q];
-      Qt[mfma_row<T>(lk, q) * TB + lr] = v;
+      Qt[lr * TB + mfma_row<T>(lk, q)] = v;
     }
   }
   __syncthreads();
@@ -985,13 +1027,13 @@ __device__ __forceinline__ void q_quad_f(const typename v4of<T>::t (*cre)[2],
     qre = mfma16(-aim, bim, qre);
     qim = mfma16(aim, bre, qim);
   }
-  T2* Qb = Qt + (16 * qa) * TB + 16 * qb;
+  T2* Qb = Qt + (16 * qb) * TB + 16 * qa;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     T2 v;
     v.x = qre[q];
     v.y = qim[q];
-    Qb[mfma_row<T>(lk, q) * TB + lr] = v;
+    Qb[lr * TB + mfma_row<T>(lk, q)] = v;
   }
 }
 
@@ -1023,7 +1065,7 @@ __device__ void rows2_work(const GJ2Job& jb, int I, int nt) {
     for (int a2 = 0; a2 < 2; ++a2)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const T2 v = Qk[(16 * a2 + mfma_row<T>(lk, q)) * TB + 16 * qa + lr];
+        const T2 v = Qk[(16 * qa + lr) * TB + 16 * a2 + mfma_row<T>(lk, q)];
         c4re[a2][0][q] = v.x;
         c4im[a2][0][q] = v.y;
       }
@@ -1036,7 +1078,7 @@ __device__ void rows2_work(const GJ2Job& jb, int I, int nt) {
 #pragma unroll
       for (int s = 0; s < 8; ++s)
 #pragma unroll
-        for (int a2 = 0; a2 < 2; ++a2) qk[s][a2] = Qk[(16 * a2 + lr) * TB + acc_k<T>(s, lk)];
+        for (int a2 = 0; a2 < 2; ++a2) qk[s][a2] = Qk[acc_k<T>(s, lk) * TB + 16 * a2 + lr];
     }
   }
   if (two) {
@@ -1154,6 +1196,35 @@ __global__ __launch_bounds__(256) void k_gj2_rows(GJ2Jobs jobs, int nt) {
   int tmp = q * jobs.j[0].wgs + w;
   GJ2Job jb = pick2(jobs, &tmp);
   rows2_work<T>(jb, w, nt);
+}
+
+// Panel tiles p0 .. p0 + np - 1 (slot p mod 4) of each job's L and Q buffers
+// transposed in place, one tile per workgroup: the one-panel kernels write
+// row-major tiles, the two-panel passes read and write k-major ones.
+struct PanelTr {
+  void* L;
+  void* Q;
+};
+struct PanelTrs {
+  PanelTr j[MAXJ];
+  int n;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_panel_transpose(PanelTrs js, int nt, int p0, int np) {
+  using T2 = typename cplx<T>::t;
+  __shared__ T2 buf[TB][TB + 1];
+  const int per = 2 * np * nt;
+  const int q = blockIdx.x / per;
+  int r = blockIdx.x - q * per;
+  const int which = r / (np * nt);
+  r -= which * np * nt;
+  const int p = p0 + r / nt, I = r % nt;
+  void* const base = which ? RCP_SEL16(js, q, Q) : RCP_SEL16(js, q, L);
+  T2* const t = slot_ptr<T2>(base, p, nt) + size_t(I) * TB * TB;
+  for (int e = threadIdx.x; e < TB * TB; e += 256) buf[e / TB][e % TB] = t[e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < TB * TB; e += 256) t[e] = buf[e % TB][e / TB];
 }
 
 // dst = D - C1 src1 C1 - C2 src2 C2 on packed tiles (src may be null), with
@@ -1319,6 +1390,13 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
         k_gj_fused<T, 2><<<grid, 256, 0, s>>>(js, nt, tiles);
       RCP_HIP(hipGetLastError());
     }
+    PanelTrs tr{};
+    for (int q = 0; q < nch; ++q)
+      tr.j[tr.n++] = PanelTr{fs[ch[q].g]->wsL[4 * ch[q].c], fs[ch[q].g]->wsQ[4 * ch[q].c]};
+    if (nt >= 2) {   // panels 0 and 1 to the k-major layout of the passes
+      k_panel_transpose<T><<<nch * 2 * 2 * nt, 256, 0, s>>>(tr, nt, 0, 2);
+      RCP_HIP(hipGetLastError());
+    }
     // pairs (K, K+1); the look-ahead forms the next pair (or the last panel)
     for (int K = 0; K + 1 < nt; K += 2) {
       const int nlook = nt - (K + 2) >= 2 ? 2 : nt - (K + 2);
@@ -1353,6 +1431,10 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
       }
     }
     if (nt & 1) {   // odd panel count: the last panel alone, negated
+      if (nt >= 3) {   // formed by the last pass: back to row-major
+        k_panel_transpose<T><<<nch * 2 * 1 * nt, 256, 0, s>>>(tr, nt, nt - 1, 1);
+        RCP_HIP(hipGetLastError());
+      }
       GJJobs js{};
       for (int q = 0; q < nch; ++q) {
         GJJob b = job(ch[q], nt - 1);

@@ -111,6 +111,11 @@ def test_config2_reciprocal_equals_converged_brute_force(rcp):
     assert rel < 1e-9
 
 
+@lru_cache(maxsize=None)
+def config2_oracle():
+    return ora.adjoint(ora.setup(W.config2()))
+
+
 @pytest.mark.timeout(900)
 def test_config2_matches_oracle_at_full_size(rcp):
     """Benchmark size (2040 x 1080): GPU reciprocal field, F and adjoint against the
@@ -122,10 +127,48 @@ def test_config2_matches_oracle_at_full_size(rcp):
     Fa, g = rcp.adjoint_grad(fac, p)
     zg = z.cpu().numpy().ravel()
     gg = g.cpu().numpy()
-    ref = ora.adjoint(ora.setup(p))
+    ref = config2_oracle()
     assert np.linalg.norm(zg - ref.z) / np.linalg.norm(ref.z) < 1e-10
     assert abs(F.item() - ref.F) / ref.F < 1e-10
     assert np.linalg.norm(gg - ref.grad_eps) / np.linalg.norm(ref.grad_eps) < 1e-9
+
+
+@pytest.mark.timeout(900)
+def test_config2_batch_of_eight_as_benchmarked(rcp):
+    """The benchmark's launch configuration: eight config-2 geometries (the
+    benchmark's widths) factored side by side, sixteen chains in every launch
+    (two per XCD).  Geometry 0 (the config-2 widths) against the oracle: field, F
+    and adjoint; the last two bit-identical to their factorisation as a batch of
+    two (four chains); batched adjoints equal single ones."""
+    import torch
+    from dataclasses import replace
+    p = W.config2()
+    probs = [replace(p, widths=W.seeded_widths(len(p.widths), 1002 + 97 * k)) for k in range(8)]
+    assert probs[0].widths == p.widths
+    eps = [rcp.eps_from_widths(q) for q in probs]
+    facs = rcp.factor_batch(probs, eps)
+    F0, z0 = rcp.reciprocal_average(facs[0], probs[0], want_z=True)
+    Fs = [rcp.reciprocal_average(f, q).item() for f, q in zip(facs, probs)]
+    Fb, gb = rcp.adjoint_grad_batch(facs, probs)
+    F7, g7 = rcp.adjoint_grad(facs[7], probs[7])
+    assert Fb[7].item() == F7.item() and torch.equal(gb[7], g7)
+    z0 = z0.cpu().numpy().ravel()
+    g0 = gb[0].cpu().numpy()
+    del facs, F7, g7
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    pair = rcp.factor_batch(probs[6:], eps[6:])
+    for f, q, F in zip(pair, probs[6:], Fs[6:]):
+        assert rcp.reciprocal_average(f, q).item() == F
+    del pair
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    assert len(set(Fs)) == 8
+    ref = config2_oracle()
+    assert np.linalg.norm(z0 - ref.z) / np.linalg.norm(ref.z) < 1e-10
+    assert abs(F0.item() - ref.F) / ref.F < 1e-10
+    assert abs(Fs[0] - ref.F) / ref.F < 1e-10
+    assert np.linalg.norm(g0 - ref.grad_eps) / np.linalg.norm(ref.grad_eps) < 1e-9
 
 
 @pytest.mark.timeout(900)
