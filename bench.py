@@ -67,9 +67,9 @@ DESCR = {
 # for the kernel source it was measured on: reported when factor.hip still has
 # this hash.
 TRAFFIC = {"config": "config2", "batch": 8,
-           "sha256": "51c48179a4c8148c97f159d8727ba250eddef14b8cbf81001ec8a6cb3c43a7a8",
-           "fetch_bytes": 239355883,     # 116876.2 KiB FETCH_SIZE x 1.99995
-           "write_bytes": 156265267}    # 152602.8 KiB WRITE_SIZE x 1.00000
+           "sha256": "251856f62f609e0b2ffab7c71b57a6079310f3e17daad0fee73ebae3d4252a76",
+           "fetch_bytes": 240000371,     # 117190.9 KiB FETCH_SIZE x 1.99995
+           "write_bytes": 156255642}    # 152593.4 KiB WRITE_SIZE x 1.00000
 
 
 def factor_source_sha256():
