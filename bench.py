@@ -541,6 +541,16 @@ def main():
         torch.cuda.synchronize()
         t_f32 = a.elapsed_time(b) * 1e-3
         it, res = f32.last_solve_stats()
+        t_b32 = None
+        if B > 1:   # the step's B geometries with FP32 factors, side by side
+            eps_b = [rcp.eps_from_widths(p, w, device=dev) for w in widths[-B:]]
+            torch.cuda.synchronize()
+            a.record(stream)
+            facs32 = rcp.factor_batch([p] * B, eps_b, rcp.RCP_FP32_REFINED, buffers=bufs)
+            b.record(stream)
+            torch.cuda.synchronize()
+            t_b32 = a.elapsed_time(b) * 1e-3
+            del facs32, eps_b
         fac = rcp.Factors(p, eps, rcp.RCP_FP64, buffer=buf)
         F64, z64 = rcp.reciprocal_average(fac, p, want_z=True)
         torch.cuda.synchronize()
@@ -553,6 +563,15 @@ def main():
                                "refine_steps": it, "rel_residual": res,
                                "field_rel_err_vs_fp64": zerr,
                                "F_rel_err_vs_fp64": abs(F32.item() - F64.item()) / abs(F64.item())}
+        if t_b32 is not None:
+            out["fp32_refined"]["lu_batch"] = {
+                "geometries": B, "seconds": round(t_b32, 5),
+                "tflops_nominal": round(B * nominal_lu_flops(p) / t_b32 / 1e12, 3),
+                "tflops_executed": round(B * executed_lu_flops(p) / t_b32 / 1e12, 3),
+                "frac_fp32_peak_executed":
+                    round(B * executed_lu_flops(p) / t_b32 / 1e12 / FP32_PEAK_TFLOPS, 4),
+                "speedup_vs_fp64_batch": round(out["lu_batch"]["seconds"] / t_b32, 3)
+                if "lu_batch" in out else None}
         log(f"fp32 refined: factor {t_f32 * 1e3:.1f} ms, {it} steps, field err {zerr:.2e}")
         del f32, buf32
         # broadband: the geometry at the eight wavelengths of a flat spectral rule

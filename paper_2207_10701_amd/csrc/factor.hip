@@ -988,22 +988,30 @@ __device__ void pivot2_work(const GJ2Job& jb, int nt, double2 (*B1)[TB + 1],
 
 // Rows 16 qa .. 16 qa + 15 of tile (I, C) of the full symmetric matrix as the
 // accumulator blocks (a', qa), a' = 0, 1, of its transpose, from the packed
-// tiles (tile (I, C) for I > C, tile (C, I) transposed for I < C).
+// tiles (tile (I, C) for I > C, tile (C, I) transposed for I < C), staged in
+// LDS first.
+// Staging: the stored tile (max(I, C), min(I, C)) copied row-major into LDS by
+// the workgroup with contiguous loads.
 template <typename T>
-__device__ __forceinline__ void load_lt(const GJ2Job& jb, int I, int C,
-                                        typename v4of<T>::t (*cre)[2],
-                                        typename v4of<T>::t (*cim)[2], int lr, int lk, int qa) {
+__device__ __forceinline__ void stage_tile(const GJ2Job& jb, int I, int C,
+                                           typename cplx<T>::t (*lds)[TB + 1]) {
   using T2 = typename cplx<T>::t;
-  const T2* X = static_cast<const T2*>(jb.X);
-  const size_t TT = size_t(TB) * TB;
-  const bool below = I > C;
-  const T2* src = X + (below ? tile_index(I, C) : tile_index(C, I)) * TT;
+  const T2* src = static_cast<const T2*>(jb.X) +
+                  (I > C ? tile_index(I, C) : tile_index(C, I)) * size_t(TB) * TB;
+  for (int e = threadIdx.x; e < TB * TB; e += 256) lds[e / TB][e % TB] = src[e];
+}
+
+// Reading the rows from the staged tile (below: the stored tile is (I, C)).
+template <typename T>
+__device__ __forceinline__ void load_lt_lds(const typename cplx<T>::t (*lds)[TB + 1], bool below,
+                                            typename v4of<T>::t (*cre)[2],
+                                            typename v4of<T>::t (*cim)[2], int lr, int lk, int qa) {
 #pragma unroll
   for (int a2 = 0; a2 < 2; ++a2)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = 16 * a2 + mfma_row<T>(lk, q), j = 16 * qa + lr;
-      const T2 v = below ? src[j * TB + i] : src[i * TB + j];
+      const typename cplx<T>::t v = below ? lds[j][i] : lds[i][j];
       cre[a2][0][q] = v.x;
       cim[a2][0][q] = v.y;
     }
@@ -1043,7 +1051,7 @@ __device__ __forceinline__ void q_quad_f(const typename v4of<T>::t (*cre)[2],
 // Row K4 of panel K3 and the pivots come from the pivot work.  Every operand
 // is loaded before the first store, so one memory latency covers the row.
 template <typename T>
-__device__ void rows2_work(const GJ2Job& jb, int I, int nt) {
+__device__ void rows2_work(const GJ2Job& jb, int I, int nt, typename cplx<T>::t (*lt)[TB][TB + 1]) {
   using T2 = typename cplx<T>::t;
   using V4 = typename v4of<T>::t;
   const int K = jb.k, K3 = K + 2, K4 = K + 3;
@@ -1070,8 +1078,11 @@ __device__ void rows2_work(const GJ2Job& jb, int I, int nt) {
         c4im[a2][0][q] = v.y;
       }
   } else {
-    load_lt<T>(jb, I, K3, c3re, c3im, lr, lk, qa);
-    if (two) load_lt<T>(jb, I, K4, c4re, c4im, lr, lk, qa);
+    // S''_{I,K3} (and S''_{I,K4}) through LDS: half of them are stored
+    // transposed, and a direct read in the accumulator layout would take
+    // sixteen rows per quarter-wave
+    stage_tile<T>(jb, I, K3, lt[0]);
+    if (two) stage_tile<T>(jb, I, K4, lt[1]);
 #pragma unroll
     for (int s = 0; s < 8; ++s) p3[s] = P3[acc_k<T>(s, lk) * TB + 16 * qb + lr];
     if (two) {
@@ -1080,6 +1091,9 @@ __device__ void rows2_work(const GJ2Job& jb, int I, int nt) {
 #pragma unroll
         for (int a2 = 0; a2 < 2; ++a2) qk[s][a2] = Qk[acc_k<T>(s, lk) * TB + 16 * a2 + lr];
     }
+    __syncthreads();
+    load_lt_lds<T>(lt[0], I > K3, c3re, c3im, lr, lk, qa);
+    if (two) load_lt_lds<T>(lt[1], I > K4, c4re, c4im, lr, lk, qa);
   }
   if (two) {
 #pragma unroll
@@ -1191,11 +1205,12 @@ __global__ __launch_bounds__(256, 2) void k_gj2_fused(GJ2Jobs jobs, int nt, size
 // The row tiles of panels k+2 (and k+3), one per workgroup.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj2_rows(GJ2Jobs jobs, int nt) {
+  __shared__ typename cplx<T>::t lt[2][TB][TB + 1];
   int q, w;
   if (!job_of(jobs.n, jobs.j[0].wgs, &q, &w)) return;
   int tmp = q * jobs.j[0].wgs + w;
   GJ2Job jb = pick2(jobs, &tmp);
-  rows2_work<T>(jb, w, nt);
+  rows2_work<T>(jb, w, nt, lt);
 }
 
 // Panel tiles p0 .. p0 + np - 1 (slot p mod 4) of each job's L and Q buffers
