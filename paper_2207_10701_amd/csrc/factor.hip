@@ -1051,7 +1051,8 @@ __device__ __forceinline__ void q_quad_f(const typename v4of<T>::t (*cre)[2],
 // Row K4 of panel K3 and the pivots come from the pivot work.  Every operand
 // is loaded before the first store, so one memory latency covers the row.
 template <typename T>
-__device__ void rows2_work(const GJ2Job& jb, int I, int nt, typename cplx<T>::t (*lt)[TB][TB + 1]) {
+__device__ void rows2_work(const GJ2Job& jb, int I, int nt, typename cplx<T>::t (*lt)[TB][TB + 1],
+                           typename cplx<T>::t (*xch)[4][64]) {
   using T2 = typename cplx<T>::t;
   using V4 = typename v4of<T>::t;
   const int K = jb.k, K3 = K + 2, K4 = K + 3;
@@ -1067,7 +1068,7 @@ __device__ void rows2_work(const GJ2Job& jb, int I, int nt, typename cplx<T>::t 
   if (two && I == K4) return;
   V4 c3re[2][2], c3im[2][2], c4re[2][2], c4im[2][2];
   double2 p3[8], p4[8];
-  T2 qk[8][2];
+  T2 qk[8];   // row block qb of Q3_K4, the part of the L4 update this wave does
   if (I == K3) {   // L4_K3^T = Q3_K4
 #pragma unroll
     for (int a2 = 0; a2 < 2; ++a2)
@@ -1087,9 +1088,7 @@ __device__ void rows2_work(const GJ2Job& jb, int I, int nt, typename cplx<T>::t 
     for (int s = 0; s < 8; ++s) p3[s] = P3[acc_k<T>(s, lk) * TB + 16 * qb + lr];
     if (two) {
 #pragma unroll
-      for (int s = 0; s < 8; ++s)
-#pragma unroll
-        for (int a2 = 0; a2 < 2; ++a2) qk[s][a2] = Qk[acc_k<T>(s, lk) * TB + 16 * a2 + lr];
+      for (int s = 0; s < 8; ++s) qk[s] = Qk[acc_k<T>(s, lk) * TB + 16 * qb + lr];
     }
     __syncthreads();
     load_lt_lds<T>(lt[0], I > K3, c3re, c3im, lr, lk, qa);
@@ -1103,18 +1102,38 @@ __device__ void rows2_work(const GJ2Job& jb, int I, int nt, typename cplx<T>::t 
     if (qb == 0) store_lt<T>(c3re, c3im, slot_ptr<T2>(jb.Lb, K3, nt) + I * TT, lr, lk, qa);
     q_quad_f<T>(c3re, c3im, p3, slot_ptr<T2>(jb.Qb, K3, nt) + I * TT, lr, lk, qa, qb);
     if (!two) return;
+    // L4_I^T -= Q3_K4 L3_I^T, right operand from the L3 blocks: block (qb, qa)
+    // here, block (1 - qb, qa) in the wave of the same qa, exchanged in LDS
+    V4 hre = qb ? c4re[1][0] : c4re[0][0];
+    V4 him = qb ? c4im[1][0] : c4im[0][0];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {   // L4_I^T -= Q3_K4 L3_I^T, right operand from the L3 blocks
+    for (int s = 0; s < 8; ++s) {
       const T bre = c3re[s >> 2][0][s & 3], bim = c3im[s >> 2][0][s & 3];
-#pragma unroll
-      for (int a2 = 0; a2 < 2; ++a2) {
-        const T nare = -qk[s][a2].x, aim = qk[s][a2].y, naim = -qk[s][a2].y;
-        c4re[a2][0] = mfma16(nare, bre, c4re[a2][0]);
-        c4im[a2][0] = mfma16(nare, bim, c4im[a2][0]);
-        c4re[a2][0] = mfma16(aim, bim, c4re[a2][0]);
-        c4im[a2][0] = mfma16(naim, bre, c4im[a2][0]);
-      }
+      const T nare = -qk[s].x, aim = qk[s].y, naim = -qk[s].y;
+      hre = mfma16(nare, bre, hre);
+      him = mfma16(nare, bim, him);
+      hre = mfma16(aim, bim, hre);
+      him = mfma16(naim, bre, him);
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      T2 v;
+      v.x = hre[q];
+      v.y = him[q];
+      xch[wave][q][lane] = v;
+    }
+    __syncthreads();
+    V4 ore, oim;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T2 v = xch[wave ^ 1][q][lane];
+      ore[q] = v.x;
+      oim[q] = v.y;
+    }
+    c4re[0][0] = qb ? ore : hre;
+    c4im[0][0] = qb ? oim : him;
+    c4re[1][0] = qb ? hre : ore;
+    c4im[1][0] = qb ? him : oim;
   }
   if (qb == 0) store_lt<T>(c4re, c4im, slot_ptr<T2>(jb.Lb, K4, nt) + I * TT, lr, lk, qa);
   q_quad_f<T>(c4re, c4im, p4, slot_ptr<T2>(jb.Qb, K4, nt) + I * TT, lr, lk, qa, qb);
@@ -1206,11 +1225,12 @@ __global__ __launch_bounds__(256, 2) void k_gj2_fused(GJ2Jobs jobs, int nt, size
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj2_rows(GJ2Jobs jobs, int nt) {
   __shared__ typename cplx<T>::t lt[2][TB][TB + 1];
+  __shared__ typename cplx<T>::t xch[4][4][64];
   int q, w;
   if (!job_of(jobs.n, jobs.j[0].wgs, &q, &w)) return;
   int tmp = q * jobs.j[0].wgs + w;
   GJ2Job jb = pick2(jobs, &tmp);
-  rows2_work<T>(jb, w, nt, lt);
+  rows2_work<T>(jb, w, nt, lt, xch);
 }
 
 // Panel tiles p0 .. p0 + np - 1 (slot p mod 4) of each job's L and Q buffers
