@@ -67,9 +67,9 @@ DESCR = {
 # for the kernel source it was measured on: reported when factor.hip still has
 # this hash.
 TRAFFIC = {"config": "config2", "batch": 8,
-           "sha256": "251856f62f609e0b2ffab7c71b57a6079310f3e17daad0fee73ebae3d4252a76",
-           "fetch_bytes": 240000371,     # 117190.9 KiB FETCH_SIZE x 1.99995
-           "write_bytes": 156255642}    # 152593.4 KiB WRITE_SIZE x 1.00000
+           "sha256": "c43e94fd9b57d78449a943e3cd3d0a40906bfb2dee04134e22ae6ed378093999",
+           "fetch_bytes": 239119551,     # 116760.8 KiB FETCH_SIZE x 1.99995
+           "write_bytes": 156256051}    # 152593.8 KiB WRITE_SIZE x 1.00000
 
 
 def factor_source_sha256():
