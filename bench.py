@@ -13,7 +13,8 @@ solver over 1000 planewave right-hand sides), the average over 16 outputs under
 a non-translation-invariant (dense W) correlated light, a broadband evaluation
 (the geometry at 8 wavelengths, factored side by side), a few batched L-BFGS-B
 iterations of inverse design, the FP32-factor + FP64-refinement
-variant, the factorisation rate (LU TF/s), the live roofline of the dominant
+variant (one geometry, and the B geometries factored side by side), the
+factorisation rate (LU TF/s), the live roofline of the dominant
 kernel (HIP events on the launching stream), and the FP64 CPU oracle timed on
 a bounded sample of the same workload.
 
