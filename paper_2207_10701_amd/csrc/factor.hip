@@ -609,8 +609,8 @@ __device__ void lookahead_work(const GJJob& jb, int g, int nt, double2 (*Ps)[TB 
 // in slot p mod 4 of its chain's four panel buffers, each 32 x 32 panel tile
 // stored k-major (element (r, k) at k TB + r): the sixteen lanes that supply
 // one MFMA operand column then read 256 contiguous bytes instead of sixteen
-// rows.  The first two panels of a block come from the one-panel kernels
-// (row-major) and are transposed in place before the first pass.
+// rows.  A block opens with pass K = -2, which applies nothing and forms
+// panels 0 and 1 by the same pivot work and row launch.
 struct GJ2Job {
   int k;         // first panel of the pair this launch applies
   int nlook;     // panels formed ahead: 0, 1 (k+2) or 2 (k+2, k+3)
@@ -862,6 +862,7 @@ __device__ __forceinline__ void quad2(const GJ2Job& jb, int nt, int R, int C,
     dre[0][0][q] = v.x;
     dim[0][0][q] = v.y;
   }
+  if (K < 0) return;   // the start of a block: no panels applied yet
   quad_nt_update_t<T>(dre[0][0], dim[0][0], slot_ptr<T2>(jb.Qb, K, nt) + R * TT + 16 * qa,
                       slot_ptr<T2>(jb.Lb, K, nt) + C * TT + 16 * qb, lr, lk);
   quad_nt_update_t<T>(dre[0][0], dim[0][0], slot_ptr<T2>(jb.Qb, K2, nt) + R * TT + 16 * qa,
@@ -1359,7 +1360,7 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
       b.health = f->health + size_t(x.block) * nt + (k + 1 < nt ? k + 1 : k);
       return b;
     };
-    {   // panel 0 (the "next" slot of k = -1, i.e. slot 0)
+    if (!pairs || nt < 2) {   // panel 0 (the "next" slot of k = -1, i.e. slot 0)
       GJJobs js{};
       for (int q = 0; q < nch; ++q) {
         GJJob b = job(ch[q], -1);
@@ -1407,36 +1408,17 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
       RCP_HIP(hipGetLastError());
       return RCP_OK;
     }
-    if (nt >= 2) {   // panel 1 from the untouched tiles and panel 0 (look-ahead only)
-      const int R = nch >= 16 ? 2 : 1;
-      const int look_wgs = ceil_div(nt, R);
-      GJJobs js{};
-      for (int q = 0; q < nch; ++q) {
-        GJJob b = job(ch[q], 0);
-        b.wgs_upd = 0;
-        b.wgs = look_wgs;
-        js.j[js.n++] = b;
-      }
-      KTimer kt(K_GJ_PANEL, s, nch * cmac * nt);
-      const int grid = grid_size(nch, look_wgs);
-      if (R == 1)
-        k_gj_fused<T, 1><<<grid, 256, 0, s>>>(js, nt, tiles);
-      else
-        k_gj_fused<T, 2><<<grid, 256, 0, s>>>(js, nt, tiles);
-      RCP_HIP(hipGetLastError());
-    }
     PanelTrs tr{};
     for (int q = 0; q < nch; ++q)
       tr.j[tr.n++] = PanelTr{fs[ch[q].g]->wsL[4 * ch[q].c], fs[ch[q].g]->wsQ[4 * ch[q].c]};
-    if (nt >= 2) {   // panels 0 and 1 to the k-major layout of the passes
-      k_panel_transpose<T><<<nch * 2 * 2 * nt, 256, 0, s>>>(tr, nt, 0, 2);
-      RCP_HIP(hipGetLastError());
-    }
-    // pairs (K, K+1); the look-ahead forms the next pair (or the last panel)
-    for (int K = 0; K + 1 < nt; K += 2) {
+    // pairs (K, K+1); the look-ahead forms the next pair (or the last panel).
+    // K = -2 opens the block: no panels to apply, only the pivot work and row
+    // tiles of panels 0 and 1 on the untouched tiles
+    for (int K = -2; K + 1 < nt; K += 2) {
       const int nlook = nt - (K + 2) >= 2 ? 2 : nt - (K + 2);
       const int last = nlook == 0 ? 1 : 0;
       const int look_wgs = nlook > 0 ? 1 : 0;   // the pivot work of the next pair
+      const int upd = K < 0 ? 0 : upd_wgs;
       GJ2Jobs js{};
       for (int q = 0; q < nch; ++q) {
         const rcp_factors* f = fs[ch[q].g];
@@ -1444,8 +1426,8 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
         b.k = K;
         b.nlook = nlook;
         b.last = last;
-        b.wgs_upd = upd_wgs;
-        b.wgs = upd_wgs + look_wgs;
+        b.wgs_upd = upd;
+        b.wgs = upd + look_wgs;
         b.X = block_ptr(f, ch[q].block);
         b.Lb = f->wsL[4 * ch[q].c];
         b.Qb = f->wsQ[4 * ch[q].c];
@@ -1454,8 +1436,9 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
         js.j[js.n++] = b;
       }
       {
-        KTimer kt(last ? K_GJ_LAST : K_GJ_UPDATE, s, nch * 2.0 * cmac * double(tiles));
-        k_gj2_fused<T><<<grid_size(nch, upd_wgs + look_wgs), 256, 0, s>>>(js, nt, tiles);
+        KTimer kt(K < 0 ? K_GJ_PANEL : (last ? K_GJ_LAST : K_GJ_UPDATE), s,
+                  K < 0 ? nch * 6.0 * cmac : nch * 2.0 * cmac * double(tiles));
+        k_gj2_fused<T><<<grid_size(nch, upd + look_wgs), 256, 0, s>>>(js, nt, tiles);
         RCP_HIP(hipGetLastError());
       }
       if (nlook > 0) {   // row tiles of the next pair's panels
