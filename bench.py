@@ -68,9 +68,9 @@ DESCR = {
 # for the kernel source it was measured on: reported when factor.hip still has
 # this hash.
 TRAFFIC = {"config": "config2", "batch": 8,
-           "sha256": "c43e94fd9b57d78449a943e3cd3d0a40906bfb2dee04134e22ae6ed378093999",
-           "fetch_bytes": 239119551,     # 116760.8 KiB FETCH_SIZE x 1.99995
-           "write_bytes": 156256051}    # 152593.8 KiB WRITE_SIZE x 1.00000
+           "sha256": "9b3505216775754df6fa8bff99c13cf8e4cdee186eda9903e069526add1e5dc3",
+           "fetch_bytes": 241575506,     # 117960.3 KiB FETCH_SIZE x 1.99994
+           "write_bytes": 156255334}    # 152593.1 KiB WRITE_SIZE x 1.00000
 
 
 def factor_source_sha256():
