@@ -159,6 +159,51 @@ def gpu_batch_fn(device="cuda", precision: int = 0, buffers=None) -> BatchFn:
     return fn
 
 
+def angle_study(base: Problem, batch_fn: BatchFn, angles_deg: Sequence[float],
+                annulus_deg: Tuple[float, float] = (10.0, 20.0), designs: int = 8,
+                iters: int = 12, seed: int = 9100, log: Optional[Callable[[str], None]] = None) -> dict:
+    """The qualitative behaviour of optimized concentrators under incoherent light
+    (Sec. "Designs", Fig. 3 left): the optimized average intensity F against the
+    half-angle c of a cone (it falls with c, roughly as 1/c once c exceeds the
+    angular acceptance of the focus), and the gain of a design optimized for an
+    annulus [th1, th2] (and for the widest cone) over a lens-like design, the
+    best one for the smallest cone.  Every optimization starts from the same
+    seeded widths; F is the best of the designs."""
+    import math
+    import workloads as W
+
+    starts = [np.array(W.seeded_widths(len(base.widths), seed + k)) for k in range(designs)]
+
+    def optimize(p):
+        res, lock = maximize([p] * designs, batch_fn, iters=iters, starts=starts)
+        best = max(res, key=lambda r: r.F)
+        return best, res, lock
+
+    cones = []
+    lens = None
+    for a in angles_deg:
+        p = W.with_light(base, light=W.CONE, c=math.radians(a))
+        best, res, lock = optimize(p)
+        if lens is None:
+            lens = best.widths
+        cones.append({"c_deg": a, "F_start_mean": float(np.mean([r.F0 for r in res])),
+                      "F_opt": best.F, "F_opt_times_c": best.F * math.radians(a),
+                      "evaluations": lock.evaluations})
+        if log:
+            log(f"cone {a} deg: F {cones[-1]['F_start_mean']:.4g} -> {best.F:.4g}")
+    gains = []
+    lights = [("annulus", W.with_light(base, light=W.ANNULUS, th1=math.radians(annulus_deg[0]),
+                                       th2=math.radians(annulus_deg[1]))),
+              ("cone", W.with_light(base, light=W.CONE, c=math.radians(max(angles_deg))))]
+    for name, p in lights:
+        F_lens = float(batch_fn([(p, lens)])[0][0])
+        best, res, lock = optimize(p)
+        gains.append({"light": name, "F_lens": F_lens, "F_opt": best.F, "gain": best.F / F_lens})
+        if log:
+            log(f"{name}: lens {F_lens:.4g}, optimized {best.F:.4g}")
+    return {"cones": cones, "gains_over_lens": gains}
+
+
 def _main():
     import argparse
     import json
@@ -171,8 +216,21 @@ def _main():
                     choices=["config1", "config2", "config3", "config4_large"])
     ap.add_argument("--designs", type=int, default=8)
     ap.add_argument("--iters", type=int, default=10)
+    ap.add_argument("--study", action="store_true",
+                    help="optimized F against the cone half-angle, and annulus gains over a lens")
+    ap.add_argument("--angles", default="0.25,1,2.5,5,10,20", help="cone half-angles (deg) for --study")
     args = ap.parse_args()
     base = getattr(W, args.config)()
+    if args.study:
+        t0 = time.perf_counter()
+        import sys
+        out = angle_study(base, gpu_batch_fn(), [float(a) for a in args.angles.split(",")],
+                          designs=args.designs, iters=args.iters,
+                          log=lambda m: print(m, file=sys.stderr, flush=True))
+        out.update({"config": args.config, "designs": args.designs, "iters": args.iters,
+                    "seconds": round(time.perf_counter() - t0, 1)})
+        print(json.dumps(out))
+        return
     problems = [replace(base, widths=W.seeded_widths(len(base.widths), 9000 + k))
                 for k in range(args.designs)]
     torch.cuda.synchronize()

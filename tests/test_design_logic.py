@@ -50,3 +50,33 @@ def test_lockstep_reports_a_failing_batch_to_every_optimizer():
         assert "batched evaluation failed" in str(e)
     else:
         raise AssertionError("no error raised")
+
+
+def test_angle_study_bookkeeping():
+    """The study's lens is the best design for the smallest cone, and its gains
+    compare each light's optimum with that lens under the same light (synthetic
+    objective: F = (1 - |x - t|^2) / angle, t depending on the light)."""
+    import math
+    from paper_2207_10701_amd.design import angle_study
+    base = W.small_problem(3, 3, seed=1)
+
+    def fn(batch):
+        out = []
+        for p, x in batch:
+            ang = p.c if p.light == W.CONE else p.th2
+            t = 0.3 if p.light == W.CONE else 0.7
+            F = (1.0 - float(np.sum((x - t) ** 2))) / ang
+            out.append((F, -2.0 * (x - t) / ang))
+        return out
+
+    out = angle_study(base, fn, [1.0, 4.0], annulus_deg=(2.0, 4.0), designs=2, iters=30)
+    cones = out["cones"]
+    assert [c["c_deg"] for c in cones] == [1.0, 4.0]
+    assert cones[0]["F_opt"] > cones[1]["F_opt"]
+    for c in cones:   # optimum x = t: F c = 1
+        assert abs(c["F_opt_times_c"] - 1.0) < 1e-6
+    gains = {g["light"]: g for g in out["gains_over_lens"]}
+    # the lens (x = 0.3) under the annulus: 1 - 3 * 0.16 over th2
+    assert abs(gains["annulus"]["F_lens"] - (1 - 3 * 0.16) / math.radians(4.0)) < 1e-6
+    assert abs(gains["annulus"]["gain"] - 1.0 / (1 - 3 * 0.16)) < 1e-6
+    assert abs(gains["cone"]["gain"] - 1.0) < 1e-6
