@@ -204,6 +204,39 @@ def angle_study(base: Problem, batch_fn: BatchFn, angles_deg: Sequence[float],
     return {"cones": cones, "gains_over_lens": gains}
 
 
+def collimator_gains(base: Problem, batch_fn: BatchFn, cone_deg: float = 20.0,
+                     annulus_deg: Tuple[float, float] = (10.0, 20.0), designs: int = 8,
+                     iters: int = 12, seed: int = 9200,
+                     log: Optional[Callable[[str], None]] = None) -> List[dict]:
+    """Output-mode power of a collimator optimized for a cone and for an annulus,
+    against random metasurfaces (the seeded starts) under the same light
+    (Sec. "Designs", Fig. 2 left)."""
+    import math
+    import workloads as W
+
+    starts = [np.array(W.seeded_widths(len(base.widths), seed + k)) for k in range(designs)]
+    out = []
+    for name, p in (("cone", W.with_light(base, light=W.CONE, c=math.radians(cone_deg))),
+                    ("annulus", W.with_light(base, light=W.ANNULUS, th1=math.radians(annulus_deg[0]),
+                                             th2=math.radians(annulus_deg[1])))):
+        res, lock = maximize([p] * designs, batch_fn, iters=iters, starts=starts)
+        F_rand = float(np.mean([r.F0 for r in res]))
+        best = max(res, key=lambda r: r.F)
+        out.append({"light": name, "F_random_mean": F_rand, "F_opt": best.F, "gain": best.F / F_rand,
+                    "evaluations": lock.evaluations})
+        if log:
+            log(f"collimator {name}: random {F_rand:.4g}, optimized {best.F:.4g}")
+    return out
+
+
+def collimator_problem(seed: int = 1005) -> Problem:
+    """A collimator of the config 4-large size: 100 x 20 wavelengths, normal output
+    mode on a monitor row 10 wavelengths above the pillars."""
+    import workloads as W
+    return W.metasurface("collimator4", 100, 20, seed, objective=W.COLLIMATOR, monitor_y=11.5,
+                         c_deg=20.0)
+
+
 def _main():
     import argparse
     import json
@@ -219,7 +252,17 @@ def _main():
     ap.add_argument("--study", action="store_true",
                     help="optimized F against the cone half-angle, and annulus gains over a lens")
     ap.add_argument("--angles", default="0.25,1,2.5,5,10,20", help="cone half-angles (deg) for --study")
+    ap.add_argument("--collimator-study", action="store_true",
+                    help="collimator gains over random metasurfaces, cone and annulus")
     args = ap.parse_args()
+    if args.collimator_study:
+        import sys
+        t0 = time.perf_counter()
+        res = collimator_gains(collimator_problem(), gpu_batch_fn(), designs=args.designs,
+                               iters=args.iters, log=lambda m: print(m, file=sys.stderr, flush=True))
+        print(json.dumps({"collimator": res, "designs": args.designs, "iters": args.iters,
+                          "seconds": round(time.perf_counter() - t0, 1)}))
+        return
     base = getattr(W, args.config)()
     if args.study:
         t0 = time.perf_counter()

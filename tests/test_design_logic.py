@@ -80,3 +80,23 @@ def test_angle_study_bookkeeping():
     assert abs(gains["annulus"]["F_lens"] - (1 - 3 * 0.16) / math.radians(4.0)) < 1e-6
     assert abs(gains["annulus"]["gain"] - 1.0 / (1 - 3 * 0.16)) < 1e-6
     assert abs(gains["cone"]["gain"] - 1.0) < 1e-6
+
+
+def test_collimator_gains_bookkeeping():
+    """Gains are the best optimized F over the mean F of the random starts,
+    under each light (synthetic objective with its optimum F = 1)."""
+    from paper_2207_10701_amd.design import collimator_gains
+    base = W.small_problem(3, 3, seed=1, objective=W.COLLIMATOR)
+
+    def fn(batch):
+        out = []
+        for p, x in batch:
+            t = 0.4 if p.light == W.CONE else 0.6
+            out.append((1.0 - float(np.sum((x - t) ** 2)), -2.0 * (x - t)))
+        return out
+
+    res = collimator_gains(base, fn, designs=3, iters=30)
+    assert [r["light"] for r in res] == ["cone", "annulus"]
+    for r in res:
+        assert abs(r["F_opt"] - 1.0) < 1e-9
+        assert abs(r["gain"] - 1.0 / r["F_random_mean"]) < 1e-9
