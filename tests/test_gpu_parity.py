@@ -203,6 +203,26 @@ def test_factor_pairs_match_oracle_solves(rcp, name):
     assert rel(Xc.cpu().numpy().ravel(), ref) < 1e-10
 
 
+@pytest.mark.parametrize("height,npml,focus", [(2, 4, 0.3), (3, 8, 1.0)], ids=["2-tiles", "3-tiles"])
+def test_factor_batch_smallest_tile_counts(rcp, height, npml, focus):
+    """Blocks of two and three 32-row tiles: the block-opening pass is followed at
+    once by the last pass (two), or by a pass whose look-ahead forms the odd last
+    panel for the one-panel final update (three).  Against the oracle and the
+    one-panel-per-launch factorisation of each geometry."""
+    from dataclasses import replace
+    base = W.small_problem(3, height, seed=41, npml=npml, focus_height=focus)
+    assert (base.ny + 31) // 32 == height
+    probs = [replace(base, widths=W.seeded_widths(len(base.widths), 800 + g)) for g in range(3)]
+    eps = [rcp.eps_from_widths(p, device="cuda") for p in probs]
+    facs = rcp.factor_batch(probs, eps)
+    for p, e, f in zip(probs, eps, facs):
+        Fb = rcp.reciprocal_average(f, p).item()
+        Fs = rcp.reciprocal_average(rcp.Factors(p, e), p).item()
+        assert abs(Fs - Fb) <= 1e-12 * abs(Fs)
+        ref = ora.reciprocal(oracle_setup(p))
+        assert abs(Fb - ref) / ref < 1e-10
+
+
 @pytest.mark.parametrize("count", [3, 8])
 def test_adjoint_batch_matches_single(rcp, count):
     """Batched adjoint (solves of all sets in the same launches) is bit-identical
