@@ -14,13 +14,18 @@
 //   S_IJ <- S_IJ - Q_I L_J^T (I, J != K),  S_IK <- Q_I,  S_KK <- -P,
 // and after all panels the tiles hold -S^{-1}; the last panel negates.
 //
-// Look-ahead: launch k applies update k to every tile outside tile column
-// k+1, while a few workgroups compute the update-k values of column k+1
-// directly in the layout the next panel needs, invert the next pivot block
-// and form Q for panel k+1 into the other half of double-buffered panel
-// buffers.  Column k+1 values never go back to the factor tiles: update k+1
-// overwrites that column anyway.  One launch per panel, no dependencies
+// One geometry, one panel per launch with look-ahead: launch k applies update
+// k to every tile outside tile column k+1, while a few workgroups compute the
+// update-k values of column k+1 directly in the layout the next panel needs,
+// invert the next pivot block and form Q for panel k+1 into the other half of
+// double-buffered panel buffers.  Column k+1 values never go back to the
+// factor tiles: update k+1 overwrites that column anyway.  No dependencies
 // between the workgroups of a launch.
+//
+// Batches (2 to 8 geometries side by side): two panels per pass, each tile
+// read and written once per pair; one workgroup per chain does the next
+// pair's pivot work inside the pass and a short launch forms the next pair's
+// row tiles (the two-panel section below).
 //
 // The TB x TB pivot blocks are inverted without pivoting, in FP64 for both
 // storage precisions, and the smallest pivot modulus of every panel is
