@@ -68,8 +68,8 @@ DESCR = {
 # for the kernel source it was measured on: reported when factor.hip still has
 # this hash.
 TRAFFIC = {"config": "config2", "batch": 8,
-           "sha256": "9b3505216775754df6fa8bff99c13cf8e4cdee186eda9903e069526add1e5dc3",
-           "fetch_bytes": 241575506,     # 117960.3 KiB FETCH_SIZE x 1.99994
+           "sha256": "fb597ba1694361a2fca86ff8acc19129db1490493012b4722f212e089891ed6e",
+           "fetch_bytes": 240276593,     # 117325.8 KiB FETCH_SIZE x 1.99994
            "write_bytes": 156255334}    # 152593.1 KiB WRITE_SIZE x 1.00000
 
 
