@@ -297,8 +297,9 @@ int rcp_last_solve_stats(const rcp_factors* f, rcp_solve_stats* stats);
  * class with HIP events on the launching stream (k = 0 turns timing off);
  * rcp_timing_stop waits for those events and fills stats[c] for the classes
  *   0 Gauss-Jordan panels formed apart from a tile update (first panel of a
- *     block; for batches also the second, and the row tiles of each next
- *     pair of panels)                                 work = algorithmic flops
+ *     block; for batches the pass that opens a block with the pivot work of
+ *     panels 0 and 1, and the row tiles of each next pair of panels)
+ *                                                     work = algorithmic flops
  *   1 Gauss-Jordan tile update: for batches panels k, k+1 in one pass with
  *     the pivot work of panels k+2, k+3; for one geometry update k fused
  *     with panel k+1                                  work = algorithmic flops
