@@ -183,6 +183,7 @@ def serving(args):
                                  "p99_ms": round(s_pool["p99_ms"], 2),
                                  "evals_per_s": round(s_pool["evals_per_s"], 3),
                                  "cache_hits": sum(1 for r in pres if r.cache_hit),
+                                 "shared_sweep_requests": sum(1 for r in pres if r.group > 1),
                                  "failed": s_pool["failed"]},
             "failed": s_con["failed"]}
 

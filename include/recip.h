@@ -212,6 +212,21 @@ int rcp_adjoint_grad_batch(int32_t count, rcp_factors* const* factors,
                            const rcp_objective* objs, const rcp_light* lights, double* F_dev,
                            double* const* grad_eps_dev, rcp_stream stream);
 
+/* a11 -- several evaluations on one cached factor set (requests for the same
+ * geometry with their own objectives and lights, Eq. 7 each): F_k = v_k^dag
+ * T_k v_k with v_k = (A^{-dag} w_k) on the incidence line of lights[k] and
+ * T_k its Toeplitz correlation.  RCP_FP64 factors with count >= 2 solve all
+ * objectives in one multi-RHS sweep (every factor block read once for all of
+ * them); otherwise one (refined) solve per objective.  Each F_k equals
+ * rcp_reciprocal_average with objs[k] and lights[k] to rounding.  F_dev:
+ * count float64 (device).  work_dev: at least
+ * rcp_reciprocal_many_work_bytes(f, count) bytes, 256-byte aligned, scratch.
+ * count 1..64; RCP_ENOMEM when work_bytes is short. */
+size_t rcp_reciprocal_many_work_bytes(const rcp_factors* f, int32_t count);
+int rcp_reciprocal_average_many(const rcp_factors* f, int32_t count, const rcp_objective* objs,
+                                const rcp_light* lights, double* F_dev, void* work_dev,
+                                size_t work_bytes, rcp_stream stream);
+
 /* ---- any correlation W and many outputs --------------------------------
  * Sec. "Incoherent light": the reciprocal identity of Eq. 7 holds for
  * arbitrarily correlated light, where W is a dense Hermitian M x M matrix on

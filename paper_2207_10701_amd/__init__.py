@@ -223,6 +223,25 @@ def adjoint_grad_batch(facs, problems=None, stream=None):
     return F, grads
 
 
+def reciprocal_average_many(fac: Factors, problems, stream=None,
+                            work: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """F for several requests on the same factors (problems of this geometry with
+    their own objectives and lights): one multi-RHS reciprocal sweep for all of
+    them, then each one's Toeplitz form.  Returns F of shape (len(problems),)."""
+    K = len(problems)
+    if K < 1 or K > 64:
+        raise ValueError("reciprocal_average_many takes 1 to 64 problems")
+    dev = fac.buf.device
+    need = int(lib.rcp_reciprocal_many_work_bytes(fac.handle, K))
+    work = _work(need, dev, work)
+    F = torch.empty(K, dtype=torch.float64, device=dev)
+    objs = (_lib.Objective * K)(*[objective_struct(p) for p in problems])
+    lights = (_lib.Light * K)(*[light_struct(p) for p in problems])
+    check(lib.rcp_reciprocal_average_many(fac.handle, K, objs, lights, F.data_ptr(),
+                                          work.data_ptr(), need, _stream(stream)))
+    return F
+
+
 def broadband_grad(facs, weights, problems=None, stream=None):
     """Weighted sum over 1-8 factor sets (one geometry at the wavelengths of a
     spectral rule, e.g. from factor_batch): returns (F of shape (B + 1,) with the

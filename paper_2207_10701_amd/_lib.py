@@ -85,6 +85,8 @@ def _load():
         "rcp_adjoint_grad_batch": (C.c_int, [i32, P(vp), P(Objective), P(Light), vp, P(vp), vp]),
         "rcp_broadband_grad": (C.c_int, [i32, P(vp), P(Objective), P(Light), P(f64), vp, vp, vp]),
         "rcp_width_grad": (C.c_int, [P(Grid), P(Pillars), vp, vp, vp]),
+        "rcp_reciprocal_many_work_bytes": (sz, [vp, i32]),
+        "rcp_reciprocal_average_many": (C.c_int, [vp, i32, P(Objective), P(Light), vp, vp, sz, vp]),
         "rcp_dense_work_bytes": (sz, [vp, i32, i32]),
         "rcp_reciprocal_average_dense": (C.c_int, [vp, i32, P(Objective), P(Light), vp, vp, vp,
                                                    vp, sz, vp]),

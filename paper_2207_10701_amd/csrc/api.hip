@@ -489,6 +489,45 @@ int rcp_reciprocal_average(const rcp_factors* fc, const rcp_objective* obj, cons
   return toeplitz_form(f, light, z, F_dev, static_cast<double2*>(v_dev), nullptr, stream);
 }
 
+size_t rcp_reciprocal_many_work_bytes(const rcp_factors* f, int32_t count) {
+  if (!f || count < 1 || count > 64) return 0;
+  return align256(2 * size_t(count) * f->nx * f->ny * sizeof(double2));
+}
+
+int rcp_reciprocal_average_many(const rcp_factors* fc, int32_t count, const rcp_objective* objs,
+                                const rcp_light* lights, double* F_dev, void* work_dev,
+                                size_t work_bytes, rcp_stream stream) {
+  rcp_factors* f = const_cast<rcp_factors*>(fc);
+  if (!f) return fail(RCP_EINVAL, "factors is NULL");
+  if (count < 1 || count > 64) return fail(RCP_EINVAL, "count must be 1 to 64");
+  if (!objs || !lights || !F_dev || !work_dev) return fail(RCP_EINVAL, "NULL argument");
+  for (int k = 0; k < count; ++k) {
+    int rc = check_objective(f, &objs[k]);
+    if (!rc) rc = check_light(f, &lights[k], false);
+    if (rc) return rc;
+  }
+  const size_t need = rcp_reciprocal_many_work_bytes(f, count);
+  if (work_bytes < need) return fail(RCP_ENOMEM, "work buffer: need " + std::to_string(need) + " bytes");
+  const size_t N = size_t(f->nx) * f->ny;
+  double2* B = static_cast<double2*>(work_dev);
+  double2* Z = B + size_t(count) * N;
+  int lo, hi, rc = RCP_OK;
+  if (f->precision == RCP_FP64 && count >= 2) {   // all objectives in one multi-RHS sweep
+    for (int k = 0; k < count && !rc; ++k) rc = objective_rhs(f, &objs[k], B + k * N, &lo, &hi, stream);
+    if (!rc) rc = solve_multi_fp64(f, count, B, nullptr, 0, Z, 1, stream);
+  } else {
+    for (int k = 0; k < count && !rc; ++k) {
+      rc = objective_rhs(f, &objs[k], f->vec[V_RHS], &lo, &hi, stream);
+      if (!rc)
+        rc = solve_vec_refined(f, f->vec[V_RHS], Z + k * N, 1, lo, hi, kRefineTol, kRefineMax,
+                               stream, nullptr);
+    }
+  }
+  for (int k = 0; k < count && !rc; ++k)
+    rc = toeplitz_form(f, &lights[k], Z + k * N, F_dev + k, nullptr, nullptr, stream);
+  return rc;
+}
+
 int rcp_adjoint_grad(const rcp_factors* fc, const rcp_objective* obj, const rcp_light* light,
                      double* F_dev, double* grad_eps_dev, rcp_stream stream) {
   rcp_factors* f = const_cast<rcp_factors*>(fc);

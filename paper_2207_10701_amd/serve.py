@@ -6,8 +6,11 @@ flight, each on its own HIP stream driven by its own host thread, so their
 kernels overlap on the device.  A request is admitted when a slot is free and
 the device memory its factors need (``rcp_factor_bytes``) fits in the budget;
 factors of finished requests stay cached (keyed by geometry) until their
-memory is needed, so repeated geometries skip the factorisation.  Admission
-is first come, first served.  Latency is measured from arrival to result.
+memory is needed, so repeated geometries skip the factorisation.  When a
+request starts on cached factors, the requests for the same geometry that
+have already arrived (plain evaluations, up to ``group``) go with it: one
+multi-right-hand-side reciprocal sweep serves all of them.  Admission is
+first come, first served.  Latency is measured from arrival to result.
 
 The device work goes through an executor: ``GpuExecutor`` calls librecip;
 ``FakeExecutor`` models costs and memory on the host so the scheduling logic
@@ -41,6 +44,7 @@ class Result:
     done: float = 0.0
     cache_hit: bool = False
     slot: int = -1
+    group: int = 1               # requests served by the same evaluation call
 
     @property
     def latency(self) -> float:
@@ -92,6 +96,14 @@ class GpuExecutor:
             stream.synchronize()
         return F.item(), (gw.cpu().numpy() if gw is not None else None)
 
+    def evaluate_many(self, fac, problems, stream):
+        """Plain evaluations of several requests on one factor set."""
+        torch, rcp = self.torch, self.rcp
+        with torch.cuda.stream(stream):
+            F = rcp.reciprocal_average_many(fac, problems, stream=stream)
+            stream.synchronize()
+        return [float(v) for v in F.cpu().numpy()]
+
     def release(self, fac) -> None:
         fac.release()
         fac.buf = None
@@ -108,6 +120,7 @@ class FakeExecutor:
         self.bytes_per_cell = bytes_per_cell
         self.fail_on = fail_on
         self.factor_calls = 0
+        self.group_sizes: List[int] = []
         self.live = 0
         self.peak_live = 0
         self.lock = threading.Lock()
@@ -133,6 +146,12 @@ class FakeExecutor:
         F = float(sum(p.widths)) + p.c + p.th1 + p.th2
         return F, ([1.0] * len(p.widths) if adjoint else None)
 
+    def evaluate_many(self, fac, problems, stream):
+        time.sleep(self.eval_seconds)   # one sweep for all of them
+        with self.lock:
+            self.group_sizes.append(len(problems))
+        return [float(sum(p.widths)) + p.c + p.th1 + p.th2 for p in problems]
+
     def release(self, fac) -> None:
         with self.lock:
             self.live -= fac["bytes"]
@@ -156,9 +175,12 @@ class Server:
     """Continuous batching with memory-ledger admission and a factor cache."""
 
     def __init__(self, executor, slots: int = 4, hbm_budget: int = 200 << 30,
-                 cache: bool = True):
+                 cache: bool = True, group: int = 16):
         if slots < 1:
             raise ValueError("slots must be >= 1")
+        if not 1 <= group <= 64:
+            raise ValueError("group must be 1 to 64")
+        self.group = group
         self.ex = executor
         self.nslots = slots
         self.budget = int(hbm_budget)
@@ -246,6 +268,28 @@ class Server:
             self.results[req.rid] = res
             self.cv.notify_all()
 
+    def _run_group(self, reqs: List[Request], slot: int, entry: _Entry, t0: float,
+                   arrivals: List[float]):
+        """Plain evaluations of several requests on the same cached factors."""
+        start = time.perf_counter() - t0
+        err, Fs = None, [None] * len(reqs)
+        try:
+            Fs = self.ex.evaluate_many(entry.fac, [r.problem for r in reqs], self.streams[slot])
+        except Exception as e:
+            err = str(e)
+        done = time.perf_counter() - t0
+        with self.cv:
+            entry.users -= 1
+            entry.last_used = done
+            self.free_slots.append(slot)
+            self.free_slots.sort()
+            self.inflight -= 1
+            for r, a, F in zip(reqs, arrivals, Fs):
+                self.results[r.rid] = Result(rid=r.rid, F=F, error=err, arrival=a, start=start,
+                                             done=done, cache_hit=True, slot=slot,
+                                             group=len(reqs))
+            self.cv.notify_all()
+
     # -- driver -----------------------------------------------------------------------------
     def run(self, requests: List[Request], realtime: bool = True) -> List[Result]:
         """Serve a request stream.  realtime: replay the arrival times; otherwise
@@ -253,10 +297,14 @@ class Server:
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
         t0 = time.perf_counter()
         threads = []
+        taken = set()      # requests that went with an earlier one
         i = 0
         with self.cv:
             while i < len(pending):
                 req = pending[i]
+                if req.rid in taken:
+                    i += 1
+                    continue
                 now = time.perf_counter() - t0
                 if realtime and req.arrival > now:
                     self.cv.wait(timeout=req.arrival - now)
@@ -276,8 +324,23 @@ class Server:
                 self.inflight += 1
                 self.max_inflight = max(self.max_inflight, self.inflight)
                 self.peak_bytes = max(self.peak_bytes, self.used)
-                th = threading.Thread(target=self._run, args=(req, slot, entry, t0, arrival),
-                                      daemon=True)
+                group = [req]
+                if entry.ready and not req.adjoint and self.group > 1:
+                    key = geometry_key(req.problem)
+                    for other in pending[i + 1:]:
+                        if len(group) >= self.group or (realtime and other.arrival > now):
+                            break
+                        if (other.rid not in taken and not other.adjoint
+                                and geometry_key(other.problem) == key):
+                            group.append(other)
+                            taken.add(other.rid)
+                if len(group) > 1:
+                    arrivals = [r.arrival if realtime else 0.0 for r in group]
+                    th = threading.Thread(target=self._run_group,
+                                          args=(group, slot, entry, t0, arrivals), daemon=True)
+                else:
+                    th = threading.Thread(target=self._run, args=(req, slot, entry, t0, arrival),
+                                          daemon=True)
                 th.start()
                 threads.append(th)
                 i += 1

@@ -33,3 +33,51 @@ def test_mix_equals_alone_and_oracle(rcp):
     for q, r in list(zip(reqs, out))[:2]:
         ref = ora.reciprocal(ora.setup(q.problem))
         assert abs(r.F - ref) / ref < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_reciprocal_average_many_equals_single_calls(rcp, precision):
+    """Several objectives and lights on one factor set (concentrator/collimator,
+    cone/annulus): one multi-RHS sweep (FP64) or refined solves one by one
+    (FP32 factors) give each single call's F; the FP64 ones match the oracle."""
+    import torch
+    from dataclasses import replace
+    prec = rcp.RCP_FP64 if precision == "fp64" else rcp.RCP_FP32_REFINED
+    base = W.small_problem(5, 4, seed=8)
+    probs = [
+        base,
+        W.with_light(base, light=W.ANNULUS, th1=0.1, th2=0.4),
+        replace(base, objective=W.COLLIMATOR, monitor_row=base.ny - base.npml - 5, phi=0.1),
+        replace(W.with_light(base, light=W.CONE, c=0.05), focus=(base.focus[0] + 7, base.focus[1])),
+        replace(base, objective=W.COLLIMATOR, monitor_row=base.ny - base.npml - 9,
+                light=W.ANNULUS, th1=0.2, th2=0.5),
+    ]
+    fac = rcp.Factors(base, rcp.eps_from_widths(base, device="cuda"), prec)
+    F = rcp.reciprocal_average_many(fac, probs).cpu().numpy()
+    for k, q in enumerate(probs):
+        Fs = rcp.reciprocal_average(fac, q).item()
+        assert abs(F[k] - Fs) <= 1e-12 * abs(Fs), (k, F[k], Fs)
+        if prec == rcp.RCP_FP64 and k in (0, 2):
+            ref = ora.reciprocal(ora.setup(q))
+            assert abs(F[k] - ref) / ref < 1e-10
+    torch.cuda.synchronize()
+
+
+def test_pool_requests_grouped_on_cached_factors(rcp):
+    """A pool stream served with grouping: requests that share cached factors
+    run as one multi-RHS evaluation; every result equals the request alone."""
+    import torch
+    from paper_2207_10701_amd.serve import GpuExecutor, Server
+    reqs = W.serving_stream(12, rate=500.0, seed=5003, scale=0.04, geometry_pool=2,
+                            adjoint_frac=0.0)
+    ex = GpuExecutor()
+    srv = Server(ex, slots=1, hbm_budget=8 << 30, group=8)
+    out = srv.run(reqs, realtime=False)
+    srv.close()
+    assert all(r.error is None for r in out), [r.error for r in out]
+    assert sum(r.cache_hit for r in out) >= len(reqs) - 2
+    for q, r in zip(reqs, out):
+        fac = rcp.Factors(q.problem, rcp.eps_from_widths(q.problem, device="cuda"))
+        F = rcp.reciprocal_average(fac, q.problem).item()
+        torch.cuda.synchronize()
+        assert abs(F - r.F) <= 1e-10 * abs(F)

@@ -104,3 +104,37 @@ def test_realtime_replay_respects_arrivals():
     out = Server(FakeExecutor(), slots=2, hbm_budget=10 ** 12).run(reqs)
     for q, r in zip(reqs, out):
         assert r.start >= q.arrival - 1e-3
+
+
+def test_requests_on_cached_factors_share_one_sweep():
+    """Requests for a geometry whose factors are cached and ready go together
+    (plain evaluations, up to `group`); adjoint requests never do; results are
+    those of single evaluations; group=1 turns grouping off."""
+    reqs = stream(40, geometry_pool=2, adjoint_frac=0.25)
+    ex = FakeExecutor(factor_seconds=lambda p: 0.02)
+    out = Server(ex, slots=1, hbm_budget=10 ** 12, group=8).run(reqs, realtime=False)
+    assert all(r.error is None for r in out)
+    alone = FakeExecutor()
+    for q, r in zip(reqs, out):
+        F, _ = alone.evaluate(None, q.problem, q.adjoint, None)
+        assert r.F == F
+        if q.adjoint:
+            assert r.grad_widths is not None
+    assert ex.group_sizes and max(ex.group_sizes) > 1 and max(ex.group_sizes) <= 8
+    grouped = sum(ex.group_sizes)
+    plain = sum(1 for q in reqs if not q.adjoint)
+    assert grouped <= plain
+    assert ex.factor_calls == 2       # one per geometry of the pool
+    ex1 = FakeExecutor(factor_seconds=lambda p: 0.02)
+    out1 = Server(ex1, slots=1, hbm_budget=10 ** 12, group=1).run(reqs, realtime=False)
+    assert not ex1.group_sizes
+    assert [r.F for r in out1] == [r.F for r in out]
+
+
+def test_group_size_recorded():
+    reqs = stream(20, geometry_pool=1, adjoint_frac=0.0)
+    out = Server(FakeExecutor(factor_seconds=lambda p: 0.02), slots=1, hbm_budget=10 ** 12,
+                 group=6).run(reqs, realtime=False)
+    sizes = [r.group for r in out]
+    assert sizes[0] == 1 and max(sizes) == 6
+    assert all(r.cache_hit for r, g in zip(out, sizes) if g > 1)
