@@ -173,6 +173,19 @@ def serving(args):
     pres = pool.run(preqs, realtime=True)
     pool.close()
     s_pool = summarize(pres)
+    # a backlog: 64 plain requests over 4 geometries, all waiting at the start;
+    # requests on cached factors share one multi-RHS sweep (group 16) or not (1)
+    breqs = W.serving_stream(64, rate=200.0, seed=5004, scale=args.serve_scale, adjoint_frac=0.0,
+                             geometry_pool=4)
+    backlog = {}
+    for g in (16, 1):
+        srv = Server(ex, slots=4, hbm_budget=200 << 30, cache=True, group=g)
+        bres = srv.run(breqs, realtime=False)
+        srv.close()
+        sb = summarize(bres)
+        backlog[f"group_{g}"] = {"evals_per_s": round(sb["evals_per_s"], 3),
+                                 "p99_ms": round(sb["p99_ms"], 2), "failed": sb["failed"],
+                                 "shared_sweep_requests": sum(1 for r in bres if r.group > 1)}
     return {"requests": len(reqs), "rate_per_s": 200.0, "scale": args.serve_scale,
             "slots": 4, "p50_ms": round(s_con["p50_ms"], 2), "p99_ms": round(s_con["p99_ms"], 2),
             "evals_per_s": round(s_con["evals_per_s"], 3), "max_inflight": conc.max_inflight,
@@ -185,6 +198,7 @@ def serving(args):
                                  "cache_hits": sum(1 for r in pres if r.cache_hit),
                                  "shared_sweep_requests": sum(1 for r in pres if r.group > 1),
                                  "failed": s_pool["failed"]},
+            "backlog_64_on_4_geometries": backlog,
             "failed": s_con["failed"]}
 
 
