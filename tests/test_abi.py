@@ -154,3 +154,14 @@ def test_broadband_argument_checks():
     bad = (C.c_double * 1)(float("inf"))
     rc = lib.rcp_broadband_grad(1, handles, o, lt, bad, C.c_void_p(0x1000), C.c_void_p(0x1000), None)
     assert rc == _lib.RCP_EINVAL and b"finite" in lib.rcp_last_error()
+
+
+def test_reciprocal_many_argument_checks():
+    from paper_2207_10701_amd import _lib
+    lib = _lib.lib
+    o = (_lib.Objective * 1)()
+    lt = (_lib.Light * 1)()
+    assert lib.rcp_reciprocal_many_work_bytes(None, 1) == 0
+    rc = lib.rcp_reciprocal_average_many(None, 1, o, lt, C.c_void_p(0x1000), C.c_void_p(0x1000),
+                                         1 << 20, None)
+    assert rc == _lib.RCP_EINVAL and b"NULL" in lib.rcp_last_error()
