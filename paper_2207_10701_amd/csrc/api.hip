@@ -54,6 +54,7 @@ Layout compute_layout(int nx, int ny, int precision) {
   size_t cap = 2;
   while (cap < 2 * size_t(nx)) cap <<= 1;
   L.off_fft = take(4 * cap * 16);
+  L.off_part = take(2 * 2 * tiles * TB * 16);
   L.total = o;
   return L;
 }
@@ -393,6 +394,8 @@ int rcp_factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, vo
     f->red = reinterpret_cast<double*>(b + L.off_red);
     for (int q = 0; q < 4; ++q)
       f->fft[q] = reinterpret_cast<double2*>(b + L.off_fft) + q * f->fft_cap;
+    for (int c = 0; c < 2; ++c)
+      f->part[c] = reinterpret_cast<double2*>(b + L.off_part) + c * 2 * f->tiles * TB;
     f->last_iters = 0;
     f->last_residual = 0.0;
     rc = launch_assemble(f, grid->eps_dev, stream);

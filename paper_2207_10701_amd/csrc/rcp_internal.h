@@ -29,6 +29,7 @@ struct Layout {
   size_t off_dco, off_eco, off_cco;
   size_t off_L, off_Q, off_P;     // GJ panel workspace, 4 slots for each of 2 chains
   size_t off_health, off_vec, off_red, off_fft;
+  size_t off_part;                // per-tile partial sums of the vector sweep, 2 chains
   size_t total;
 };
 
@@ -58,6 +59,7 @@ struct rcp_factors {
   double2* vec[rcp::NVEC];
   double* red;
   double2* fft[4];            // symbol spectrum, work, temp, W v
+  double2* part[2];           // vector-sweep partial sums of chain c: tiles x (row, column) x TB
   // statistics of the last refined solve
   int last_iters;
   double last_residual;

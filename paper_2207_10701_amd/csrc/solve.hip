@@ -9,8 +9,10 @@
 //   back left      u_i = g_i - X_i (C_i u_{i+1}),       i = m-1 .. 0
 //   back right     u_i = g_i - X_i (C_{i-1} u_{i-1}),   i = m+1 .. nx-1
 // conj(A)^{-1} (= A^{-dag}, since A = A^T) uses conj(X_i) and conj(C_i).
-// One right-hand side: a matrix-vector product per block, bound by reading
-// the packed lower tiles once.  Many right-hand sides: an MFMA GEMM per block.
+// One right-hand side: a symmetric matrix-vector product per block that reads
+// each packed lower tile once (row and column shares of every tile, then a
+// fixed-order sum per row), bound by HBM.  Many right-hand sides: an MFMA GEMM
+// per block.
 #include <cmath>
 #include <vector>
 
@@ -18,8 +20,6 @@
 
 namespace {
 using namespace rcp;
-
-constexpr int NPMAX = 2048;   // largest padded block size supported
 
 struct SvJob {
   const void* X;
@@ -30,6 +30,7 @@ struct SvJob {
   const double2* c1;
   const double2* v2;
   const double2* c2;
+  double2* part;         // partial sums of this chain (tiles x 2 x TB)
 };
 // Job table of a launch: the left and right chain step of each factor set; two
 // entries for one set, 2 MAX_BATCH for batches (the table is a kernel argument,
@@ -44,28 +45,8 @@ __device__ __forceinline__ double2 maybe_conj(double2 a, int c) {
   return c ? make_double2(a.x, -a.y) : a;
 }
 
-// One 512-thread workgroup per (job, 8-row quarter of a 32-row strip), so a
-// block is spread over 4 * nt workgroups.  Wave w takes the tiles J = w + 8u
-// of the strip.  Every load instruction of a wave reads whole cache lines:
-//   stored tile (I, J <= I): its rows r0 .. r0+7 are 4 KB contiguous; lane l
-//     of load c holds row 2c + l/32, column l%32, and keeps a partial sum per
-//     c (reduced over the 32 lanes of equal l/32 at the end);
-//   tile (J > I, I), used transposed: columns r0 .. r0+7 of each of its 32
-//     rows (128 B each); lane l of load c holds row 8c + l/8, column r0 + l%8,
-//     and keeps one partial sum for output row l%8 (reduced over l/8).
-// All tile loads are issued before the input vector is formed in LDS, so one
-// memory latency covers the step.  Partial sums are combined in a fixed
-// order: the result does not depend on scheduling.
-// MT = tiles per wave = ceil(nt / 8) (nt <= 64, np <= 2048).
-template <typename T, int MT, int NJ>
-__global__ __launch_bounds__(512) void k_gemv(SvJobs<NJ> jobs, int nt, int ny, int conjop) {
-  using T2 = typename cplx<T>::t;
-  __shared__ double2 g[NPMAX];
-  __shared__ double2 redd[8][8];
-  __shared__ double2 redt[8][8];
-  const int per_job = 4 * nt;
-  const int ji = blockIdx.x / per_job, rem = blockIdx.x % per_job;
-  const int I = rem >> 2, r0 = (rem & 3) * 8;
+template <int NJ>
+__device__ __forceinline__ SvJob job_of(const SvJobs<NJ>& jobs, int ji) {
   SvJob jb;
   if constexpr (NJ == 2) {
     jb = jobs.j[0];
@@ -80,90 +61,112 @@ __global__ __launch_bounds__(512) void k_gemv(SvJobs<NJ> jobs, int nt, int ny, i
     jb.c1 = RCP_SEL16(jobs, ji, c1);
     jb.v2 = RCP_SEL16(jobs, ji, v2);
     jb.c2 = RCP_SEL16(jobs, ji, c2);
+    jb.part = RCP_SEL16(jobs, ji, part);
   }
-  const int tid = threadIdx.x;
-  const T2* X = static_cast<const T2*>(jb.X);
-  const int wave = tid >> 6, lane = tid & 63;
-  T2 x[MT][4];
+  return jb;
+}
+
+// y = op(X) g for a symmetric block X stored as its packed lower tiles, every
+// stored tile read once.  One wave per stored tile (I, J), J <= I, packed
+// index t; it writes two 32-vectors of partial sums:
+//   part[t][0] = op(X_IJ) g_J     (a share of the rows of strip I)
+//   part[t][1] = op(X_IJ)^T g_I   (a share of the rows of strip J; J < I only)
+// and k_symv_reduce adds the shares of each row in a fixed order.
+// g = f - op(C1) v1 - op(C2) v2 (each term optional), zero in the padding.
+// In registers, load c (0..15) of lane l holds row 2c + l/32, column l%32 of
+// the tile, so each load instruction reads 1 KB (complex128) contiguous.  The
+// column shares are summed in-lane over the 16 loads, then across the two
+// half-waves; the row shares across the 32 lanes of a half-wave by recursive
+// halving (each exchange halves the values a lane holds).
+template <typename T, int NJ>
+__global__ __launch_bounds__(256) void k_symv_tiles(SvJobs<NJ> jobs, int ny, int tiles,
+                                                    int conjop) {
+  using T2 = typename cplx<T>::t;
+  __shared__ double2 gs[4][64];
+  const int per_job = (tiles + 3) >> 2;
+  const int ji = blockIdx.x / per_job;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = (blockIdx.x - ji * per_job) * 4 + wave;
+  const SvJob jb = job_of(jobs, ji);
+  const int tt = t < tiles ? t : tiles - 1;
+  int I = static_cast<int>((sqrtf(8.0f * tt + 1.0f) - 1.0f) * 0.5f);
+  if ((I + 1) * (I + 2) / 2 <= tt) ++I;
+  if (I * (I + 1) / 2 > tt) --I;
+  const int J = tt - I * (I + 1) / 2;
+  const T2* X = static_cast<const T2*>(jb.X) + size_t(tt) * TB * TB + lane;
+  T2 x[16];
 #pragma unroll
-  for (int u = 0; u < MT; ++u) {
-    const int J = wave + 8 * u;
-    if (J < nt) {
-      if (J <= I) {
-        const T2* t = X + tile_index(I, J) * TB * TB + r0 * TB + lane;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) x[u][c] = t[c * 64];
-      } else {
-        const T2* t = X + tile_index(J, I) * TB * TB + (lane >> 3) * TB + r0 + (lane & 7);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) x[u][c] = t[c * 8 * TB];
-      }
-    }
-  }
-  const int np = nt * TB;
-  for (int k = tid; k < np; k += 512) {
+  for (int c = 0; c < 16; ++c) x[c] = X[c * 64];
+  {
+    const int k = (lane < 32 ? J : I) * TB + (lane & 31);
     double2 v = make_double2(0.0, 0.0);
     if (k < ny) {
       if (jb.f) v = jb.f[k];
       if (jb.v1) v = csub(v, cmul(maybe_conj(jb.c1[k], conjop), jb.v1[k]));
       if (jb.v2) v = csub(v, cmul(maybe_conj(jb.c2[k], conjop), jb.v2[k]));
     }
-    g[k] = v;
+    gs[wave][lane] = v;
   }
   __syncthreads();
+  if (t >= tiles) return;
   const double cs_im = conjop ? -1.0 : 1.0;
-  double2 accd[4], acct = make_double2(0.0, 0.0);
+  const int h = lane >> 5;
+  const double2 gj = gs[wave][lane & 31];
+  double2 rp[16];
+  double2 cp = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int c = 0; c < 4; ++c) accd[c] = make_double2(0.0, 0.0);
+  for (int c = 0; c < 16; ++c) {
+    double2 xv = to_c128(x[c]);
+    xv.y *= cs_im;
+    rp[c] = cmul(xv, gj);
+    cp = cadd(cp, cmul(xv, gs[wave][32 + 2 * c + h]));
+  }
+  // 16 row values -> 8 (lane bit 4) -> 4 (bit 3) -> 2 (bit 2) -> 1 (bit 1);
+  // lane l then holds row 2 ((l >> 1) & 15) + h summed over bits 4..1
 #pragma unroll
-  for (int u = 0; u < MT; ++u) {
-    const int J = wave + 8 * u;
-    if (J < nt) {
-      if (J <= I) {
-        const double2 gv = g[J * TB + (lane & 31)];
+  for (int w = 8, b = 16; w >= 1; w >>= 1, b >>= 1) {
+    const bool up = (lane & b) != 0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          double2 xv = to_c128(x[u][c]);
-          xv.y *= cs_im;
-          accd[c] = cadd(accd[c], cmul(xv, gv));
-        }
-      } else {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          double2 xv = to_c128(x[u][c]);
-          xv.y *= cs_im;
-          acct = cadd(acct, cmul(xv, g[J * TB + 8 * c + (lane >> 3)]));
-        }
-      }
+    for (int i = 0; i < w; ++i) {
+      const double2 send = up ? rp[i] : rp[i + w];
+      const double2 keep = up ? rp[i + w] : rp[i];
+      rp[i] = make_double2(keep.x + __shfl_xor(send.x, b, 64), keep.y + __shfl_xor(send.y, b, 64));
     }
   }
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-#pragma unroll
-    for (int d = 1; d < 32; d <<= 1) {
-      accd[c].x += __shfl_xor(accd[c].x, d, 64);
-      accd[c].y += __shfl_xor(accd[c].y, d, 64);
-    }
+  rp[0].x += __shfl_xor(rp[0].x, 1, 64);
+  rp[0].y += __shfl_xor(rp[0].y, 1, 64);
+  cp.x += __shfl_xor(cp.x, 32, 64);
+  cp.y += __shfl_xor(cp.y, 32, 64);
+  double2* P = jb.part + size_t(t) * 2 * TB;
+  if ((lane & 1) == 0) P[2 * ((lane >> 1) & 15) + h] = rp[0];
+  if (J < I && lane < 32) P[TB + lane] = cp;
+}
+
+// out[k] = base[k] + the shares of row k of strip I = k / TB: part[(I, J)][0]
+// for J <= I, part[(J, I)][1] for J > I.  One workgroup per (job, strip):
+// thread (q, r) sums the shares of row r with J = q mod 8 in ascending J, then
+// the eight sums of each row are added in q order.
+template <int NJ>
+__global__ __launch_bounds__(256) void k_symv_reduce(SvJobs<NJ> jobs, int nt, int ny) {
+  __shared__ double2 red[8][TB];
+  const int ji = blockIdx.x / nt;
+  const int I = blockIdx.x - ji * nt;
+  const int q = threadIdx.x >> 5, r = threadIdx.x & 31;
+  const SvJob jb = job_of(jobs, ji);
+  const double2* P = jb.part;
+  double2 sum = make_double2(0.0, 0.0);
+  for (int J = q; J < nt; J += 8) {
+    const size_t at = J <= I ? tile_index(I, J) * 2 * TB + r : tile_index(J, I) * 2 * TB + TB + r;
+    sum = cadd(sum, P[at]);
   }
-#pragma unroll
-  for (int d = 8; d < 64; d <<= 1) {
-    acct.x += __shfl_xor(acct.x, d, 64);
-    acct.y += __shfl_xor(acct.y, d, 64);
-  }
-  if ((lane & 31) == 0) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) redd[wave][2 * c + (lane >> 5)] = accd[c];
-  }
-  if (lane < 8) redt[wave][lane] = acct;
+  red[q][r] = sum;
   __syncthreads();
-  if (tid < 8) {
-    double2 sum = make_double2(0.0, 0.0);
-    for (int w = 0; w < 8; ++w) sum = cadd(sum, cadd(redd[w][tid], redt[w][tid]));
-    const int row = I * TB + r0 + tid;
-    if (row < ny) {
-      double2 b = jb.base ? jb.base[row] : make_double2(0.0, 0.0);
-      jb.out[row] = cadd(b, sum);
-    }
+  const int k = I * TB + threadIdx.x;
+  if (threadIdx.x < TB && k < ny) {
+    double2 s = red[0][threadIdx.x];
+#pragma unroll
+    for (int u = 1; u < 8; ++u) s = cadd(s, red[u][threadIdx.x]);
+    jb.out[k] = jb.base ? cadd(jb.base[k], s) : s;
   }
 }
 
@@ -494,7 +497,6 @@ int run_solve_vec(rcp_factors* const* fs, int B, const double2* const* rhs, doub
   using SvJobs = ::SvJobs<NJ>;
   const rcp_factors* f0 = fs[0];
   const int N = f0->nx, ny = f0->ny, nt = f0->nt, m = f0->m;
-  if (f0->np > NPMAX) return fail(RCP_EINVAL, "block size too large for the vector sweep");
   const int lenL = m, lenR = N - 1 - m;
   auto U = [&](int g, int i) { return u[g] + size_t(i) * ny; };
   auto Fb = [&](int g, int i) { return rhs[g] + size_t(i) * ny; };
@@ -502,20 +504,16 @@ int run_solve_vec(rcp_factors* const* fs, int B, const double2* const* rhs, doub
   auto launch = [&](SvJobs& js) -> int {
     if (js.n == 0) return RCP_OK;
     KTimer kt(K_GEMV, s, double(js.n) * f0->tiles * TB * TB * sizeof(typename cplx<T>::t));
-    const dim3 grid(4 * nt * js.n);
-    switch ((nt + 7) / 8) {
-      case 1: k_gemv<T, 1, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
-      case 2: k_gemv<T, 2, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
-      case 3: k_gemv<T, 3, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
-      case 4: k_gemv<T, 4, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
-      case 5: k_gemv<T, 5, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
-      case 6: k_gemv<T, 6, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
-      case 7: k_gemv<T, 7, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
-      default: k_gemv<T, 8, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
-    }
+    const int tiles = static_cast<int>(f0->tiles);
+    k_symv_tiles<T, NJ><<<((tiles + 3) / 4) * js.n, 256, 0, s>>>(js, ny, tiles, conjop);
+    RCP_HIP(hipGetLastError());
+    k_symv_reduce<NJ><<<nt * js.n, 256, 0, s>>>(js, nt, ny);
     RCP_HIP(hipGetLastError());
     return RCP_OK;
   };
+  // the left chain's steps (and the middle block) use set g's partial-sum
+  // area 0, the right chain's area 1
+  auto P = [&](int g, int c) { return fs[g]->part[c]; };
   // forward sweeps; g_i is known zero while no source block has been passed
   std::vector<std::vector<char>> zero(B, std::vector<char>(N, 0));
   const int steps = lenL > lenR ? lenL : lenR;
@@ -531,7 +529,7 @@ int run_solve_vec(rcp_factors* const* fs, int B, const double2* const* rhs, doub
         } else {
           js.j[js.n++] = SvJob{block_ptr(fs[g], i), U(g, i), nullptr, Fb(g, i),
                                prevz ? nullptr : U(g, i - 1), i > 0 ? C(g, i - 1) : nullptr,
-                               nullptr, nullptr};
+                               nullptr, nullptr, P(g, 0)};
         }
       }
       if (st < lenR) {
@@ -542,7 +540,7 @@ int run_solve_vec(rcp_factors* const* fs, int B, const double2* const* rhs, doub
         } else {
           js.j[js.n++] = SvJob{block_ptr(fs[g], i), U(g, i), nullptr, Fb(g, i),
                                prevz ? nullptr : U(g, i + 1), i < N - 1 ? C(g, i) : nullptr,
-                               nullptr, nullptr};
+                               nullptr, nullptr, P(g, 1)};
         }
       }
     }
@@ -552,7 +550,8 @@ int run_solve_vec(rcp_factors* const* fs, int B, const double2* const* rhs, doub
   {
     SvJobs js{};
     for (int g = 0; g < B; ++g) {
-      SvJob z{block_ptr(fs[g], m), U(g, m), nullptr, Fb(g, m), nullptr, nullptr, nullptr, nullptr};
+      SvJob z{block_ptr(fs[g], m), U(g, m), nullptr, Fb(g, m), nullptr, nullptr, nullptr, nullptr,
+              P(g, 0)};
       if (m - 1 >= 0 && !zero[g][m - 1]) {
         z.v1 = U(g, m - 1);
         z.c1 = C(g, m - 1);
@@ -572,12 +571,12 @@ int run_solve_vec(rcp_factors* const* fs, int B, const double2* const* rhs, doub
       if (st < lenL) {
         int i = m - 1 - st;
         js.j[js.n++] = SvJob{block_ptr(fs[g], i), U(g, i), zero[g][i] ? nullptr : U(g, i), nullptr,
-                             U(g, i + 1), C(g, i), nullptr, nullptr};
+                             U(g, i + 1), C(g, i), nullptr, nullptr, P(g, 0)};
       }
       if (st < lenR) {
         int i = m + 1 + st;
         js.j[js.n++] = SvJob{block_ptr(fs[g], i), U(g, i), zero[g][i] ? nullptr : U(g, i), nullptr,
-                             U(g, i - 1), C(g, i - 1), nullptr, nullptr};
+                             U(g, i - 1), C(g, i - 1), nullptr, nullptr, P(g, 1)};
       }
     }
     int rc = launch(js);
