@@ -68,9 +68,9 @@ DESCR = {
 # for the kernel source it was measured on: reported when factor.hip still has
 # this hash.
 TRAFFIC = {"config": "config2", "batch": 8,
-           "sha256": "fb597ba1694361a2fca86ff8acc19129db1490493012b4722f212e089891ed6e",
-           "fetch_bytes": 240276593,     # 117325.8 KiB FETCH_SIZE x 1.99994
-           "write_bytes": 156255334}    # 152593.1 KiB WRITE_SIZE x 1.00000
+           "sha256": "12ad555b37cc1c3c5337dbea853ab32d9f1ae824dc97255ad33961d3ffbb737d",
+           "fetch_bytes": 212418588,     # 103723.1 KiB FETCH_SIZE x 1.99994
+           "write_bytes": 156259942}    # 152597.6 KiB WRITE_SIZE x 1.00000
 
 
 def factor_source_sha256():

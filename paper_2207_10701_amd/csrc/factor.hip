@@ -695,9 +695,11 @@ __device__ __forceinline__ void tile_nn_update(typename v4of<T>::t (*cre)[2],
 }
 
 // dst = sg (S - A0 B0^T - A1 B1^T) with k-major panel tiles A0, B0, A1, B1:
-// the accumulators start from S (no separate copy of the tile in registers),
-// then eight chunks of two k-steps, the next chunk in flight while the
-// current one multiplies.
+// eight chunks of two k-steps into zeroed accumulators, the next chunk in
+// flight while the current one multiplies; S is added at the end.  Vector
+// loads retire in issue order, so the tile S (from HBM) is requested after
+// the first two chunks (from L2): the first products wait only for L2, and
+// S arrives while they run.
 template <typename T>
 __device__ __forceinline__ void tile_update2_pipelined(typename cplx<T>::t* dst,
                                                        const typename cplx<T>::t* A0,
@@ -711,16 +713,20 @@ __device__ __forceinline__ void tile_update2_pipelined(typename cplx<T>::t* dst,
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const T2 v = dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr];
-        cre[a][b][q] = v.x;
-        cim[a][b][q] = v.y;
-      }
+    for (int b = 0; b < 2; ++b) {
+      cre[a][b] = V4{0, 0, 0, 0};
+      cim[a][b] = V4{0, 0, 0, 0};
+    }
   T2 a0[2][2], b0[2][2], a1[2][2], b1[2][2];
   load_ksteps_t(a0, b0, A0, B0, 0, lr, lk);
   load_ksteps_t(a1, b1, A0, B0, 1, lr, lk);
+  T2 sv[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sv[a][b][q] = dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr];
   mma_ksteps<T>(cre, cim, a0, b0);
   load_ksteps_t(a0, b0, A0, B0, 2, lr, lk);
   mma_ksteps<T>(cre, cim, a1, b1);
@@ -742,8 +748,8 @@ __device__ __forceinline__ void tile_update2_pipelined(typename cplx<T>::t* dst,
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         T2 v;
-        v.x = cre[a][b][q] * sg;
-        v.y = cim[a][b][q] * sg;
+        v.x = (sv[a][b][q].x + cre[a][b][q]) * sg;
+        v.y = (sv[a][b][q].y + cim[a][b][q]) * sg;
         dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr] = v;
       }
 }

@@ -9,10 +9,12 @@
 //   back left      u_i = g_i - X_i (C_i u_{i+1}),       i = m-1 .. 0
 //   back right     u_i = g_i - X_i (C_{i-1} u_{i-1}),   i = m+1 .. nx-1
 // conj(A)^{-1} (= A^{-dag}, since A = A^T) uses conj(X_i) and conj(C_i).
-// One right-hand side: a symmetric matrix-vector product per block that reads
-// each packed lower tile once (row and column shares of every tile, then a
-// fixed-order sum per row), bound by HBM.  Many right-hand sides: an MFMA GEMM
-// per block.
+// One right-hand side: a symmetric matrix-vector product per block.  Blocks
+// of more than GEMV_NT_MAX tiles per edge read each packed lower tile once (row
+// and column shares of every tile, then a fixed-order sum per row; bound by
+// HBM); smaller blocks use one launch per step, which reads the tiles above
+// the diagonal again as transposes (bound by latency).  Many right-hand sides:
+// an MFMA GEMM per block.
 #include <cmath>
 #include <vector>
 
@@ -20,6 +22,12 @@
 
 namespace {
 using namespace rcp;
+
+// Blocks of at most GEMV_NT_MAX tiles per edge use the one-launch product
+// k_gemv (it reads the tiles above the diagonal a second time, as transposes,
+// but saves the second launch, which dominates for small blocks).
+constexpr int GEMV_NT_MAX = 20;
+constexpr int GEMV_NPMAX = GEMV_NT_MAX * TB;
 
 struct SvJob {
   const void* X;
@@ -64,6 +72,116 @@ __device__ __forceinline__ SvJob job_of(const SvJobs<NJ>& jobs, int ji) {
     jb.part = RCP_SEL16(jobs, ji, part);
   }
   return jb;
+}
+
+// One 512-thread workgroup per (job, 8-row quarter of a 32-row strip), so a
+// block is spread over 4 * nt workgroups.  Wave w takes the tiles J = w + 8u
+// of the strip.  Every load instruction of a wave reads whole cache lines:
+//   stored tile (I, J <= I): its rows r0 .. r0+7 are 4 KB contiguous; lane l
+//     of load c holds row 2c + l/32, column l%32, and keeps a partial sum per
+//     c (reduced over the 32 lanes of equal l/32 at the end);
+//   tile (J > I, I), used transposed: columns r0 .. r0+7 of each of its 32
+//     rows (128 B each); lane l of load c holds row 8c + l/8, column r0 + l%8,
+//     and keeps one partial sum for output row l%8 (reduced over l/8).
+// All tile loads are issued before the input vector is formed in LDS, so one
+// memory latency covers the step.  Partial sums are combined in a fixed
+// order: the result does not depend on scheduling.
+// MT = tiles per wave = ceil(nt / 8).  Used for small blocks (nt <= GEMV_NT_MAX),
+// where one launch per step beats the two of the tile-once product below.
+template <typename T, int MT, int NJ>
+__global__ __launch_bounds__(512) void k_gemv(SvJobs<NJ> jobs, int nt, int ny, int conjop) {
+  using T2 = typename cplx<T>::t;
+  __shared__ double2 g[GEMV_NPMAX];
+  __shared__ double2 redd[8][8];
+  __shared__ double2 redt[8][8];
+  const int per_job = 4 * nt;
+  const int ji = blockIdx.x / per_job, rem = blockIdx.x % per_job;
+  const int I = rem >> 2, r0 = (rem & 3) * 8;
+  const SvJob jb = job_of(jobs, ji);
+  const int tid = threadIdx.x;
+  const T2* X = static_cast<const T2*>(jb.X);
+  const int wave = tid >> 6, lane = tid & 63;
+  T2 x[MT][4];
+#pragma unroll
+  for (int u = 0; u < MT; ++u) {
+    const int J = wave + 8 * u;
+    if (J < nt) {
+      if (J <= I) {
+        const T2* t = X + tile_index(I, J) * TB * TB + r0 * TB + lane;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x[u][c] = t[c * 64];
+      } else {
+        const T2* t = X + tile_index(J, I) * TB * TB + (lane >> 3) * TB + r0 + (lane & 7);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x[u][c] = t[c * 8 * TB];
+      }
+    }
+  }
+  const int np = nt * TB;
+  for (int k = tid; k < np; k += 512) {
+    double2 v = make_double2(0.0, 0.0);
+    if (k < ny) {
+      if (jb.f) v = jb.f[k];
+      if (jb.v1) v = csub(v, cmul(maybe_conj(jb.c1[k], conjop), jb.v1[k]));
+      if (jb.v2) v = csub(v, cmul(maybe_conj(jb.c2[k], conjop), jb.v2[k]));
+    }
+    g[k] = v;
+  }
+  __syncthreads();
+  const double cs_im = conjop ? -1.0 : 1.0;
+  double2 accd[4], acct = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) accd[c] = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int u = 0; u < MT; ++u) {
+    const int J = wave + 8 * u;
+    if (J < nt) {
+      if (J <= I) {
+        const double2 gv = g[J * TB + (lane & 31)];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          double2 xv = to_c128(x[u][c]);
+          xv.y *= cs_im;
+          accd[c] = cadd(accd[c], cmul(xv, gv));
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          double2 xv = to_c128(x[u][c]);
+          xv.y *= cs_im;
+          acct = cadd(acct, cmul(xv, g[J * TB + 8 * c + (lane >> 3)]));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+      accd[c].x += __shfl_xor(accd[c].x, d, 64);
+      accd[c].y += __shfl_xor(accd[c].y, d, 64);
+    }
+  }
+#pragma unroll
+  for (int d = 8; d < 64; d <<= 1) {
+    acct.x += __shfl_xor(acct.x, d, 64);
+    acct.y += __shfl_xor(acct.y, d, 64);
+  }
+  if ((lane & 31) == 0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) redd[wave][2 * c + (lane >> 5)] = accd[c];
+  }
+  if (lane < 8) redt[wave][lane] = acct;
+  __syncthreads();
+  if (tid < 8) {
+    double2 sum = make_double2(0.0, 0.0);
+    for (int w = 0; w < 8; ++w) sum = cadd(sum, cadd(redd[w][tid], redt[w][tid]));
+    const int row = I * TB + r0 + tid;
+    if (row < ny) {
+      double2 b = jb.base ? jb.base[row] : make_double2(0.0, 0.0);
+      jb.out[row] = cadd(b, sum);
+    }
+  }
 }
 
 // y = op(X) g for a symmetric block X stored as its packed lower tiles, every
@@ -504,6 +622,16 @@ int run_solve_vec(rcp_factors* const* fs, int B, const double2* const* rhs, doub
   auto launch = [&](SvJobs& js) -> int {
     if (js.n == 0) return RCP_OK;
     KTimer kt(K_GEMV, s, double(js.n) * f0->tiles * TB * TB * sizeof(typename cplx<T>::t));
+    if (nt <= GEMV_NT_MAX) {
+      const dim3 grid(4 * nt * js.n);
+      switch ((nt + 7) / 8) {
+        case 1: k_gemv<T, 1, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+        case 2: k_gemv<T, 2, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+        default: k_gemv<T, 3, NJ><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+      }
+      RCP_HIP(hipGetLastError());
+      return RCP_OK;
+    }
     const int tiles = static_cast<int>(f0->tiles);
     k_symv_tiles<T, NJ><<<((tiles + 3) / 4) * js.n, 256, 0, s>>>(js, ny, tiles, conjop);
     RCP_HIP(hipGetLastError());

@@ -44,6 +44,10 @@ PROBLEMS = {
     # 276 rows: nine 32-row tiles with a ragged last one, so each wave of the
     # vector sweep takes two tiles
     "conc_tall": W.small_problem(2, 13, seed=10, npml=8, focus_height=9.0),
+    # 696 rows: 22 tiles per edge (a ragged last one), above the size where the
+    # vector sweep switches from the one-launch product to the tile-once
+    # product with its per-tile shares and row sums
+    "conc_tile_once": W.small_problem(2, 34, seed=12, npml=8, focus_height=25.0),
 }
 
 
@@ -241,6 +245,25 @@ def test_adjoint_batch_matches_single(rcp, count):
     ref = ora.adjoint(oracle_setup(probs[-1]))
     assert abs(Fb[-1].item() - ref.F) / abs(ref.F) < 1e-10
     assert rel(gb[-1].cpu().numpy(), ref.grad_eps) < 1e-9
+
+
+def test_adjoint_batch_tile_once_product(rcp):
+    """Batched solves on blocks of 22 tiles (the tile-once product, sixteen jobs
+    per launch at eight sets) equal one adjoint per set bit for bit and match
+    the oracle."""
+    from dataclasses import replace
+    base = PROBLEMS["conc_tile_once"]
+    probs = [replace(base, widths=W.seeded_widths(len(base.widths), 700 + g)) for g in range(8)]
+    eps = [rcp.eps_from_widths(p, device="cuda") for p in probs]
+    facs = rcp.factor_batch(probs, eps)
+    Fb, gb = rcp.adjoint_grad_batch(facs, probs)
+    for g in (0, 7):
+        F1, g1 = rcp.adjoint_grad(facs[g], probs[g])
+        assert Fb[g].item() == F1.item()
+        assert torch_equal(gb[g], g1)
+        ref = ora.adjoint(oracle_setup(probs[g]))
+        assert abs(Fb[g].item() - ref.F) / abs(ref.F) < 1e-10
+        assert rel(gb[g].cpu().numpy(), ref.grad_eps) < 1e-9
 
 
 def test_adjoint_batch_refined_fp32_falls_back_per_set(rcp):
