@@ -68,9 +68,9 @@ DESCR = {
 # for the kernel source it was measured on: reported when factor.hip still has
 # this hash.
 TRAFFIC = {"config": "config2", "batch": 8,
-           "sha256": "12ad555b37cc1c3c5337dbea853ab32d9f1ae824dc97255ad33961d3ffbb737d",
-           "fetch_bytes": 212418588,     # 103723.1 KiB FETCH_SIZE x 1.99994
-           "write_bytes": 156259942}    # 152597.6 KiB WRITE_SIZE x 1.00000
+           "sha256": "5f225f6026e7da83ef542137fd659a7f21ca9ec798c94d61f8b38b724bfffc01",
+           "fetch_bytes": 213551139,     # 104276.1 KiB FETCH_SIZE x 1.99994
+           "write_bytes": 156257485}    # 152595.2 KiB WRITE_SIZE x 1.00000
 
 
 def factor_source_sha256():

@@ -25,7 +25,8 @@
 // Batches (2 to 8 geometries side by side): two panels per pass, each tile
 // read and written once per pair; one workgroup per chain does the next
 // pair's pivot work inside the pass and a short launch forms the next pair's
-// row tiles (the two-panel section below).
+// row tiles (the two-panel section below).  The pivot work that opens a block
+// rides in the launch that forms the block's Schur complement.
 //
 // The TB x TB pivot blocks are inverted without pivoting, in FP64 for both
 // storage precisions, and the smallest pivot modulus of every panel is
@@ -1291,37 +1292,96 @@ struct SchurJobs {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_schur(SchurJobs jobs, int ny, size_t tiles) {
+__device__ __forceinline__ SchurJob schur_job_of(const SchurJobs& jobs, int ji) {
+  SchurJob jb;
+  jb.dst = RCP_SEL16(jobs, ji, dst);
+  jb.src1 = RCP_SEL16(jobs, ji, src1);
+  jb.src2 = RCP_SEL16(jobs, ji, src2);
+  jb.dco = RCP_SEL16(jobs, ji, dco);
+  jb.eco = RCP_SEL16(jobs, ji, eco);
+  jb.c1 = RCP_SEL16(jobs, ji, c1);
+  jb.c2 = RCP_SEL16(jobs, ji, c2);
+  return jb;
+}
+
+// Packed tiles t0 .. t0 + NTL - 1 (those below tiles) of dst, by the 256
+// threads of a workgroup: each thread forms its elements in registers before
+// it stores any, so that all of its loads are in flight together (a store
+// might alias a later load otherwise).
+template <typename T, int NTL>
+__device__ __forceinline__ void schur_tiles(const SchurJob& jb, int ny, size_t t0, size_t tiles) {
   using T2 = typename cplx<T>::t;
+  constexpr int EPT = TB * TB / 256;
+  double2 v[NTL][EPT];
+#pragma unroll
+  for (int k = 0; k < NTL; ++k) {
+    const size_t t = t0 + k;
+    if (t >= tiles) break;
+    int I, J;
+    tile_coords(static_cast<int>(t), &I, &J);
+    const T2* s1 = jb.src1 ? static_cast<const T2*>(jb.src1) + t * TB * TB : nullptr;
+    const T2* s2 = jb.src2 ? static_cast<const T2*>(jb.src2) + t * TB * TB : nullptr;
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int a = I * TB + e / TB, b = J * TB + e % TB;
+      double2 x = make_double2(0.0, 0.0);
+      if (a == b) {
+        x = (a < ny) ? jb.dco[a] : make_double2(1.0, 0.0);
+      } else if (a == b + 1 && a < ny) {
+        x = jb.eco[b];
+      } else if (b == a + 1 && b < ny) {
+        x = jb.eco[a];
+      }
+      if (a < ny && b < ny) {
+        if (s1) x = csub(x, cmul(cmul(jb.c1[a], jb.c1[b]), to_c128(s1[e])));
+        if (s2) x = csub(x, cmul(cmul(jb.c2[a], jb.c2[b]), to_c128(s2[e])));
+      }
+      v[k][u] = x;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NTL; ++k) {
+    const size_t t = t0 + k;
+    if (t >= tiles) break;
+    T2* dst = static_cast<T2*>(jb.dst) + t * TB * TB;
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) dst[threadIdx.x + 256 * u] = from_c128<T2>(v[k][u]);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_schur(SchurJobs jobs, int ny, size_t tiles) {
   const size_t t = blockIdx.x % tiles;
   const int ji = static_cast<int>(blockIdx.x / tiles);
-  void* const jdst = RCP_SEL16(jobs, ji, dst);
-  const void* const jsrc1 = RCP_SEL16(jobs, ji, src1);
-  const void* const jsrc2 = RCP_SEL16(jobs, ji, src2);
-  const double2* const dco = RCP_SEL16(jobs, ji, dco);
-  const double2* const eco = RCP_SEL16(jobs, ji, eco);
-  const double2* const c1 = RCP_SEL16(jobs, ji, c1);
-  const double2* const c2 = RCP_SEL16(jobs, ji, c2);
-  int I, J;
-  tile_coords(static_cast<int>(t), &I, &J);
-  T2* dst = static_cast<T2*>(jdst) + t * TB * TB;
-  const T2* s1 = jsrc1 ? static_cast<const T2*>(jsrc1) + t * TB * TB : nullptr;
-  const T2* s2 = jsrc2 ? static_cast<const T2*>(jsrc2) + t * TB * TB : nullptr;
-  for (int e = threadIdx.x; e < TB * TB; e += 256) {
-    int a = I * TB + e / TB, b = J * TB + e % TB;
-    double2 v = make_double2(0.0, 0.0);
-    if (a == b) {
-      v = (a < ny) ? dco[a] : make_double2(1.0, 0.0);
-    } else if (a == b + 1 && a < ny) {
-      v = eco[b];
-    } else if (b == a + 1 && b < ny) {
-      v = eco[a];
-    }
-    if (a < ny && b < ny) {
-      if (s1) v = csub(v, cmul(cmul(c1[a], c1[b]), to_c128(s1[e])));
-      if (s2) v = csub(v, cmul(cmul(c2[a], c2[b]), to_c128(s2[e])));
-    }
-    dst[e] = from_c128<T2>(v);
+  schur_tiles<T, 1>(schur_job_of<T>(jobs, ji), ny, t, tiles);
+}
+
+// The Schur complements that start the next blocks of a two-panel sweep, and
+// the pivot work of their panels 0 and 1 beside them (the pass K = -2): per
+// chain, workgroup 0 forms the three tiles of that pivot area, (0, 0), (1, 0)
+// and (1, 1), and inverts the pivots, while the other workgroups form the
+// remaining tiles, OPEN_TILES each.  The pivot inversions, latency-bound, run while
+// the rest of the block streams through HBM.  sj.j[q] and gj.j[q] describe
+// the same block; gj.j[q].wgs = 1 + ceil((tiles - 3) / OPEN_TILES).
+constexpr int OPEN_TILES = 2;
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_gj2_open(GJ2Jobs gj, SchurJobs sj, int ny, int nt,
+                                                     size_t tiles) {
+  __shared__ double2 B1[TB][TB + 1];
+  __shared__ double2 B2[TB][TB + 1];
+  __shared__ double2 B3[TB][TB + 1];
+  int q, w;
+  if (!job_of(gj.n, gj.j[0].wgs, &q, &w)) return;
+  const SchurJob sjob = schur_job_of<T>(sj, q);
+  if (w == 0) {
+    schur_tiles<T, 3>(sjob, ny, 0, 3);
+    __syncthreads();   // the tiles are read back by every wave of this workgroup
+    int tmp = q * gj.j[0].wgs;
+    const GJ2Job jb = pick2(gj, &tmp);
+    pivot2_work<T>(jb, nt, B1, B2, B3);
+  } else {
+    schur_tiles<T, OPEN_TILES>(sjob, ny, 3 + size_t(w - 1) * OPEN_TILES, tiles);
   }
 }
 
@@ -1337,13 +1397,46 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
   auto E = [&](int g, int i) { return fs[g]->eco + size_t(i) * ny; };
   auto C = [&](int g, int i) { return fs[g]->cco + size_t(i) * ny; };
 
-  auto schur = [&](SchurJobs js) -> int {
+  struct Chain {
+    int g, c, block;
+  };
+  // chains whose block-opening pivot work (pass K = -2) already ran beside
+  // their Schur complements
+  Chain opened[MAXJ];
+  int nopened = 0;
+  // Schur complements js.j[q] = the next block of chain ch[q]; with two-panel
+  // sweeps the opening pivot work of those blocks rides in the same launch
+  auto schur = [&](SchurJobs js, const Chain* ch) -> int {
+    nopened = 0;
     if (js.n == 0) return RCP_OK;
     int nsrc = 0;
     for (int q = 0; q < js.n; ++q) nsrc += 1 + (js.j[q].src1 != nullptr) + (js.j[q].src2 != nullptr);
     KTimer kt(K_SCHUR, s, double(nsrc) * tiles * TB * TB * f0->elem_bytes);
-    k_schur<T><<<static_cast<int>(tiles * js.n), 256, 0, s>>>(js, ny, tiles);
+    if (!pairs || nt < 2) {
+      k_schur<T><<<static_cast<int>(tiles * js.n), 256, 0, s>>>(js, ny, tiles);
+      RCP_HIP(hipGetLastError());
+      return RCP_OK;
+    }
+    GJ2Jobs gj{};
+    const int per = 1 + ceil_div(static_cast<int>(tiles) - 3, OPEN_TILES);
+    for (int q = 0; q < js.n; ++q) {
+      const rcp_factors* f = fs[ch[q].g];
+      if (block_ptr(f, ch[q].block) != js.j[q].dst) return fail(RCP_EINVAL, "internal: opener job order");
+      GJ2Job b{};
+      b.k = -2;
+      b.nlook = 2;
+      b.wgs = per;
+      b.X = js.j[q].dst;
+      b.Lb = f->wsL[4 * ch[q].c];
+      b.Qb = f->wsQ[4 * ch[q].c];
+      b.Pb = f->wsP[4 * ch[q].c];
+      b.health = f->health + size_t(ch[q].block) * nt;
+      gj.j[gj.n++] = b;
+      opened[q] = ch[q];
+    }
+    k_gj2_open<T><<<grid_size(gj.n, per), 256, 0, s>>>(gj, js, ny, nt, tiles);
     RCP_HIP(hipGetLastError());
+    nopened = js.n;
     return RCP_OK;
   };
   const int upd_wgs = static_cast<int>((tiles + 3) / 4);
@@ -1351,10 +1444,11 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
   const double cmac = 8.0 * TB * TB * TB;   // flops of one TB^3 complex product
   // Sweep the given blocks (chain c of geometry g) through all panels; the
   // panel buffers of chain c alternate between halves 2c and 2c+1.
-  struct Chain {
-    int g, c, block;
-  };
   auto sweep = [&](int nch, const Chain* ch) -> int {
+    bool open_done = nopened == nch;
+    for (int q = 0; q < nch && open_done; ++q)
+      open_done = opened[q].g == ch[q].g && opened[q].c == ch[q].c && opened[q].block == ch[q].block;
+    nopened = 0;
     // single-panel job k: panel k in slot k mod 4, panel k+1 in the next slot
     auto job = [&](const Chain& x, int k) {
       const rcp_factors* f = fs[x.g];
@@ -1446,7 +1540,7 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
         b.health = f->health + size_t(ch[q].block) * nt;
         js.j[js.n++] = b;
       }
-      {
+      if (K >= 0 || !open_done) {
         KTimer kt(K < 0 ? K_GJ_PANEL : (last ? K_GJ_LAST : K_GJ_UPDATE), s,
                   K < 0 ? nch * 6.0 * cmac : nch * 2.0 * cmac * double(tiles));
         k_gj2_fused<T><<<grid_size(nch, upd + look_wgs), 256, 0, s>>>(js, nt, tiles);
@@ -1481,14 +1575,19 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
 
   {   // chain heads
     SchurJobs js{};
+    Chain nxt[MAXJ];
     for (int g = 0; g < B; ++g) {
-      if (lenL > 0)
+      if (lenL > 0) {
+        nxt[js.n] = Chain{g, 0, 0};
         js.j[js.n++] = SchurJob{block_ptr(fs[g], 0), nullptr, nullptr, D(g, 0), E(g, 0), nullptr, nullptr};
-      if (lenR > 0)
+      }
+      if (lenR > 0) {
+        nxt[js.n] = Chain{g, 1, N - 1};
         js.j[js.n++] = SchurJob{block_ptr(fs[g], N - 1), nullptr, nullptr, D(g, N - 1), E(g, N - 1),
                                 nullptr, nullptr};
+      }
     }
-    int rc = schur(js);
+    int rc = schur(js, nxt);
     if (rc) return rc;
   }
   const int steps = lenL > lenR ? lenL : lenR;
@@ -1503,15 +1602,20 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
     int rc = sweep(nch, ch);
     if (rc) return rc;
     SchurJobs js{};
+    Chain nxt[MAXJ];
     for (int g = 0; g < B; ++g) {
-      if (bL >= 0 && bL + 1 < m)
+      if (bL >= 0 && bL + 1 < m) {
+        nxt[js.n] = Chain{g, 0, bL + 1};
         js.j[js.n++] = SchurJob{block_ptr(fs[g], bL + 1), block_ptr(fs[g], bL), nullptr,
                                 D(g, bL + 1), E(g, bL + 1), C(g, bL), nullptr};
-      if (bR >= 0 && bR - 1 > m)
+      }
+      if (bR >= 0 && bR - 1 > m) {
+        nxt[js.n] = Chain{g, 1, bR - 1};
         js.j[js.n++] = SchurJob{block_ptr(fs[g], bR - 1), block_ptr(fs[g], bR), nullptr,
                                 D(g, bR - 1), E(g, bR - 1), C(g, bR - 1), nullptr};
+      }
     }
-    rc = schur(js);
+    rc = schur(js, nxt);
     if (rc) return rc;
   }
   {   // middle blocks
@@ -1531,7 +1635,7 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
       js.j[js.n++] = z;
       ch[nch++] = Chain{g, 0, m};
     }
-    int rc = schur(js);
+    int rc = schur(js, ch);
     if (rc) return rc;
     rc = sweep(nch, ch);
     if (rc) return rc;
