@@ -908,6 +908,34 @@ __device__ __forceinline__ void store_lt(const typename v4of<T>::t (*cre)[2],
     }
 }
 
+// Quadrant (qa, qb) of Q = L P from L^T accumulator blocks and the P fragment
+// pf[s] = P[acc_k(s)][16 qb + lr] (loaded beforehand).
+template <typename T>
+__device__ __forceinline__ void q_quad_f(const typename v4of<T>::t (*cre)[2],
+                                         const typename v4of<T>::t (*cim)[2], const double2 (&pf)[8],
+                                         typename cplx<T>::t* Qt, int lr, int lk, int qa, int qb) {
+  using T2 = typename cplx<T>::t;
+  using V4 = typename v4of<T>::t;
+  V4 qre = V4{0, 0, 0, 0}, qim = V4{0, 0, 0, 0};
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const T bre = static_cast<T>(pf[s].x), bim = static_cast<T>(pf[s].y);
+    const T are = cre[s >> 2][0][s & 3], aim = cim[s >> 2][0][s & 3];
+    qre = mfma16(are, bre, qre);
+    qim = mfma16(are, bim, qim);
+    qre = mfma16(-aim, bim, qre);
+    qim = mfma16(aim, bre, qim);
+  }
+  T2* Qb = Qt + (16 * qb) * TB + 16 * qa;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    T2 v;
+    v.x = qre[q];
+    v.y = qim[q];
+    Qb[lr * TB + mfma_row<T>(lk, q)] = v;
+  }
+}
+
 // Pivot work of the next pair, once per chain (the last workgroup-sized job of
 // a pass): P3 = S''_{K3,K3}^{-1}; with K4: E = L3_K4 = S''_{K4,K3} and
 // Q3_K4 = E P3 (their rows of the K3 panel buffers), P4 = (S''_{K4,K4} -
@@ -997,6 +1025,25 @@ __device__ void pivot2_work(const GJ2Job& jb, int nt, double2 (*B1)[TB + 1],
   double2* P4 = jb.Pb + size_t(K4 & 3) * TT;
   for (int e = tid; e < TB * TB; e += 256) P4[e] = B2[e / TB][e % TB];
   if (tid == 0) jb.health[K4] = min4;
+  // Row tile K3 of panel K4, from what is at hand: L4_K3 = (Q3_K4)^T (B3)
+  // and Q4_K3 = L4_K3 P4 (B2), so that the row launch takes only the rows
+  // outside the pivot pair
+  {
+    V4 cre[2][2], cim[2][2];
+    double2 pf[8];
+#pragma unroll
+    for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double2 v = B3[16 * a2 + mfma_row<T>(lk, q)][16 * qa + lr];
+        cre[a2][0][q] = static_cast<T>(v.x);
+        cim[a2][0][q] = static_cast<T>(v.y);
+      }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) pf[s] = B2[acc_k<T>(s, lk)][16 * qb + lr];
+    if (qb == 0) store_lt<T>(cre, cim, slot_ptr<T2>(jb.Lb, K4, nt) + K3 * TT, lr, lk, qa);
+    q_quad_f<T>(cre, cim, pf, slot_ptr<T2>(jb.Qb, K4, nt) + K3 * TT, lr, lk, qa, qb);
+  }
 }
 
 // Rows 16 qa .. 16 qa + 15 of tile (I, C) of the full symmetric matrix as the
@@ -1030,39 +1077,12 @@ __device__ __forceinline__ void load_lt_lds(const typename cplx<T>::t (*lds)[TB 
     }
 }
 
-// Quadrant (qa, qb) of Q = L P from L^T accumulator blocks and the P fragment
-// pf[s] = P[acc_k(s)][16 qb + lr] (loaded beforehand).
-template <typename T>
-__device__ __forceinline__ void q_quad_f(const typename v4of<T>::t (*cre)[2],
-                                         const typename v4of<T>::t (*cim)[2], const double2 (&pf)[8],
-                                         typename cplx<T>::t* Qt, int lr, int lk, int qa, int qb) {
-  using T2 = typename cplx<T>::t;
-  using V4 = typename v4of<T>::t;
-  V4 qre = V4{0, 0, 0, 0}, qim = V4{0, 0, 0, 0};
-#pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const T bre = static_cast<T>(pf[s].x), bim = static_cast<T>(pf[s].y);
-    const T are = cre[s >> 2][0][s & 3], aim = cim[s >> 2][0][s & 3];
-    qre = mfma16(are, bre, qre);
-    qim = mfma16(are, bim, qim);
-    qre = mfma16(-aim, bim, qre);
-    qim = mfma16(aim, bre, qim);
-  }
-  T2* Qb = Qt + (16 * qb) * TB + 16 * qa;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    T2 v;
-    v.x = qre[q];
-    v.y = qim[q];
-    Qb[lr * TB + mfma_row<T>(lk, q)] = v;
-  }
-}
-
-// Row tile I of the next pair's panels after the pass (whose tiles of columns
-// K3, K4 now hold S'') and its pivot work: L3_I = S''_{I,K3}, Q3_I = L3_I P3;
-// with K4: L4_I = S''_{I,K4} - L3_I (Q3_K4)^T (L4_K3 = (Q3_K4)^T), Q4_I = L4_I P4.
-// Row K4 of panel K3 and the pivots come from the pivot work.  Every operand
-// is loaded before the first store, so one memory latency covers the row.
+// Row tile I (outside the pivot pair K3, K4) of the next pair's panels after
+// the pass, whose tiles of columns K3, K4 now hold S'': L3_I = S''_{I,K3},
+// Q3_I = L3_I P3; with K4: L4_I = S''_{I,K4} - L3_I (Q3_K4)^T, Q4_I = L4_I P4.
+// Rows K3 and K4 of the panels and the pivots come from the pivot work.  The
+// operands of the first two products are loaded before the first store, so
+// one memory latency covers them.
 template <typename T>
 __device__ void rows2_work(const GJ2Job& jb, int I, int nt, typename cplx<T>::t (*lt)[TB][TB + 1],
                            typename cplx<T>::t (*xch)[4][64]) {
@@ -1077,77 +1097,62 @@ __device__ void rows2_work(const GJ2Job& jb, int I, int nt, typename cplx<T>::t 
   const double2* P3 = jb.Pb + size_t(K3 & 3) * TT;
   const double2* P4 = jb.Pb + size_t(K4 & 3) * TT;
   const T2* Qk = slot_ptr<T2>(jb.Qb, K3, nt) + K4 * TT;
-  if (I == K3 && !two) return;
-  if (two && I == K4) return;
   V4 c3re[2][2], c3im[2][2], c4re[2][2], c4im[2][2];
   double2 p3[8], p4[8];
   T2 qk[8];   // row block qb of Q3_K4, the part of the L4 update this wave does
-  if (I == K3) {   // L4_K3^T = Q3_K4
+  // S''_{I,K3} (and S''_{I,K4}) through LDS: half of them are stored
+  // transposed, and a direct read in the accumulator layout would take
+  // sixteen rows per quarter-wave
+  stage_tile<T>(jb, I, K3, lt[0]);
+  if (two) stage_tile<T>(jb, I, K4, lt[1]);
 #pragma unroll
-    for (int a2 = 0; a2 < 2; ++a2)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const T2 v = Qk[(16 * qa + lr) * TB + 16 * a2 + mfma_row<T>(lk, q)];
-        c4re[a2][0][q] = v.x;
-        c4im[a2][0][q] = v.y;
-      }
-  } else {
-    // S''_{I,K3} (and S''_{I,K4}) through LDS: half of them are stored
-    // transposed, and a direct read in the accumulator layout would take
-    // sixteen rows per quarter-wave
-    stage_tile<T>(jb, I, K3, lt[0]);
-    if (two) stage_tile<T>(jb, I, K4, lt[1]);
-#pragma unroll
-    for (int s = 0; s < 8; ++s) p3[s] = P3[acc_k<T>(s, lk) * TB + 16 * qb + lr];
-    if (two) {
-#pragma unroll
-      for (int s = 0; s < 8; ++s) qk[s] = Qk[acc_k<T>(s, lk) * TB + 16 * qb + lr];
-    }
-    __syncthreads();
-    load_lt_lds<T>(lt[0], I > K3, c3re, c3im, lr, lk, qa);
-    if (two) load_lt_lds<T>(lt[1], I > K4, c4re, c4im, lr, lk, qa);
-  }
+  for (int s = 0; s < 8; ++s) p3[s] = P3[acc_k<T>(s, lk) * TB + 16 * qb + lr];
   if (two) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) p4[s] = P4[acc_k<T>(s, lk) * TB + 16 * qb + lr];
+    for (int s = 0; s < 8; ++s) qk[s] = Qk[acc_k<T>(s, lk) * TB + 16 * qb + lr];
   }
-  if (I != K3) {
-    if (qb == 0) store_lt<T>(c3re, c3im, slot_ptr<T2>(jb.Lb, K3, nt) + I * TT, lr, lk, qa);
-    q_quad_f<T>(c3re, c3im, p3, slot_ptr<T2>(jb.Qb, K3, nt) + I * TT, lr, lk, qa, qb);
-    if (!two) return;
-    // L4_I^T -= Q3_K4 L3_I^T, right operand from the L3 blocks: block (qb, qa)
-    // here, block (1 - qb, qa) in the wave of the same qa, exchanged in LDS
-    V4 hre = qb ? c4re[1][0] : c4re[0][0];
-    V4 him = qb ? c4im[1][0] : c4im[0][0];
+  __syncthreads();
+  load_lt_lds<T>(lt[0], I > K3, c3re, c3im, lr, lk, qa);
+  if (two) load_lt_lds<T>(lt[1], I > K4, c4re, c4im, lr, lk, qa);
+  if (qb == 0) store_lt<T>(c3re, c3im, slot_ptr<T2>(jb.Lb, K3, nt) + I * TT, lr, lk, qa);
+  q_quad_f<T>(c3re, c3im, p3, slot_ptr<T2>(jb.Qb, K3, nt) + I * TT, lr, lk, qa, qb);
+  if (!two) return;
+  // P4 is needed only by the last product: loaded here, it arrives during the
+  // L4 update and exchange, and its registers are free during Q3
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const T bre = c3re[s >> 2][0][s & 3], bim = c3im[s >> 2][0][s & 3];
-      const T nare = -qk[s].x, aim = qk[s].y, naim = -qk[s].y;
-      hre = mfma16(nare, bre, hre);
-      him = mfma16(nare, bim, him);
-      hre = mfma16(aim, bim, hre);
-      him = mfma16(naim, bre, him);
-    }
+  for (int s = 0; s < 8; ++s) p4[s] = P4[acc_k<T>(s, lk) * TB + 16 * qb + lr];
+  // L4_I^T -= Q3_K4 L3_I^T, right operand from the L3 blocks: block (qb, qa)
+  // here, block (1 - qb, qa) in the wave of the same qa, exchanged in LDS
+  V4 hre = qb ? c4re[1][0] : c4re[0][0];
+  V4 him = qb ? c4im[1][0] : c4im[0][0];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      T2 v;
-      v.x = hre[q];
-      v.y = him[q];
-      xch[wave][q][lane] = v;
-    }
-    __syncthreads();
-    V4 ore, oim;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const T2 v = xch[wave ^ 1][q][lane];
-      ore[q] = v.x;
-      oim[q] = v.y;
-    }
-    c4re[0][0] = qb ? ore : hre;
-    c4im[0][0] = qb ? oim : him;
-    c4re[1][0] = qb ? hre : ore;
-    c4im[1][0] = qb ? him : oim;
+  for (int s = 0; s < 8; ++s) {
+    const T bre = c3re[s >> 2][0][s & 3], bim = c3im[s >> 2][0][s & 3];
+    const T nare = -qk[s].x, aim = qk[s].y, naim = -qk[s].y;
+    hre = mfma16(nare, bre, hre);
+    him = mfma16(nare, bim, him);
+    hre = mfma16(aim, bim, hre);
+    him = mfma16(naim, bre, him);
   }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    T2 v;
+    v.x = hre[q];
+    v.y = him[q];
+    xch[wave][q][lane] = v;
+  }
+  __syncthreads();
+  V4 ore, oim;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const T2 v = xch[wave ^ 1][q][lane];
+    ore[q] = v.x;
+    oim[q] = v.y;
+  }
+  c4re[0][0] = qb ? ore : hre;
+  c4im[0][0] = qb ? oim : him;
+  c4re[1][0] = qb ? hre : ore;
+  c4im[1][0] = qb ? him : oim;
   if (qb == 0) store_lt<T>(c4re, c4im, slot_ptr<T2>(jb.Lb, K4, nt) + I * TT, lr, lk, qa);
   q_quad_f<T>(c4re, c4im, p4, slot_ptr<T2>(jb.Qb, K4, nt) + I * TT, lr, lk, qa, qb);
 }
@@ -1234,7 +1239,8 @@ __global__ __launch_bounds__(256, 2) void k_gj2_fused(GJ2Jobs jobs, int nt, size
     update2_work<T>(jb, w - look, nt, tiles);
 }
 
-// The row tiles of panels k+2 (and k+3), one per workgroup.
+// The row tiles of panels k+2 (and k+3) outside the pivot rows, one per
+// workgroup.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj2_rows(GJ2Jobs jobs, int nt) {
   __shared__ typename cplx<T>::t lt[2][TB][TB + 1];
@@ -1243,7 +1249,8 @@ __global__ __launch_bounds__(256) void k_gj2_rows(GJ2Jobs jobs, int nt) {
   if (!job_of(jobs.n, jobs.j[0].wgs, &q, &w)) return;
   int tmp = q * jobs.j[0].wgs + w;
   GJ2Job jb = pick2(jobs, &tmp);
-  rows2_work<T>(jb, w, nt, lt, xch);
+  const int K3 = jb.k + 2;   // rows K3 (and K4) come from the pivot work
+  rows2_work<T>(jb, w < K3 ? w : w + jb.nlook, nt, lt, xch);
 }
 
 // Panel tiles p0 .. p0 + np - 1 (slot p mod 4) of each job's L and Q buffers
@@ -1546,10 +1553,13 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
         k_gj2_fused<T><<<grid_size(nch, upd + look_wgs), 256, 0, s>>>(js, nt, tiles);
         RCP_HIP(hipGetLastError());
       }
-      if (nlook > 0) {   // row tiles of the next pair's panels
-        for (int q = 0; q < js.n; ++q) js.j[q].wgs = nt;
-        KTimer kt(K_GJ_PANEL, s, nch * cmac * nlook * nt);
-        k_gj2_rows<T><<<grid_size(nch, nt), 256, 0, s>>>(js, nt);
+      // row tiles of the next pair's panels; the pivot rows come from the
+      // pivot work, and with two tiles per edge nothing else is left
+      const int rows = nt - nlook;
+      if (nlook > 0 && rows > 0) {
+        for (int q = 0; q < js.n; ++q) js.j[q].wgs = rows;
+        KTimer kt(K_GJ_PANEL, s, nch * cmac * nlook * rows);
+        k_gj2_rows<T><<<grid_size(nch, rows), 256, 0, s>>>(js, nt);
         RCP_HIP(hipGetLastError());
       }
     }
