@@ -68,9 +68,9 @@ DESCR = {
 # for the kernel source it was measured on: reported when factor.hip still has
 # this hash.
 TRAFFIC = {"config": "config2", "batch": 8,
-           "sha256": "5f225f6026e7da83ef542137fd659a7f21ca9ec798c94d61f8b38b724bfffc01",
-           "fetch_bytes": 213551139,     # 104276.1 KiB FETCH_SIZE x 1.99994
-           "write_bytes": 156257485}    # 152595.2 KiB WRITE_SIZE x 1.00000
+           "sha256": "e1028bf2792498d6f320f140a3eb45b6f84bbc5000c5fefbaa64f0a71716751b",
+           "fetch_bytes": 212189500,     # 103611.0 KiB FETCH_SIZE x 1.99995
+           "write_bytes": 156782592}    # 153108.0 KiB WRITE_SIZE x 1.00000
 
 
 def factor_source_sha256():

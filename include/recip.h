@@ -312,13 +312,14 @@ int rcp_last_solve_stats(const rcp_factors* f, rcp_solve_stats* stats);
  * class with HIP events on the launching stream (k = 0 turns timing off);
  * rcp_timing_stop waits for those events and fills stats[c] for the classes
  *   0 Gauss-Jordan panels formed apart from a tile update (first panel of a
- *     block; for batches the pass that opens a block with the pivot work of
- *     panels 0 and 1, and the row tiles of each next pair of panels)
- *                                                     work = algorithmic flops
+ *     block; for batches the row tiles of each next pair of panels, and the
+ *     pass that opens a block with the pivot work of panels 0 and 1 when the
+ *     Schur-complement launch did not carry it)     work = algorithmic flops
  *   1 Gauss-Jordan tile update: for batches panels k, k+1 in one pass with
  *     the pivot work of panels k+2, k+3; for one geometry update k fused
  *     with panel k+1                                  work = algorithmic flops
- *   2 Schur-complement formation   work = bytes of factor blocks read + written
+ *   2 Schur-complement formation (for batches with the pivot work that opens
+ *     the next block)               work = bytes of factor blocks read + written
  *   3 single-RHS block product     work = bytes of factor blocks read
  *   4 multi-RHS block GEMM         work = algorithmic flops (8 per complex MAC)
  *   5 Gauss-Jordan last pass of a block (negated)    work = algorithmic flops
