@@ -137,7 +137,8 @@ int rcp_eps_from_widths(const rcp_grid* grid, const rcp_pillars* pillars,
                         double* eps_out_dev, rcp_stream stream);
 
 /* Bytes of device memory rcp_factor needs for this grid and precision
- * (factor blocks, operator coefficients, work vectors).  Exact; serving
+ * (factor blocks, operator coefficients, work vectors and scratch of the
+ * solves).  Exact; serving
  * admits requests by this number.  Returns 0 for an invalid grid. */
 size_t rcp_factor_bytes(const rcp_grid* grid, int32_t precision);
 
