@@ -4,9 +4,10 @@ Each test checks the oracle against something the paper or the mathematics
 fixes: the reciprocity identity of Eq. 7 against the quadrature of Eq. 6, the
 closed-form correlations against their defining integrals, the 2D Green's
 function (i/4) H0(kr), source/receiver reciprocity, the discrete flux balance
-of a lossless medium, the discrete planewave dispersion, symmetry, limits and
-linearity in the light distribution, central finite differences for the
-gradient, and the paper's Gauss-Legendre convergence numbers.
+of a lossless medium, the discrete planewave dispersion, the unit power of the
+planewave sources and the output-mode amplitude of the collimator objective,
+symmetry, limits and linearity in the light distribution, central finite
+differences for the gradient, and the paper's Gauss-Legendre convergence numbers.
 """
 import json
 import math
@@ -15,6 +16,7 @@ from pathlib import Path
 
 import numpy as np
 import pytest
+import scipy.integrate as si
 import scipy.special as sps
 
 import workloads as W
@@ -200,6 +202,104 @@ def test_P7_vacuum_planewave_phase(deg, tol):
     ry = win[:, 1:] / win[:, :-1]
     assert np.max(np.abs(rx - np.exp(1j * kx * h))) < tol
     assert np.max(np.abs(ry - np.exp(1j * kyt * h))) < tol
+
+
+# -- absolute scale of the sources and of the collimator mode --------------------------
+
+def uniform_medium(width_wl, height_wl, n, h):
+    """A box of uniform index n (no pillars) whose incidence line sits mid-height."""
+    p = W.metasurface("medium", width_wl, height_wl, 0, h=h)
+    return replace(p, eps_bg=n * n, eps_sub=n * n, eps_pillar=n * n, pillar_centers=(),
+                   widths=(), n_source=n, source_row=p.ny // 2)
+
+
+def radiated_power_per_length(p, theta):
+    """Power the aperture source b0(theta) radiates, per unit aperture length.
+
+    By the discrete flux identity (P6) the power leaving every region that holds
+    the source is Im sum_c conj(u_c) b_c; times h^2 it is the y-flux
+    sum_i Im(conj u_ij u_i,j+1) of a line, and 1/k normalises it so that a
+    planewave exp(i k_y y) of amplitude a carries |a|^2 k_y / k per unit length.
+    """
+    lu = fdfd.factor(fdfd.operator(p))
+    b = fdfd.planewave_sources(p, [theta])[:, 0]
+    u = lu.solve(b)
+    P = p.h ** 2 / fdfd.k0(p) * float(np.sum(np.imag(np.conj(u) * b)))
+    return P / (p.m_aperture * p.h)
+
+
+def finite_aperture_factor(p, theta):
+    """Power of a uniform sheet current of length L over that of the same current
+    per unit length on an infinite line (continuum, both sides).
+
+    A current J exp(i k_x x) on [0, L] has the spectrum J L sinc((k' - k_x) L / 2);
+    each propagating component k' radiates |J(k')|^2 / (4 k k_y(k')) to each side,
+    k_y = sqrt(K^2 - k'^2).  The infinite line gives |J|^2 L / (4 k k_y(k_x)) per
+    side, so the factor is k_y(k_x) L / (2 pi) * int sinc^2 / k_y(k') dk'.
+    """
+    K = p.n_source * fdfd.k0(p)
+    L = p.m_aperture * p.h
+    kx = K * math.sin(theta)
+    val, _ = si.quad(lambda kp: np.sinc((kp - kx) * L / (2 * math.pi)) ** 2, -K, K,
+                     weight="alg", wvar=(-0.5, -0.5), limit=2000)
+    return K * math.cos(theta) * L / (2 * math.pi) * val
+
+
+@pytest.mark.parametrize("n", [1.5, 2.0])
+def test_P16_planewave_sources_carry_unit_power(n):
+    """Sec. "Reciprocal approach": the sources are unit-power incident planewaves.
+
+    The aperture source b0(theta) must radiate one unit of power per unit length
+    to each side of the incidence line (2 per unit length in all), up to the
+    finite-aperture factor of the continuum and the second-order dispersion error
+    of the 5-point stencil: |P/2 - factor| <= (K h)^2 / 4, and the error falls ~4x
+    when h halves.  A lost factor 2 gives P/2 = 1/4, a lost sqrt(n) gives 1/n and a
+    lost cos(theta) gives 1/cos(theta) (1.3 at 40 deg).
+    """
+    for deg in (0.0, 20.0, 40.0):
+        th = math.radians(deg)
+        errs = []
+        for h in (0.05, 0.025):
+            p = uniform_medium(8, 2, n, h)
+            ratio = radiated_power_per_length(p, th) / 2.0 / finite_aperture_factor(p, th)
+            K = n * fdfd.k0(p)
+            assert abs(ratio - 1.0) <= (K * h) ** 2 / 4, (n, deg, h, ratio)
+            errs.append(ratio - 1.0)
+        assert 3.5 < errs[0] / errs[1] < 4.5, (n, deg, errs)
+
+
+@pytest.mark.parametrize("sin_phi", [0.1875, 0.3125])
+def test_P17_collimator_objective_is_the_output_mode_amplitude(sin_phi):
+    """Sec. "Reciprocal approach": the collimator FOM is the overlap of the field
+    with the output planewave mode at angle phi.
+
+    A vacuum planewave exp(i k sin(phi) x) is driven by a full-width line current
+    with stretched phase through the x-PML (as in P7).  On the monitor row w(phi)^dag u
+    must equal the wave's amplitude there (the mean of |u| over the row), and the
+    mode of the mirrored angle must not see it: sin(phi) is chosen so that the
+    phase 2 k sin(phi) x runs through whole cycles over the aperture.  A flipped
+    sign of phi makes |w(phi)^dag u| ~ 0; a lost h / L multiplies it by M.
+    """
+    phi = math.asin(sin_phi)
+    p = W.metasurface("vac", 8, 6, 0, objective=W.COLLIMATOR, phi=phi, monitor_y=3.0)
+    p = replace(p, eps_sub=1.0, eps_pillar=1.0, pillar_centers=(), widths=(), n_source=1.0)
+    assert abs(2 * fdfd.k0(p) * sin_phi * p.m_aperture * p.h / (2 * math.pi)
+               - round(2 * sin_phi * p.m_aperture * p.h)) < 1e-12
+    lu = fdfd.factor(fdfd.operator(p))
+    k, h = fdfd.k0(p), p.h
+    kx = k * sin_phi
+    sxc, sxf, syc, _ = fdfd.stretches(p)
+    xt = np.concatenate([[0.0], np.cumsum(sxf[1:p.nx] * h)]) + (-p.npml + 0.5) * h
+    js = p.npml + 20
+    b = np.zeros(p.nx * p.ny, complex)
+    b[fdfd.index(p, np.arange(p.nx), js)] = -sxc * syc[js] * np.exp(1j * kx * xt)
+    u = lu.solve(b)
+    i0, i1 = p.aperture
+    amp = np.abs(u.reshape(p.nx, p.ny)[i0:i1, p.monitor_row]).mean()
+    a_plus = abs(np.vdot(fdfd.objective_vector(p), u))
+    a_minus = abs(np.vdot(fdfd.objective_vector(replace(p, phi=-phi)), u))
+    assert abs(a_plus - amp) < 5e-3 * amp, (a_plus, amp)
+    assert a_minus < 1e-2 * amp, (a_minus, amp)
 
 
 # -- symmetry, limits, linearity -------------------------------------------------------
