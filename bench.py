@@ -29,6 +29,7 @@ import os
 import sys
 import threading
 import time
+from dataclasses import replace
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -103,52 +104,85 @@ def calibrate_copy():
 
 
 def nominal_lu_flops(p):
-    """Nominal block-elimination count: a dense complex inverse per block, 8 n^3 flops."""
+    """Dense-equivalent count: a dense complex inverse per block, 8 n^3 flops.  The
+    symmetric sweep does about half of it, so rates on this count can exceed the peak."""
     return 8.0 * p.ny ** 3 * p.nx
+
+
+def method_lu_flops(p):
+    """The method's own count: the symmetric inverse of a complex n x n block costs
+    4 n^3 flops (n columns, each a rank-1 update of the symmetric half, 8 flops per
+    complex multiply-add), n = ny unpadded."""
+    return 4.0 * p.ny ** 3 * p.nx
 
 
 def executed_lu_flops(p):
     """Flops the symmetric tile sweep executes: per block, nt panels each updating the
-    nt (nt + 1) / 2 packed 32 x 32 tiles with a rank-32 complex product."""
+    nt (nt + 1) / 2 packed 32 x 32 tiles with a rank-32 complex product (padded rows
+    and whole diagonal tiles included)."""
     nt = -(-p.ny // 32)
     return 8.0 * 32 ** 3 * nt * (nt * (nt + 1) // 2) * p.nx
 
 
-def cpu_baseline(p_full, width_wl=48):
-    """FP64 oracle (SuperLU + direct Toeplitz sum + adjoint) on a width slice, scaled by width."""
-    from dataclasses import replace
+def lu_rates(p, seconds, count=1, peak=None):
+    peak = FP64_PEAK_TFLOPS if peak is None else peak
+    m = count * method_lu_flops(p) / seconds / 1e12
+    return {"tflops_method_4n3": round(m, 3),
+            "frac_peak_method": round(m / peak, 4),
+            "tflops_executed": round(count * executed_lu_flops(p) / seconds / 1e12, 3),
+            "tflops_dense_equiv_8n3": round(count * nominal_lu_flops(p) / seconds / 1e12, 3)}
 
+
+def host_description():
+    """nproc, CPU model and the BLAS / OpenMP thread settings of this host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
+                                          "MKL_NUM_THREADS")}
+    return {"nproc": os.cpu_count(), "cpu_model": model, "env": env}
+
+
+def cpu_baseline(p):
+    """FP64 oracle on the benchmark workload itself: one geometry of the step
+    (SuperLU factor + reciprocal F by the direct Toeplitz double sum + adjoint
+    gradient), BLAS limited to one thread (SuperLU is sequential anyway)."""
     import workloads as W
     from oracle import average as ora
     try:
         from threadpoolctl import threadpool_limits
     except Exception:   # pragma: no cover
         threadpool_limits = None
-    wl_full = (p_full.nx - 2 * p_full.npml) * p_full.h
-    height = int(round((p_full.ny - 2 * p_full.npml) * p_full.h))
-    fh = (p_full.focus[1] - (p_full.pillar_row0 + p_full.pillar_rows)) * p_full.h
-    ps = W.metasurface("cpu_sample", width_wl, height, 7001, focus_height=fh,
-                       c_deg=math.degrees(p_full.c) if p_full.light == W.CONE else 10.0,
-                       objective=p_full.objective, light=p_full.light,
-                       th1_deg=math.degrees(p_full.th1), th2_deg=math.degrees(p_full.th2))
     ctx = threadpool_limits(limits=1) if threadpool_limits else None
     t0 = time.perf_counter()
-    s = ora.setup(ps)
+    s = ora.setup(p)
     g = ora.adjoint(s)
     t = time.perf_counter() - t0
-    if ctx is not None:
-        ctx.unregister() if hasattr(ctx, "unregister") else None
-    scale = ps.nx / p_full.nx
-    return {"value": scale / t, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle factor + reciprocal + adjoint on a {width_wl}-wavelength-wide "
-                      f"slice ({ps.nx}x{ps.ny} cells) of the same depth, {t:.1f} s, "
-                      f"scaled by width x{scale:.4f} (SuperLU/COLAMD, BLAS limited to 1 thread; "
-                      f"SuperLU cost grows faster than width, so this favours the CPU)",
-            "sample_seconds": t, "sample_F": g.F}
+    del s
+    if ctx is not None and hasattr(ctx, "unregister"):
+        ctx.unregister()
+    return {"value": 1.0 / t, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"one geometry of the benchmark workload itself ({p.nx}x{p.ny} cells, "
+                      f"the first seeded widths of the step): SuperLU/COLAMD factor + reciprocal F "
+                      f"(direct O(M^2) Toeplitz sum) + adjoint gradient, {t:.1f} s on one thread; "
+                      f"sparse LU with a fill-reducing ordering is a different, asymptotically "
+                      f"cheaper algorithm than block elimination",
+            "sample_seconds": round(t, 2), "sample_F": g.F, "host": host_description()}
 
 
 def serving(args):
-    """Poisson mix of concentrator/collimator requests: continuous batching vs sequential."""
+    """The serving mix as stated: a seeded Poisson stream at 200 requests/s of
+    concentrator and collimator evaluations, widths 20-300 and depths 10-60
+    wavelengths (every geometry fresh), 20% with an adjoint gradient, served with
+    continuous batching and admission by factor memory, against the same stream
+    served one request at a time (plain FP64, no cache).  Then two smaller mixes
+    where the factor cache and shared multi-RHS sweeps matter."""
     import torch
 
     import workloads as W
@@ -159,47 +193,58 @@ def serving(args):
     # warm the kernels once
     Server(ex, slots=1, hbm_budget=200 << 30, cache=False).run(reqs[:1], realtime=False)
     torch.cuda.synchronize()
-    seq = Server(ex, slots=1, hbm_budget=200 << 30, cache=False)
-    s_seq = summarize(seq.run(reqs, realtime=True))
     conc = Server(ex, slots=4, hbm_budget=200 << 30, cache=True)
     res = conc.run(reqs, realtime=True)
     conc.close()
     s_con = summarize(res)
-    # the same offered load over a seeded pool of 16 geometries: cached factors
-    # serve repeated geometries, only the solves and forms run again
-    preqs = W.serving_stream(args.serve_requests, rate=200.0, seed=5001, scale=args.serve_scale,
-                             adjoint_frac=0.2, geometry_pool=16)
-    pool = Server(ex, slots=4, hbm_budget=200 << 30, cache=True)
-    pres = pool.run(preqs, realtime=True)
-    pool.close()
-    s_pool = summarize(pres)
-    # a backlog: 64 plain requests over 4 geometries, all waiting at the start;
-    # requests on cached factors share one multi-RHS sweep (group 16) or not (1)
-    breqs = W.serving_stream(64, rate=200.0, seed=5004, scale=args.serve_scale, adjoint_frac=0.0,
-                             geometry_pool=4)
-    backlog = {}
-    for g in (16, 1):
-        srv = Server(ex, slots=4, hbm_budget=200 << 30, cache=True, group=g)
-        bres = srv.run(breqs, realtime=False)
-        srv.close()
-        sb = summarize(bres)
-        backlog[f"group_{g}"] = {"evals_per_s": round(sb["evals_per_s"], 3),
-                                 "p99_ms": round(sb["p99_ms"], 2), "failed": sb["failed"],
-                                 "shared_sweep_requests": sum(1 for r in bres if r.group > 1)}
-    return {"requests": len(reqs), "rate_per_s": 200.0, "scale": args.serve_scale,
-            "slots": 4, "p50_ms": round(s_con["p50_ms"], 2), "p99_ms": round(s_con["p99_ms"], 2),
-            "evals_per_s": round(s_con["evals_per_s"], 3), "max_inflight": conc.max_inflight,
-            "peak_factor_gb": round(conc.peak_bytes / 2 ** 30, 2),
-            "sequential": {"p50_ms": round(s_seq["p50_ms"], 2), "p99_ms": round(s_seq["p99_ms"], 2),
-                           "evals_per_s": round(s_seq["evals_per_s"], 3)},
-            "geometry_pool_16": {"p50_ms": round(s_pool["p50_ms"], 2),
-                                 "p99_ms": round(s_pool["p99_ms"], 2),
-                                 "evals_per_s": round(s_pool["evals_per_s"], 3),
-                                 "cache_hits": sum(1 for r in pres if r.cache_hit),
-                                 "shared_sweep_requests": sum(1 for r in pres if r.group > 1),
-                                 "failed": s_pool["failed"]},
-            "backlog_64_on_4_geometries": backlog,
-            "failed": s_con["failed"]}
+    log(f"serving: batched {s_con}")
+    seq = Server(ex, slots=1, hbm_budget=200 << 30, cache=False)
+    s_seq = summarize(seq.run(reqs, realtime=True))
+    log(f"serving: sequential {s_seq}")
+    out = {"stream": f"{len(reqs)} requests, Poisson 200/s (seed 5001, geometries seed 5002), "
+                     f"widths 20-300 and depths 10-60 wavelengths x{args.serve_scale}, "
+                     f"50/50 concentrator/collimator, cone or annulus, 20% adjoint",
+           "requests": len(reqs), "rate_per_s": 200.0, "scale": args.serve_scale,
+           "slots": 4, "p50_ms": round(s_con["p50_ms"], 2), "p99_ms": round(s_con["p99_ms"], 2),
+           "evals_per_s": round(s_con["evals_per_s"], 3), "makespan_s": round(s_con["makespan_s"], 3),
+           "max_inflight": conc.max_inflight, "peak_factor_gb": round(conc.peak_bytes / 2 ** 30, 2),
+           "failed": s_con["failed"],
+           "latency_note": "from arrival to result; the stream offers far more work than one GPU "
+                           "serves, so latency is queue-dominated",
+           "sequential_fp64": {"p50_ms": round(s_seq["p50_ms"], 2),
+                               "p99_ms": round(s_seq["p99_ms"], 2),
+                               "evals_per_s": round(s_seq["evals_per_s"], 3),
+                               "makespan_s": round(s_seq["makespan_s"], 3)}}
+    if args.serve_extras:
+        # the same kind of stream over a seeded pool of 16 geometries at a quarter
+        # of the size: cached factors serve repeated geometries
+        preqs = W.serving_stream(24, rate=200.0, seed=5001, scale=0.25, adjoint_frac=0.2,
+                                 geometry_pool=16)
+        pool = Server(ex, slots=4, hbm_budget=200 << 30, cache=True)
+        pres = pool.run(preqs, realtime=True)
+        pool.close()
+        s_pool = summarize(pres)
+        out["geometry_pool_16_scale_0.25"] = {
+            "requests": len(preqs), "p50_ms": round(s_pool["p50_ms"], 2),
+            "p99_ms": round(s_pool["p99_ms"], 2), "evals_per_s": round(s_pool["evals_per_s"], 3),
+            "cache_hits": sum(1 for r in pres if r.cache_hit),
+            "shared_sweep_requests": sum(1 for r in pres if r.group > 1),
+            "failed": s_pool["failed"]}
+        # a backlog: 64 plain requests over 4 geometries, all waiting at the start;
+        # requests on cached factors share one multi-RHS sweep (group 16) or not (1)
+        breqs = W.serving_stream(64, rate=200.0, seed=5004, scale=0.25, adjoint_frac=0.0,
+                                 geometry_pool=4)
+        backlog = {}
+        for g in (16, 1):
+            srv = Server(ex, slots=4, hbm_budget=200 << 30, cache=True, group=g)
+            bres = srv.run(breqs, realtime=False)
+            srv.close()
+            sb = summarize(bres)
+            backlog[f"group_{g}"] = {"evals_per_s": round(sb["evals_per_s"], 3),
+                                     "p99_ms": round(sb["p99_ms"], 2), "failed": sb["failed"],
+                                     "shared_sweep_requests": sum(1 for r in bres if r.group > 1)}
+        out["backlog_64_on_4_geometries_scale_0.25"] = backlog
+    return out
 
 
 def dense_extra(args, rcp, W, p, fac, t_rec, stream):
@@ -321,10 +366,12 @@ def main():
     ap.add_argument("--timing-every", type=int, default=32)
     ap.add_argument("--no-extras", action="store_true", help="time the step only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=24,
-                    help="requests in the serving measurement (0 = skip)")
-    ap.add_argument("--serve-scale", type=float, default=0.25,
-                    help="width/depth scale of the serving mix (1 = widths 20-300, depths 10-60)")
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests of the serving stream (0 = skip)")
+    ap.add_argument("--serve-scale", type=float, default=1.0,
+                    help="width/depth scale of the serving stream (1 = widths 20-300, depths 10-60)")
+    ap.add_argument("--no-serve-extras", dest="serve_extras", action="store_false",
+                    help="skip the geometry-pool and backlog serving runs")
     ap.add_argument("--batch", type=int, default=8,
                     help="geometries factored side by side per step (1-8)")
     ap.add_argument("--dense-outputs", type=int, default=16,
@@ -424,12 +471,14 @@ def main():
         if count == 0:
             return results
         for k in range(first, first + count):
-            if starts is not None:
-                starts.append(torch.cuda.Event(enable_timing=True))
-                starts[-1].record(stream)
             if pending is not None and nsets == 1:   # its factors are about to be overwritten
                 results.append(finish_adjoints(pending))
                 pending = None
+            # a step's latency clock starts once the previous step's adjoints
+            # no longer hold its factor buffers
+            if starts is not None:
+                starts.append(torch.cuda.Event(enable_timing=True))
+                starts[-1].record(stream)
             facs, ws = factor_step(k)
             if pending is not None:
                 results.append(finish_adjoints(pending))
@@ -460,13 +509,20 @@ def main():
     p99 = float(np.percentile(lat, 99))
 
     upd = kstats["gj_update"]
-    achieved = upd["work"] / (upd["ms"] * 1e-3) / 1e12 if upd["ms"] > 0 else 0.0
+    # the kernel timer counts executed flops (two panels x every packed tile of
+    # each chain's block); the roofline takes the method's count for the same
+    # work: 64 columns of a 4 n^3 symmetric inverse, 4 n^2 flops per column
+    nt = -(-p.ny // 32)
+    method_per_exec = (64 * 4.0 * p.ny ** 2) / (2 * (nt * (nt + 1) // 2) * 8.0 * 32 ** 3)
+    achieved = method_per_exec * upd["work"] / (upd["ms"] * 1e-3) / 1e12 if upd["ms"] > 0 else 0.0
     roofline = {"bound": "mfma", "kernel": "k_gj2_fused<double>", "achieved": round(achieved, 3),
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                 "traffic": measured_traffic(args.config, B),
                 "avg_launch_us": round(1e3 * upd["ms"] / max(upd["samples"], 1), 3),
-                "flops_per_launch": upd["work"] / max(upd["samples"], 1)}
+                "flops_per_launch": method_per_exec * upd["work"] / max(upd["samples"], 1),
+                "flop_count": "method: 64 columns x 4 ny^2 per chain (16 chains), "
+                              "padded rows and whole diagonal tiles not counted"}
     kernels = {}
     for name, st in kstats.items():
         if st["samples"]:
@@ -486,7 +542,9 @@ def main():
                               "factorisation when two factor sets fit)",
                       "geometries_per_step": B,
                       "precision": "complex FP64"},
-           "p50_ms": round(p50, 3), "p99_ms": round(p99, 3),
+           "step_latency_ms": {"p50": round(p50, 3), "p99": round(p99, 3),
+                               "definition": "start of a step's factorisation to its last "
+                                             "adjoint result"},
            "F": Fs[-1].item(), "roofline": roofline, "kernels": kernels}
 
     if not args.no_extras:
@@ -500,9 +558,7 @@ def main():
         b.record(stream)
         torch.cuda.synchronize()
         t_fac = a.elapsed_time(b) * 1e-3
-        out["lu_seconds"] = round(t_fac, 5)
-        out["lu_tflops_nominal"] = round(nominal_lu_flops(p) / t_fac / 1e12, 3)
-        out["lu_tflops_executed"] = round(executed_lu_flops(p) / t_fac / 1e12, 3)
+        out["lu_single"] = {"seconds": round(t_fac, 5), **lu_rates(p, t_fac)}
         if B > 1:   # the same B geometries factored side by side, as in the step
             eps_b = [rcp.eps_from_widths(p, w, device=dev) for w in widths[-B:]]
             del fac
@@ -512,13 +568,9 @@ def main():
             b.record(stream)
             torch.cuda.synchronize()
             t_b = a.elapsed_time(b) * 1e-3
-            out["lu_batch"] = {"geometries": B, "seconds": round(t_b, 5),
-                               "tflops_nominal": round(B * nominal_lu_flops(p) / t_b / 1e12, 3),
-                               "tflops_executed": round(B * executed_lu_flops(p) / t_b / 1e12, 3),
-                               "frac_fp64_peak_executed":
-                                   round(B * executed_lu_flops(p) / t_b / 1e12 / FP64_PEAK_TFLOPS, 4)}
+            out["lu_batch"] = {"geometries": B, "seconds": round(t_b, 5), **lu_rates(p, t_b, B)}
             log(f"batched factor x{B}: {t_b * 1e3:.1f} ms "
-                f"({out['lu_batch']['tflops_nominal']} TF/s nominal)")
+                f"({out['lu_batch']['tflops_method_4n3']} TF/s on the method's count)")
             fac = facs_b[-1]      # geometry widths[-1] again, now in bufs[-1]
             del facs_b
         # reciprocal average on cached factors
@@ -532,7 +584,7 @@ def main():
         torch.cuda.synchronize()
         t_rec = a.elapsed_time(b) * 1e-3 / reps
         out["reciprocal_cached_ms"] = round(1e3 * t_rec, 4)
-        log(f"factor {t_fac * 1e3:.1f} ms ({out['lu_tflops_nominal']} TF/s nominal), "
+        log(f"factor {t_fac * 1e3:.1f} ms ({out['lu_single']['tflops_method_4n3']} TF/s method), "
             f"reciprocal cached {t_rec * 1e3:.3f} ms, F={Fr.item():.10e}")
         # the brute force it replaces, same factors
         if p.light in (W.CONE, W.ANNULUS) and args.bf_angles > 0:
@@ -586,21 +638,15 @@ def main():
         F64, z64 = rcp.reciprocal_average(fac, p, want_z=True)
         torch.cuda.synchronize()
         zerr = (torch.linalg.vector_norm(z32 - z64) / torch.linalg.vector_norm(z64)).item()
-        out["fp32_refined"] = {"lu_seconds": round(t_f32, 5),
-                               "lu_tflops_nominal": round(nominal_lu_flops(p) / t_f32 / 1e12, 3),
-                               "lu_tflops_executed": round(executed_lu_flops(p) / t_f32 / 1e12, 3),
-                               "frac_fp32_peak_executed":
-                                   round(executed_lu_flops(p) / t_f32 / 1e12 / FP32_PEAK_TFLOPS, 4),
+        out["fp32_refined"] = {"lu_single": {"seconds": round(t_f32, 5),
+                                             **lu_rates(p, t_f32, 1, FP32_PEAK_TFLOPS)},
                                "refine_steps": it, "rel_residual": res,
                                "field_rel_err_vs_fp64": zerr,
                                "F_rel_err_vs_fp64": abs(F32.item() - F64.item()) / abs(F64.item())}
         if t_b32 is not None:
             out["fp32_refined"]["lu_batch"] = {
                 "geometries": B, "seconds": round(t_b32, 5),
-                "tflops_nominal": round(B * nominal_lu_flops(p) / t_b32 / 1e12, 3),
-                "tflops_executed": round(B * executed_lu_flops(p) / t_b32 / 1e12, 3),
-                "frac_fp32_peak_executed":
-                    round(B * executed_lu_flops(p) / t_b32 / 1e12 / FP32_PEAK_TFLOPS, 4),
+                **lu_rates(p, t_b32, B, FP32_PEAK_TFLOPS),
                 "speedup_vs_fp64_batch": round(out["lu_batch"]["seconds"] / t_b32, 3)
                 if "lu_batch" in out else None}
         log(f"fp32 refined: factor {t_f32 * 1e3:.1f} ms, {it} steps, field err {zerr:.2e}")
@@ -616,10 +662,13 @@ def main():
             log(f"design: {out['design']}")
     if args.serve_requests > 0:
         out["serving"] = serving(args)
+        out["p50_ms"] = out["serving"]["p50_ms"]
+        out["p99_ms"] = out["serving"]["p99_ms"]
+        out["config"]["serving"] = out["serving"]["stream"]
         log(f"serving: {out['serving']}")
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(p)
+        log("cpu baseline (oracle on the workload itself, ~1 min) ...")
+        out["cpu_baseline"] = cpu_baseline(replace(p, widths=W.seeded_widths(len(p.widths), 1002)))
         log(f"cpu baseline {out['cpu_baseline']['value']:.4g} evals/s")
     print(json.dumps(out), flush=True)
 

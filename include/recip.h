@@ -221,8 +221,9 @@ int rcp_adjoint_grad_batch(int32_t count, rcp_factors* const* factors,
  * them); otherwise one (refined) solve per objective.  Each F_k equals
  * rcp_reciprocal_average with objs[k] and lights[k] to rounding.  F_dev:
  * count float64 (device).  work_dev: at least
- * rcp_reciprocal_many_work_bytes(f, count) bytes, 256-byte aligned, scratch.
- * count 1..64; RCP_ENOMEM when work_bytes is short. */
+ * rcp_reciprocal_many_work_bytes(f, count) bytes, 256-byte aligned, scratch
+ * (RCP_EINVAL when misaligned).  count 1..64; RCP_ENOMEM when work_bytes is
+ * short. */
 size_t rcp_reciprocal_many_work_bytes(const rcp_factors* f, int32_t count);
 int rcp_reciprocal_average_many(const rcp_factors* f, int32_t count, const rcp_objective* objs,
                                 const rcp_light* lights, double* F_dev, void* work_dev,

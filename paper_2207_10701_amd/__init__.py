@@ -10,6 +10,8 @@ angle quadrature over forward solves (Eq. 6).
 from __future__ import annotations
 
 import ctypes as C
+import functools
+import inspect
 import math
 from typing import Optional, Tuple
 
@@ -30,6 +32,22 @@ __all__ = ["Factors", "factor_batch", "factor_bytes", "eps_from_widths", "recipr
 def _stream(stream: Optional[torch.cuda.Stream] = None) -> int:
     s = stream if stream is not None else torch.cuda.current_stream()
     return s.cuda_stream
+
+
+def _on_stream(fn):
+    """Run a wrapper that takes ``stream`` with that stream current, so that the
+    device temporaries it allocates (argument copies, workspaces, outputs) belong
+    to the stream its kernels run on and are not reused before they finish."""
+    sig = inspect.signature(fn)
+
+    @functools.wraps(fn)
+    def wrapper(*args, **kwargs):
+        stream = sig.bind_partial(*args, **kwargs).arguments.get("stream")
+        if stream is None:
+            return fn(*args, **kwargs)
+        with torch.cuda.stream(stream):
+            return fn(*args, **kwargs)
+    return wrapper
 
 
 def k0_of(p: Problem) -> float:
@@ -69,6 +87,7 @@ class _PillarArgs:
                                    p.sub_rows, p.pillar_row0, p.pillar_rows)
 
 
+@_on_stream
 def eps_from_widths(p: Problem, widths: Optional[torch.Tensor] = None, device="cuda",
                     stream=None) -> torch.Tensor:
     """Cell permittivity map (nx x ny float64) of the pillar layer (kernel a1)."""
@@ -90,6 +109,7 @@ def factor_bytes(p: Problem, precision: int = RCP_FP64) -> int:
 class Factors:
     """Factored operator of one geometry; owns its device buffer (a torch tensor)."""
 
+    @_on_stream
     def __init__(self, p: Problem, eps: torch.Tensor, precision: int = RCP_FP64, stream=None,
                  buffer: Optional[torch.Tensor] = None):
         self.problem = p
@@ -134,6 +154,7 @@ class Factors:
         return int(st.iters), float(st.rel_residual)
 
 
+@_on_stream
 def factor_batch(problems, eps_list, precision: int = RCP_FP64, buffers=None, stream=None):
     """Factor 1-8 same-grid geometries in the same kernel launches (chains side by side)."""
     B = len(problems)
@@ -151,6 +172,7 @@ def factor_batch(problems, eps_list, precision: int = RCP_FP64, buffers=None, st
     return [Factors._wrap(p, precision, b, C.c_void_p(h)) for p, b, h in zip(problems, buffers, outs)]
 
 
+@_on_stream
 def reciprocal_average(fac: Factors, p: Optional[Problem] = None, want_v: bool = False,
                        want_z: bool = False, symbol: Optional[torch.Tensor] = None, stream=None,
                        out: Optional[torch.Tensor] = None):
@@ -172,6 +194,7 @@ def reciprocal_average(fac: Factors, p: Optional[Problem] = None, want_v: bool =
     return res[0] if len(res) == 1 else tuple(res)
 
 
+@_on_stream
 def brute_force_average(fac: Factors, nangles: int, p: Optional[Problem] = None,
                         rhs_chunk: Optional[int] = None, per_angle: bool = False, stream=None,
                         work: Optional[torch.Tensor] = None):
@@ -191,6 +214,7 @@ def brute_force_average(fac: Factors, nangles: int, p: Optional[Problem] = None,
     return (F, pa) if per_angle else F
 
 
+@_on_stream
 def adjoint_grad(fac: Factors, p: Optional[Problem] = None, stream=None):
     """(F, dF/deps) with dF/deps an nx x ny float64 map, from one extra solve."""
     p = p or fac.problem
@@ -203,6 +227,7 @@ def adjoint_grad(fac: Factors, p: Optional[Problem] = None, stream=None):
     return F, g
 
 
+@_on_stream
 def adjoint_grad_batch(facs, problems=None, stream=None):
     """adjoint_grad for 1-8 factor sets of one grid (e.g. from factor_batch), their
     two solves advancing in the same kernel launches.  Returns (F of shape (B,),
@@ -223,6 +248,7 @@ def adjoint_grad_batch(facs, problems=None, stream=None):
     return F, grads
 
 
+@_on_stream
 def reciprocal_average_many(fac: Factors, problems, stream=None,
                             work: Optional[torch.Tensor] = None) -> torch.Tensor:
     """F for several requests on the same factors (problems of this geometry with
@@ -242,6 +268,7 @@ def reciprocal_average_many(fac: Factors, problems, stream=None,
     return F
 
 
+@_on_stream
 def broadband_grad(facs, weights, problems=None, stream=None):
     """Weighted sum over 1-8 factor sets (one geometry at the wavelengths of a
     spectral rule, e.g. from factor_batch): returns (F of shape (B + 1,) with the
@@ -269,6 +296,7 @@ def _work(need: int, device, work: Optional[torch.Tensor]) -> torch.Tensor:
     return work
 
 
+@_on_stream
 def correlation_matrix(p: Problem, thetas: torch.Tensor, C_amp: torch.Tensor, stream=None,
                        work: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Line correlation W = G C G^dag (M x M complex128) of a finite ensemble of
@@ -304,6 +332,7 @@ def _dense_args(fac: Factors, outputs, W: torch.Tensor, p: Optional[Problem]):
     return p, K, Wc, objs, light_struct(p), need
 
 
+@_on_stream
 def reciprocal_average_dense(fac: Factors, outputs, W: torch.Tensor, p: Optional[Problem] = None,
                              want_v: bool = False, stream=None,
                              work: Optional[torch.Tensor] = None):
@@ -320,6 +349,7 @@ def reciprocal_average_dense(fac: Factors, outputs, W: torch.Tensor, p: Optional
     return (F, V) if want_v else F
 
 
+@_on_stream
 def adjoint_grad_dense(fac: Factors, outputs, W: torch.Tensor, p: Optional[Problem] = None,
                        stream=None, work: Optional[torch.Tensor] = None):
     """(F of shape (K + 1,), d(sum_k F_k)/deps as an nx x ny map)."""
@@ -333,6 +363,7 @@ def adjoint_grad_dense(fac: Factors, outputs, W: torch.Tensor, p: Optional[Probl
     return F, g
 
 
+@_on_stream
 def width_grad(p: Problem, grad_eps: torch.Tensor, widths: Optional[torch.Tensor] = None,
                stream=None) -> torch.Tensor:
     """Chain rule dF/deps -> dF/dwidths (kernel, backward of eps_from_widths)."""
@@ -345,6 +376,7 @@ def width_grad(p: Problem, grad_eps: torch.Tensor, widths: Optional[torch.Tensor
     return out
 
 
+@_on_stream
 def solve(fac: Factors, B: torch.Tensor, conj_transpose: bool = False, tol: float = 1e-12,
           max_refine: int = 10, stream=None):
     """X = A^{-1} B (or A^{-dag} B) for B of shape (R, nx, ny) complex128."""
@@ -360,19 +392,32 @@ def solve(fac: Factors, B: torch.Tensor, conj_transpose: bool = False, tol: floa
 
 
 class IncoherentFOM(torch.autograd.Function):
-    """Angle-averaged FOM as a differentiable function of the pillar widths.
+    """Angle-averaged FOM as a differentiable function of the pillar widths or of
+    the per-pixel permittivity.
 
-    forward: widths -> eps (kernel) -> factor -> F = v^dag W v
-    backward: dF/dwidths from the adjoint solve and the eps(widths) chain rule.
+    x is either the widths (1-D, one per pillar of the problem) or a permittivity
+    map (nx x ny float64).
+    forward: [widths -> eps (kernel)] -> factor -> F = v^dag W v
+    backward: dF/deps from the adjoint solve (Sec. "Reciprocal approach"), and for
+    widths the eps(widths) chain rule.
     """
 
     @staticmethod
-    def forward(ctx, widths: torch.Tensor, problem: Problem, precision: int = RCP_FP64):
-        eps = eps_from_widths(problem, widths, device=widths.device)
+    def forward(ctx, x: torch.Tensor, problem: Problem, precision: int = RCP_FP64):
+        if x.dim() == 2:
+            if tuple(x.shape) != (problem.nx, problem.ny):
+                raise ValueError("a permittivity map must be nx x ny")
+            eps = x.detach()
+        elif x.dim() == 1:
+            if x.numel() != len(problem.pillar_centers):
+                raise ValueError("widths must hold one value per pillar")
+            eps = eps_from_widths(problem, x, device=x.device)
+        else:
+            raise ValueError("x must be the widths (1-D) or a permittivity map (nx x ny)")
         fac = Factors(problem, eps, precision)
-        if widths.requires_grad:
+        if x.requires_grad:
             F, g = adjoint_grad(fac, problem)
-            ctx.save_for_backward(width_grad(problem, g, widths))
+            ctx.save_for_backward(g if x.dim() == 2 else width_grad(problem, g, x))
         else:
             F = reciprocal_average(fac, problem)
             ctx.save_for_backward(None)

@@ -501,6 +501,8 @@ int rcp_reciprocal_average_many(const rcp_factors* fc, int32_t count, const rcp_
                                 const rcp_light* lights, double* F_dev, void* work_dev,
                                 size_t work_bytes, rcp_stream stream) {
   rcp_factors* f = const_cast<rcp_factors*>(fc);
+  if (reinterpret_cast<uintptr_t>(work_dev) % 256 != 0)
+    return fail(RCP_EINVAL, "workspace must be 256-byte aligned");
   if (!f) return fail(RCP_EINVAL, "factors is NULL");
   if (count < 1 || count > 64) return fail(RCP_EINVAL, "count must be 1 to 64");
   if (!objs || !lights || !F_dev || !work_dev) return fail(RCP_EINVAL, "NULL argument");

@@ -10,7 +10,9 @@ memory is needed, so repeated geometries skip the factorisation.  When a
 request starts on cached factors, the requests for the same geometry that
 have already arrived (plain evaluations, up to ``group``) go with it: one
 multi-right-hand-side reciprocal sweep serves all of them.  Admission is
-first come, first served.  Latency is measured from arrival to result.
+first come, first served among requests that need memory for new factors; a request
+whose cached geometry is busy waits on it without holding back others.
+Latency is measured from arrival to result.
 
 The device work goes through an executor: ``GpuExecutor`` calls librecip;
 ``FakeExecutor`` models costs and memory on the host so the scheduling logic
@@ -96,6 +98,10 @@ class GpuExecutor:
             stream.synchronize()
         return F.item(), (gw.cpu().numpy() if gw is not None else None)
 
+    def many_work_bytes(self, fac, count: int) -> int:
+        """Device workspace of a grouped evaluation of count requests."""
+        return int(self.rcp.lib.rcp_reciprocal_many_work_bytes(fac.handle, count))
+
     def evaluate_many(self, fac, problems, stream):
         """Plain evaluations of several requests on one factor set."""
         torch, rcp = self.torch, self.rcp
@@ -145,6 +151,10 @@ class FakeExecutor:
         time.sleep(self.eval_seconds)
         F = float(sum(p.widths)) + p.c + p.th1 + p.th2
         return F, ([1.0] * len(p.widths) if adjoint else None)
+
+    def many_work_bytes(self, fac, count: int) -> int:
+        p = fac["p"]
+        return 32 * count * p.nx * p.ny
 
     def evaluate_many(self, fac, problems, stream):
         time.sleep(self.eval_seconds)   # one sweep for all of them
@@ -208,24 +218,27 @@ class Server:
             self.ex.release(victim.fac)
         return True
 
-    def _try_admit(self, req: Request):
-        """Returns (slot, entry) if req can start now, None if it must wait."""
-        if not self.free_slots:
-            return None
+    _PARK = object()      # the request waits on its cached entry; later ones may start
+    _BLOCK = object()     # no memory for new factors: later fresh requests wait too
+
+    def _try_admit(self, req: Request, fresh_blocked: bool):
+        """(slot, entry) if req can start now, else _PARK or _BLOCK."""
         key = geometry_key(req.problem)
         entry = self.cache.get(key)
         if entry is not None:
             # factors hold per-call work vectors: one user at a time, and a
             # geometry being factored is waited for rather than factored twice
             if entry.users > 0 or not entry.ready:
-                return None
+                return self._PARK
             entry.users += 1
             return self.free_slots.pop(0), entry
+        if fresh_blocked:      # first come, first served among requests needing memory
+            return self._BLOCK
         need = self.ex.factor_bytes(req.problem)
         if need > self.budget:
             raise ServerError(f"request {req.rid} needs {need} bytes, budget {self.budget}")
         if not self._evict_for(need):
-            return None
+            return self._BLOCK
         entry = _Entry(key, None, need, users=1, ready=False)
         self.used += need
         if self.cache_enabled:
@@ -269,7 +282,7 @@ class Server:
             self.cv.notify_all()
 
     def _run_group(self, reqs: List[Request], slot: int, entry: _Entry, t0: float,
-                   arrivals: List[float]):
+                   arrivals: List[float], work_bytes: int):
         """Plain evaluations of several requests on the same cached factors."""
         start = time.perf_counter() - t0
         err, Fs = None, [None] * len(reqs)
@@ -279,6 +292,7 @@ class Server:
             err = str(e)
         done = time.perf_counter() - t0
         with self.cv:
+            self.used -= work_bytes
             entry.users -= 1
             entry.last_used = done
             self.free_slots.append(slot)
@@ -293,60 +307,96 @@ class Server:
     # -- driver -----------------------------------------------------------------------------
     def run(self, requests: List[Request], realtime: bool = True) -> List[Result]:
         """Serve a request stream.  realtime: replay the arrival times; otherwise
-        every request is present at the start (latency counted from there)."""
+        every request is present at the start (latency counted from there).
+
+        Arrived requests are scanned in arrival order at every change.  A request
+        whose geometry is cached but busy (in use, or still being factored) is
+        parked and the scan goes on, so it never holds back unrelated requests;
+        it starts, or joins a group, once its entry is free.  A fresh request
+        that does not fit in memory holds back later fresh requests (first come,
+        first served for memory), not requests on cached factors."""
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
         t0 = time.perf_counter()
         threads = []
-        taken = set()      # requests that went with an earlier one
-        i = 0
+        waiting: List[Request] = []
+        nxt = 0
         with self.cv:
-            while i < len(pending):
-                req = pending[i]
-                if req.rid in taken:
-                    i += 1
-                    continue
+            while nxt < len(pending) or waiting:
                 now = time.perf_counter() - t0
-                if realtime and req.arrival > now:
-                    self.cv.wait(timeout=req.arrival - now)
+                while nxt < len(pending) and (not realtime or pending[nxt].arrival <= now):
+                    waiting.append(pending[nxt])
+                    nxt += 1
+                started = self._admit_waiting(waiting, t0, now, realtime, threads)
+                if started:
                     continue
-                arrival = req.arrival if realtime else 0.0
-                try:
-                    adm = self._try_admit(req)
-                except ServerError as e:
-                    self.results[req.rid] = Result(rid=req.rid, error=str(e), arrival=arrival,
-                                                   done=time.perf_counter() - t0)
-                    i += 1
-                    continue
-                if adm is None:
-                    self.cv.wait(timeout=0.05)
-                    continue
-                slot, entry = adm
-                self.inflight += 1
-                self.max_inflight = max(self.max_inflight, self.inflight)
-                self.peak_bytes = max(self.peak_bytes, self.used)
-                group = [req]
-                if entry.ready and not req.adjoint and self.group > 1:
-                    key = geometry_key(req.problem)
-                    for other in pending[i + 1:]:
-                        if len(group) >= self.group or (realtime and other.arrival > now):
-                            break
-                        if (other.rid not in taken and not other.adjoint
-                                and geometry_key(other.problem) == key):
-                            group.append(other)
-                            taken.add(other.rid)
-                if len(group) > 1:
-                    arrivals = [r.arrival if realtime else 0.0 for r in group]
-                    th = threading.Thread(target=self._run_group,
-                                          args=(group, slot, entry, t0, arrivals), daemon=True)
-                else:
-                    th = threading.Thread(target=self._run, args=(req, slot, entry, t0, arrival),
-                                          daemon=True)
-                th.start()
-                threads.append(th)
-                i += 1
+                timeout = 0.05
+                if realtime and nxt < len(pending):
+                    timeout = min(timeout, max(pending[nxt].arrival - now, 0.0))
+                if waiting or nxt < len(pending):
+                    self.cv.wait(timeout=timeout)
         for th in threads:
             th.join()
         return [self.results[r.rid] for r in requests]
+
+    def _admit_waiting(self, waiting: List[Request], t0: float, now: float, realtime: bool,
+                       threads: list) -> bool:
+        """Start every waiting request that can start now; True if any did."""
+        started = False
+        fresh_blocked = False
+        i = 0
+        while i < len(waiting) and self.free_slots:
+            req = waiting[i]
+            arrival = req.arrival if realtime else 0.0
+            try:
+                adm = self._try_admit(req, fresh_blocked)
+            except ServerError as e:
+                self.results[req.rid] = Result(rid=req.rid, error=str(e), arrival=arrival,
+                                               done=time.perf_counter() - t0)
+                waiting.pop(i)
+                started = True
+                continue
+            if adm is self._PARK:
+                i += 1
+                continue
+            if adm is self._BLOCK:
+                fresh_blocked = True
+                i += 1
+                continue
+            slot, entry = adm
+            waiting.pop(i)
+            started = True
+            self.inflight += 1
+            self.max_inflight = max(self.max_inflight, self.inflight)
+            group, work = [req], 0
+            if entry.ready and not req.adjoint and self.group > 1:
+                key = geometry_key(req.problem)
+                for other in waiting[i:]:
+                    if len(group) >= self.group:
+                        break
+                    if not other.adjoint and geometry_key(other.problem) == key:
+                        group.append(other)
+                # the grouped call's workspace comes out of the same memory budget
+                while len(group) > 1:
+                    work = self.ex.many_work_bytes(entry.fac, len(group))
+                    if self._evict_for(work):
+                        break
+                    group.pop()
+                    work = 0
+                if len(group) > 1:
+                    self.used += work
+                    taken = {r.rid for r in group[1:]}
+                    waiting[i:] = [r for r in waiting[i:] if r.rid not in taken]
+            self.peak_bytes = max(self.peak_bytes, self.used)
+            if len(group) > 1:
+                arrivals = [r.arrival if realtime else 0.0 for r in group]
+                th = threading.Thread(target=self._run_group,
+                                      args=(group, slot, entry, t0, arrivals, work), daemon=True)
+            else:
+                th = threading.Thread(target=self._run, args=(req, slot, entry, t0, arrival),
+                                      daemon=True)
+            th.start()
+            threads.append(th)
+        return started
 
     def close(self):
         with self.cv:

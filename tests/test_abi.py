@@ -106,6 +106,10 @@ def test_adjoint_batch_argument_checks():
     grads = (C.c_void_p * 1)(None)
     rc = lib.rcp_adjoint_grad_batch(1, handles, o, lt, C.c_void_p(0x1000), grads, None)
     assert rc == _lib.RCP_EINVAL and b"NULL" in lib.rcp_last_error()
+    # the workspace must be 256-byte aligned, as for the other workspace entry points
+    rc = lib.rcp_reciprocal_average_many(None, 1, o, lt, C.c_void_p(0x1000), C.c_void_p(0x1008),
+                                         1 << 20, None)
+    assert rc == _lib.RCP_EINVAL and b"256-byte aligned" in lib.rcp_last_error()
 
 
 def test_dense_and_correlation_argument_checks():

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from gradcheck import assert_grad_close
 from oracle import average as ora
 
 pytestmark = pytest.mark.gpu
@@ -41,8 +42,8 @@ def test_broadband_matches_oracle(rcp, p, n):
     F = F.cpu().numpy()
     np.testing.assert_allclose(F[:-1], ref.F, rtol=1e-10)
     assert abs(F[-1] - ref.total) <= 1e-10 * abs(ref.total)
-    assert rel(g.cpu().numpy(), ref.grad_eps) < 1e-9
-    assert rel(rcp.width_grad(p, g).cpu().numpy(), ref.grad_widths) < 1e-9
+    assert_grad_close(g.cpu().numpy(), ref.grad_eps, 1e-9)
+    assert_grad_close(rcp.width_grad(p, g).cpu().numpy(), ref.grad_widths, 1e-9)
 
 
 def test_broadband_terms_equal_lone_wavelengths(rcp):
@@ -64,7 +65,7 @@ def test_broadband_refined_fp32(rcp):
     F, g = rcp.broadband_grad(facs, wts, probs)
     ref = ora.broadband(p, lams, wts)
     np.testing.assert_allclose(F.cpu().numpy()[:-1], ref.F, rtol=1e-6)
-    assert rel(g.cpu().numpy(), ref.grad_eps) < 1e-5
+    assert_grad_close(g.cpu().numpy(), ref.grad_eps, 1e-5)
 
 
 def test_broadband_argument_checks(rcp):

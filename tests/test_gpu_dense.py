@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from gradcheck import assert_grad_close
 from oracle import average as ora
 from oracle import light
 
@@ -115,9 +116,9 @@ def test_dense_adjoint_matches_oracle(rcp, name, spots, modes):
     F, g = rcp.adjoint_grad_dense(fac, outs, Wg)
     ref = ora.adjoint_dense(oracle_setup(p), outs, light.ensemble_correlation(p, th, Ca))
     np.testing.assert_allclose(F.cpu().numpy()[:-1], ref.F, rtol=1e-10)
-    assert rel(g.cpu().numpy(), ref.grad_eps) < 1e-9
+    assert_grad_close(g.cpu().numpy(), ref.grad_eps, 1e-9)
     gw = rcp.width_grad(p, g).cpu().numpy()
-    assert rel(gw, ref.grad_widths) < 1e-9
+    assert_grad_close(gw, ref.grad_widths, 1e-9)
 
 
 def test_dense_refined_fp32_matches_oracle(rcp):
@@ -131,7 +132,7 @@ def test_dense_refined_fp32_matches_oracle(rcp):
     ref = ora.adjoint_dense(oracle_setup(p), outs, light.ensemble_correlation(p, th, Ca))
     assert rel(V.cpu().numpy().T, ref.V) < 1e-8
     np.testing.assert_allclose(F.cpu().numpy()[:-1], ref.F, rtol=1e-6)
-    assert rel(g.cpu().numpy(), ref.grad_eps) < 1e-5
+    assert_grad_close(g.cpu().numpy(), ref.grad_eps, 1e-5)
 
 
 def test_dense_repeated_calls_reuse_the_workspace(rcp):
@@ -195,4 +196,4 @@ def test_config2_dense_matches_oracle_at_full_size(rcp):
     assert rel(V.cpu().numpy().T, ref.V) < 1e-10
     np.testing.assert_allclose(F.cpu().numpy()[:-1], ref.F, rtol=1e-10)
     np.testing.assert_allclose(Fa.cpu().numpy()[:-1], ref.F, rtol=1e-10)
-    assert rel(g.cpu().numpy(), ref.grad_eps) < 1e-9
+    assert_grad_close(g.cpu().numpy(), ref.grad_eps, 1e-9)

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from gradcheck import assert_grad_close
 from oracle import average as ora
 from oracle import fdfd, light
 
@@ -122,9 +123,9 @@ def test_adjoint_fp64(rcp, name):
     F, g = rcp.adjoint_grad(fac, p)
     ref = ora.adjoint(oracle_setup(p))
     assert abs(F.item() - ref.F) / abs(ref.F) < 1e-10
-    assert rel(g.cpu().numpy(), ref.grad_eps) < 1e-9
+    assert_grad_close(g.cpu().numpy(), ref.grad_eps, 1e-9)
     gw = rcp.width_grad(p, g)
-    assert rel(gw.cpu().numpy(), ref.grad_widths) < 1e-9
+    assert_grad_close(gw.cpu().numpy(), ref.grad_widths, 1e-9)
 
 
 @pytest.mark.parametrize("name", list(PROBLEMS))
@@ -244,7 +245,7 @@ def test_adjoint_batch_matches_single(rcp, count):
         assert torch_equal(gb[g], g1)
     ref = ora.adjoint(oracle_setup(probs[-1]))
     assert abs(Fb[-1].item() - ref.F) / abs(ref.F) < 1e-10
-    assert rel(gb[-1].cpu().numpy(), ref.grad_eps) < 1e-9
+    assert_grad_close(gb[-1].cpu().numpy(), ref.grad_eps, 1e-9)
 
 
 def test_adjoint_batch_tile_once_product(rcp):
@@ -263,7 +264,7 @@ def test_adjoint_batch_tile_once_product(rcp):
         assert torch_equal(gb[g], g1)
         ref = ora.adjoint(oracle_setup(probs[g]))
         assert abs(Fb[g].item() - ref.F) / abs(ref.F) < 1e-10
-        assert rel(gb[g].cpu().numpy(), ref.grad_eps) < 1e-9
+        assert_grad_close(gb[g].cpu().numpy(), ref.grad_eps, 1e-9)
 
 
 def test_adjoint_batch_refined_fp32_falls_back_per_set(rcp):

@@ -81,3 +81,38 @@ def test_pool_requests_grouped_on_cached_factors(rcp):
         F = rcp.reciprocal_average(fac, q.problem).item()
         torch.cuda.synchronize()
         assert abs(F - r.F) <= 1e-10 * abs(F)
+
+
+def test_wrappers_on_a_side_stream_outside_any_stream_context(rcp):
+    """A wrapper called with stream=side while another stream is current allocates
+    its temporaries on side: memory the current stream allocates and overwrites
+    right after the call cannot be the memory side's kernels still read."""
+    import torch
+    from dataclasses import replace
+    base = W.small_problem(5, 4, seed=8)
+    probs = [base, W.with_light(base, light=W.ANNULUS, th1=0.1, th2=0.4),
+             replace(base, objective=W.COLLIMATOR, monitor_row=base.ny - base.npml - 5, phi=0.1)]
+    fac = rcp.Factors(base, rcp.eps_from_widths(base, device="cuda"))
+    ref = rcp.reciprocal_average_many(fac, probs).cpu().tolist()
+    single = [rcp.reciprocal_average(fac, q).item() for q in probs]
+    assert all(abs(a - b) <= 1e-12 * abs(b) for a, b in zip(ref, single))
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    for _ in range(3):
+        F = rcp.reciprocal_average_many(fac, probs, stream=side)
+        junk = [torch.full((1 << 20,), 7.0, dtype=torch.float64, device="cuda") for _ in range(8)]
+        side.synchronize()
+        assert F.cpu().tolist() == ref
+        del junk
+
+
+def test_misaligned_workspace_is_rejected(rcp):
+    import torch
+    from paper_2207_10701_amd import _lib
+    p = W.small_problem(4, 4, seed=7)
+    fac = rcp.Factors(p, rcp.eps_from_widths(p, device="cuda"))
+    need = int(_lib.lib.rcp_reciprocal_many_work_bytes(fac.handle, 2))
+    work = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(rcp.RecipError) as e:
+        rcp.reciprocal_average_many(fac, [p, p], work=work[8:])
+    assert e.value.code == _lib.RCP_EINVAL and "aligned" in str(e.value)

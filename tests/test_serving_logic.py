@@ -138,3 +138,34 @@ def test_group_size_recorded():
     sizes = [r.group for r in out]
     assert sizes[0] == 1 and max(sizes) == 6
     assert all(r.cache_hit for r, g in zip(out, sizes) if g > 1)
+
+
+def test_request_on_busy_geometry_does_not_block_later_ones():
+    """A request whose geometry is still being factored waits on it; an unrelated
+    request that arrives after it starts at once (no head-of-line blocking)."""
+    pg = W.small_problem(2, 4, seed=3)
+    ph = W.small_problem(3, 4, seed=4)
+    reqs = [W.Request(rid=0, arrival=0.0, problem=pg, adjoint=False),
+            W.Request(rid=1, arrival=0.001, problem=pg, adjoint=True),
+            W.Request(rid=2, arrival=0.002, problem=ph, adjoint=False)]
+    ex = FakeExecutor(factor_seconds=lambda p: 0.3 if p is pg else 0.001)
+    out = Server(ex, slots=3, hbm_budget=10 ** 12).run(reqs)
+    assert all(r.error is None for r in out)
+    assert out[2].done < out[0].done       # H finished while G was still factoring
+    assert out[1].start >= out[0].done - 1e-3 and out[1].cache_hit
+    assert ex.factor_calls == 2
+
+
+def test_group_workspace_counts_against_the_budget():
+    """A grouped evaluation's workspace is reserved in the memory ledger; when it
+    does not fit, the group shrinks (down to single evaluations)."""
+    p = W.small_problem(2, 4, seed=3)
+    reqs = [W.Request(rid=i, arrival=0.0, problem=p, adjoint=False) for i in range(9)]
+    ex = FakeExecutor()
+    fb = ex.factor_bytes(p)
+    one = 32 * p.nx * p.ny
+    srv = Server(ex, slots=1, hbm_budget=fb + 4 * one, group=8)
+    out = srv.run(reqs, realtime=False)
+    assert all(r.error is None for r in out)
+    assert max(r.group for r in out) == 4
+    assert srv.peak_bytes <= fb + 4 * one
