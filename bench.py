@@ -179,48 +179,69 @@ def cpu_baseline(p):
 def serving(args):
     """The serving mix as stated: a seeded Poisson stream at 200 requests/s of
     concentrator and collimator evaluations, widths 20-300 and depths 10-60
-    wavelengths (every geometry fresh), 20% with an adjoint gradient, served with
-    continuous batching and admission by factor memory, against the same stream
-    served one request at a time (plain FP64, no cache).  Then two smaller mixes
-    where the factor cache and shared multi-RHS sweeps matter."""
+    wavelengths (every geometry fresh), 20% with an adjoint gradient, served
+    with continuous batching (the factorisation engine: every geometry in flight
+    advances in shared launches, new ones join between rounds; evaluations on
+    four streams beside it) and admission by factor memory, against the same
+    stream served one request at a time (plain FP64, factored alone, nothing
+    cached).  Then two smaller mixes where the factor cache and shared
+    multi-RHS sweeps matter."""
     import torch
 
     import workloads as W
-    from paper_2207_10701_amd.serve import GpuExecutor, Server, summarize
+    from paper_2207_10701_amd.serve import GpuExecutor, Server, serve_sequential, summarize
     reqs = W.serving_stream(args.serve_requests, rate=200.0, seed=5001, scale=args.serve_scale,
                             adjoint_frac=0.2)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    budget = int(free - (24 << 30))
     ex = GpuExecutor()
     # warm the kernels once
-    Server(ex, slots=1, hbm_budget=200 << 30, cache=False).run(reqs[:1], realtime=False)
+    warm = Server(ex, hbm_budget=budget, cache=False)
+    warm.run(reqs[:1], realtime=False)
+    warm.close()
     torch.cuda.synchronize()
-    conc = Server(ex, slots=4, hbm_budget=200 << 30, cache=True)
+    conc = Server(ex, factor_slots=8, eval_slots=4, hbm_budget=budget, cache=True)
     res = conc.run(reqs, realtime=True)
     conc.close()
     s_con = summarize(res)
-    log(f"serving: batched {s_con}")
-    seq = Server(ex, slots=1, hbm_budget=200 << 30, cache=False)
-    s_seq = summarize(seq.run(reqs, realtime=True))
+    log(f"serving: engine {s_con}")
+    errors = sorted({r.error for r in res if r.error})[:3]
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    seq = serve_sequential(ex, reqs, realtime=True)
+    s_seq = summarize(seq)
     log(f"serving: sequential {s_seq}")
+    work = sum(4.0 * q.problem.ny ** 3 * q.problem.nx for q in reqs)
     out = {"stream": f"{len(reqs)} requests, Poisson 200/s (seed 5001, geometries seed 5002), "
                      f"widths 20-300 and depths 10-60 wavelengths x{args.serve_scale}, "
                      f"50/50 concentrator/collimator, cone or annulus, 20% adjoint",
            "requests": len(reqs), "rate_per_s": 200.0, "scale": args.serve_scale,
-           "slots": 4, "p50_ms": round(s_con["p50_ms"], 2), "p99_ms": round(s_con["p99_ms"], 2),
+           "factor_work_tflop_method": round(work / 1e12, 1),
+           "factor_slots": 8, "eval_slots": 4, "hbm_budget_gb": round(budget / 2 ** 30, 1),
+           "p50_ms": round(s_con["p50_ms"], 2), "p99_ms": round(s_con["p99_ms"], 2),
            "evals_per_s": round(s_con["evals_per_s"], 3), "makespan_s": round(s_con["makespan_s"], 3),
-           "max_inflight": conc.max_inflight, "peak_factor_gb": round(conc.peak_bytes / 2 ** 30, 2),
-           "failed": s_con["failed"],
+           "factor_tflops_method": round(work / s_con["makespan_s"] / 1e12, 2)
+           if s_con["makespan_s"] > 0 else None,
+           "max_geometries_factoring": conc.max_factoring, "max_evaluations": conc.max_inflight,
+           "peak_ledger_gb": round(conc.peak_bytes / 2 ** 30, 2),
+           "failed": s_con["failed"], "errors": errors,
            "latency_note": "from arrival to result; the stream offers far more work than one GPU "
                            "serves, so latency is queue-dominated",
            "sequential_fp64": {"p50_ms": round(s_seq["p50_ms"], 2),
                                "p99_ms": round(s_seq["p99_ms"], 2),
                                "evals_per_s": round(s_seq["evals_per_s"], 3),
-                               "makespan_s": round(s_seq["makespan_s"], 3)}}
+                               "makespan_s": round(s_seq["makespan_s"], 3),
+                               "failed": s_seq["failed"]},
+           "speedup_vs_sequential": round(s_con["evals_per_s"] / s_seq["evals_per_s"], 3)
+           if s_seq["evals_per_s"] > 0 else None}
     if args.serve_extras:
         # the same kind of stream over a seeded pool of 16 geometries at a quarter
         # of the size: cached factors serve repeated geometries
         preqs = W.serving_stream(24, rate=200.0, seed=5001, scale=0.25, adjoint_frac=0.2,
                                  geometry_pool=16)
-        pool = Server(ex, slots=4, hbm_budget=200 << 30, cache=True)
+        pool = Server(ex, hbm_budget=budget, cache=True)
         pres = pool.run(preqs, realtime=True)
         pool.close()
         s_pool = summarize(pres)
@@ -236,7 +257,7 @@ def serving(args):
                                  geometry_pool=4)
         backlog = {}
         for g in (16, 1):
-            srv = Server(ex, slots=4, hbm_budget=200 << 30, cache=True, group=g)
+            srv = Server(ex, hbm_budget=budget, cache=True, group=g)
             bres = srv.run(breqs, realtime=False)
             srv.close()
             sb = summarize(bres)
@@ -660,6 +681,8 @@ def main():
         if args.design_iters > 0:
             out["design"] = design_extra(args, W, p, B, bufs)
             log(f"design: {out['design']}")
+    # the step's factor buffers are not needed any more: serving gets the memory
+    results = fac = bufs = buf = bufsets = None
     if args.serve_requests > 0:
         out["serving"] = serving(args)
         out["p50_ms"] = out["serving"]["p50_ms"]

@@ -163,6 +163,37 @@ int rcp_factor(const rcp_grid* grid, int32_t precision, void* buf_dev, size_t bu
 int rcp_factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, void* const* bufs,
                      size_t buf_bytes, rcp_stream stream, rcp_factors** out);
 
+/* a3 + a11 -- the factorisation engine: geometries of any grid size factored
+ * in shared kernel launches, admitted while others are in progress
+ * (continuous batching of the factorisation).  Every geometry's chains
+ * (twisted block elimination, two Gauss-Jordan panels per pass) advance one
+ * pass per round; a round carries every chain of every geometry in flight, so
+ * small and large requests fill the GPU together.  The factors of a geometry
+ * are bit-identical to rcp_factor_batch's for the same grid (batch of two or
+ * more) whatever else shares the launches.  One precision per engine; at
+ * most 8 geometries in flight; blocks of more than 32 rows (ny > 32).  The
+ * engine is not thread-safe: one host thread drives it. */
+typedef struct rcp_engine rcp_engine;
+int rcp_engine_create(int32_t precision, rcp_engine** out);
+/* Frees the engine.  Handles of geometries still in flight stay the caller's
+ * (release them); their factors are incomplete. */
+void rcp_engine_destroy(rcp_engine* e);
+/* Admit a geometry: checks as rcp_factor, assembles the operator on stream and
+ * returns its handle in *out; its factorisation advances from the engine's
+ * next round.  The handle must not be used or released before a step reports
+ * it done.  RCP_EINVAL when 8 geometries are in flight.  buf_dev as for
+ * rcp_factor (caller-owned, rcp_factor_bytes, 256-byte aligned). */
+int rcp_engine_add(rcp_engine* e, const rcp_grid* grid, void* buf_dev, size_t buf_bytes,
+                   rcp_stream stream, rcp_factors** out);
+/* Enqueue up to `rounds` rounds on stream, returning after the first round in
+ * which some geometry completes.  done[0 .. *n_done - 1] get the completed
+ * handles and status[] their pivot check (RCP_OK or RCP_ESINGULAR, checked
+ * with one wait for the stream per step that completes geometries); cap >= 8.
+ * *n_active (may be NULL): geometries still in flight.  Work enqueued on
+ * stream; a completed handle is usable in stream order. */
+int rcp_engine_step(rcp_engine* e, int32_t rounds, rcp_stream stream, rcp_factors** done,
+                    int32_t* status, int32_t cap, int32_t* n_done, int32_t* n_active);
+
 /* Solve A X = B for nrhs right-hand sides (or A^dag X = B when
  * conj_transpose != 0, using A = A^T).  B_dev, X_dev: nrhs x nx x ny
  * complex128 (row r is one grid field); B_dev and X_dev must not overlap

@@ -22,7 +22,7 @@ from . import _lib
 from ._lib import (RCP_ANNULUS, RCP_COLLIMATOR, RCP_CONCENTRATOR, RCP_CONE, RCP_FP32_REFINED,
                    RCP_FP64, RCP_SYMBOL_TABLE, RecipError, check, lib)
 
-__all__ = ["Factors", "factor_batch", "factor_bytes", "eps_from_widths", "reciprocal_average",
+__all__ = ["Factors", "factor_batch", "FactorEngine", "factor_bytes", "eps_from_widths", "reciprocal_average",
            "brute_force_average", "adjoint_grad", "adjoint_grad_batch", "width_grad", "solve",
            "IncoherentFOM", "correlation_matrix", "reciprocal_average_dense",
            "adjoint_grad_dense", "broadband_grad",
@@ -170,6 +170,85 @@ def factor_batch(problems, eps_list, precision: int = RCP_FP64, buffers=None, st
     outs = (C.c_void_p * B)()
     check(lib.rcp_factor_batch(B, grids, precision, bufs, nbytes, _stream(stream), outs))
     return [Factors._wrap(p, precision, b, C.c_void_p(h)) for p, b, h in zip(problems, buffers, outs)]
+
+
+class FactorEngine:
+    """Factorisation engine (rcp_engine_*): geometries of any grid size factored
+    in shared kernel launches, admitted while others are in progress.
+
+    add() admits a geometry (its eps map, a caller buffer or a new one) and
+    returns its Factors, usable once step() reports it done; step() enqueues
+    rounds on the engine's stream and returns the Factors completed.  One host
+    thread drives an engine."""
+
+    def __init__(self, precision: int = RCP_FP64, stream: Optional[torch.cuda.Stream] = None):
+        self.precision = precision
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        check(lib.rcp_engine_create(precision, C.byref(h)))
+        self.handle = h
+        self.inflight = {}           # handle value -> (Factors, eps kept alive)
+
+    def __len__(self) -> int:
+        return len(self.inflight)
+
+    def add(self, p: Problem, eps: torch.Tensor, buffer: Optional[torch.Tensor] = None) -> Factors:
+        if len(self.inflight) >= 8:
+            raise RecipError(_lib.RCP_EINVAL, "engine full: 8 geometries in flight")
+        nbytes = factor_bytes(p, self.precision)
+        with torch.cuda.stream(self.stream):
+            if buffer is None:
+                buffer = torch.empty(nbytes, dtype=torch.uint8, device=eps.device)
+            if buffer.numel() < nbytes:
+                raise RecipError(_lib.RCP_ENOMEM, "factor buffer too small")
+            eps = eps.to(dtype=torch.float64).contiguous()
+            g = grid_struct(p, eps)
+            h = C.c_void_p()
+            check(lib.rcp_engine_add(self.handle, C.byref(g), buffer.data_ptr(), nbytes,
+                                     self.stream.cuda_stream, C.byref(h)))
+        fac = Factors._wrap(p, self.precision, buffer, h)
+        self.inflight[h.value] = (fac, eps)
+        return fac
+
+    def step(self, rounds: int = 1 << 30):
+        """Enqueue up to `rounds` rounds; returns [(Factors, error or None)] of the
+        geometries completed (a failed one is released)."""
+        done = (C.c_void_p * 8)()
+        status = (C.c_int32 * 8)()
+        nd, na = C.c_int32(0), C.c_int32(0)
+        with torch.cuda.stream(self.stream):
+            check(lib.rcp_engine_step(self.handle, int(rounds), self.stream.cuda_stream, done,
+                                      status, 8, C.byref(nd), C.byref(na)))
+        out = []
+        for i in range(nd.value):
+            fac, _ = self.inflight.pop(done[i])
+            err = None
+            if status[i] != _lib.RCP_OK:
+                err = RecipError(status[i], lib.rcp_last_error().decode())
+                fac.release()
+            out.append((fac, err))
+        return out
+
+    def run(self):
+        """Drive every geometry in flight to completion; returns what step() does."""
+        out = []
+        while self.inflight:
+            out += self.step()
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib.rcp_engine_destroy(self.handle)
+            self.handle = None
+            for fac, _ in self.inflight.values():
+                fac.release()
+            self.inflight.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 @_on_stream

@@ -53,9 +53,9 @@ class KernelStat(C.Structure):
                 ("work", C.c_double)]
 
 
-NKCLASS = 7
+NKCLASS = 8
 KCLASS_NAMES = ["gj_panel", "gj_update", "schur", "block_gemv", "block_gemm", "gj_last",
-                "dense_zgemm"]
+                "dense_zgemm", "engine"]
 
 
 class RecipError(RuntimeError):
@@ -94,6 +94,10 @@ def _load():
                                              sz, vp]),
         "rcp_correlation_work_bytes": (sz, [i32, i32]),
         "rcp_correlation_matrix": (C.c_int, [P(Grid), P(Light), i32, vp, vp, vp, vp, sz, vp]),
+        "rcp_engine_create": (C.c_int, [i32, P(vp)]),
+        "rcp_engine_destroy": (None, [vp]),
+        "rcp_engine_add": (C.c_int, [vp, P(Grid), vp, sz, vp, P(vp)]),
+        "rcp_engine_step": (C.c_int, [vp, i32, vp, P(vp), P(i32), i32, P(i32), P(i32)]),
         "rcp_factors_release": (None, [vp]),
         "rcp_last_error": (C.c_char_p, []),
         "rcp_last_solve_stats": (C.c_int, [vp, P(SolveStats)]),

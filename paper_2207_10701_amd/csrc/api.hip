@@ -251,6 +251,65 @@ int reciprocal_field(rcp_factors* f, const rcp_objective* obj, double2* z, hipSt
   return solve_vec_refined(f, w, z, 1, lo, hi, kRefineTol, kRefineMax, s, nullptr);
 }
 
+// One factor set in a caller buffer (layout L): the handle, its views of the
+// buffer, and the operator assembled on the stream.
+int init_factors(const rcp_grid* grid, int32_t precision, const Layout& L, void* buf,
+                 rcp_stream stream, rcp_factors** out) {
+  *out = nullptr;
+  rcp_factors* f = new (std::nothrow) rcp_factors();
+  if (!f) return fail(RCP_ENOMEM, "host allocation failed");
+  *out = f;
+  f->nx = grid->nx;
+  f->ny = grid->ny;
+  f->npml = grid->npml;
+  f->h = grid->h;
+  f->k0 = grid->k0;
+  f->pml_R = grid->pml_R;
+  f->pml_m = grid->pml_m;
+  f->precision = precision;
+  f->np = ceil_div(grid->ny, TB) * TB;
+  f->nt = f->np / TB;
+  f->tiles = size_t(f->nt) * (f->nt + 1) / 2;
+  f->block_elems = f->tiles * TB * TB;
+  f->elem_bytes = precision == RCP_FP64 ? 16 : 8;
+  f->m = grid->nx / 2;
+  f->fft_cap = fft_capacity(grid->nx);
+  f->lay = L;
+  char* b = static_cast<char*>(buf);
+  f->base = b;
+  f->X = b + L.off_X;
+  f->eps = reinterpret_cast<double*>(b + L.off_eps);
+  f->sxc = reinterpret_cast<double2*>(b + L.off_sxc);
+  f->sxf = reinterpret_cast<double2*>(b + L.off_sxf);
+  f->syc = reinterpret_cast<double2*>(b + L.off_syc);
+  f->syf = reinterpret_cast<double2*>(b + L.off_syf);
+  f->dco = reinterpret_cast<double2*>(b + L.off_dco);
+  f->eco = reinterpret_cast<double2*>(b + L.off_eco);
+  f->cco = reinterpret_cast<double2*>(b + L.off_cco);
+  const size_t panel = size_t(f->np) * TB * f->elem_bytes;
+  for (int c = 0; c < 8; ++c) {
+    f->wsL[c] = b + L.off_L + c * panel;
+    f->wsQ[c] = b + L.off_Q + c * panel;
+    f->wsP[c] = reinterpret_cast<double2*>(b + L.off_P) + c * TB * TB;
+  }
+  f->health = reinterpret_cast<double*>(b + L.off_health);
+  const size_t N = size_t(f->nx) * f->ny;
+  for (int v = 0; v < NVEC; ++v) f->vec[v] = reinterpret_cast<double2*>(b + L.off_vec) + v * N;
+  f->red = reinterpret_cast<double*>(b + L.off_red);
+  for (int q = 0; q < 4; ++q)
+    f->fft[q] = reinterpret_cast<double2*>(b + L.off_fft) + q * f->fft_cap;
+  for (int c = 0; c < 2; ++c)
+    f->part[c] = reinterpret_cast<double2*>(b + L.off_part) + c * 2 * f->tiles * TB;
+  f->last_iters = 0;
+  f->last_residual = 0.0;
+  int rc = launch_assemble(f, grid->eps_dev, stream);
+  if (rc) {
+    delete f;
+    *out = nullptr;
+  }
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -347,59 +406,7 @@ int rcp_factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, vo
   }
   rcp_factors* fs[MAX_BATCH] = {};   // count <= MAX_BATCH checked above
   int rc = RCP_OK;
-  for (int g = 0; g < count && !rc; ++g) {
-    const rcp_grid* grid = &grids[g];
-    rcp_factors* f = new (std::nothrow) rcp_factors();
-    if (!f) {
-      rc = fail(RCP_ENOMEM, "host allocation failed");
-      break;
-    }
-    fs[g] = f;
-    f->nx = grid->nx;
-    f->ny = grid->ny;
-    f->npml = grid->npml;
-    f->h = grid->h;
-    f->k0 = grid->k0;
-    f->pml_R = grid->pml_R;
-    f->pml_m = grid->pml_m;
-    f->precision = precision;
-    f->np = ceil_div(grid->ny, TB) * TB;
-    f->nt = f->np / TB;
-    f->tiles = size_t(f->nt) * (f->nt + 1) / 2;
-    f->block_elems = f->tiles * TB * TB;
-    f->elem_bytes = precision == RCP_FP64 ? 16 : 8;
-    f->m = grid->nx / 2;
-    f->fft_cap = fft_capacity(grid->nx);
-    f->lay = L;
-    char* b = static_cast<char*>(bufs[g]);
-    f->base = b;
-    f->X = b + L.off_X;
-    f->eps = reinterpret_cast<double*>(b + L.off_eps);
-    f->sxc = reinterpret_cast<double2*>(b + L.off_sxc);
-    f->sxf = reinterpret_cast<double2*>(b + L.off_sxf);
-    f->syc = reinterpret_cast<double2*>(b + L.off_syc);
-    f->syf = reinterpret_cast<double2*>(b + L.off_syf);
-    f->dco = reinterpret_cast<double2*>(b + L.off_dco);
-    f->eco = reinterpret_cast<double2*>(b + L.off_eco);
-    f->cco = reinterpret_cast<double2*>(b + L.off_cco);
-    const size_t panel = size_t(f->np) * TB * f->elem_bytes;
-    for (int c = 0; c < 8; ++c) {
-      f->wsL[c] = b + L.off_L + c * panel;
-      f->wsQ[c] = b + L.off_Q + c * panel;
-      f->wsP[c] = reinterpret_cast<double2*>(b + L.off_P) + c * TB * TB;
-    }
-    f->health = reinterpret_cast<double*>(b + L.off_health);
-    const size_t N = size_t(f->nx) * f->ny;
-    for (int v = 0; v < NVEC; ++v) f->vec[v] = reinterpret_cast<double2*>(b + L.off_vec) + v * N;
-    f->red = reinterpret_cast<double*>(b + L.off_red);
-    for (int q = 0; q < 4; ++q)
-      f->fft[q] = reinterpret_cast<double2*>(b + L.off_fft) + q * f->fft_cap;
-    for (int c = 0; c < 2; ++c)
-      f->part[c] = reinterpret_cast<double2*>(b + L.off_part) + c * 2 * f->tiles * TB;
-    f->last_iters = 0;
-    f->last_residual = 0.0;
-    rc = launch_assemble(f, grid->eps_dev, stream);
-  }
+  for (int g = 0; g < count && !rc; ++g) rc = init_factors(&grids[g], precision, L, bufs[g], stream, &fs[g]);
   if (!rc) rc = factor_blocks(fs, count, stream);
   if (rc) {
     for (int g = 0; g < count; ++g) delete fs[g];
@@ -415,6 +422,61 @@ int rcp_factor(const rcp_grid* grid, int32_t precision, void* buf_dev, size_t bu
   if (!grid) return fail(RCP_EINVAL, "grid is NULL");
   void* bufs[1] = {buf_dev};
   return rcp_factor_batch(1, grid, precision, bufs, buf_bytes, stream, out);
+}
+
+int rcp_engine_create(int32_t precision, rcp_engine** out) {
+  if (!out) return fail(RCP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (precision != RCP_FP64 && precision != RCP_FP32_REFINED)
+    return fail(RCP_EINVAL, "unknown precision");
+  return engine_create(precision, out);
+}
+
+void rcp_engine_destroy(rcp_engine* e) {
+  if (e) engine_destroy(e);
+}
+
+int rcp_engine_add(rcp_engine* e, const rcp_grid* grid, void* buf_dev, size_t buf_bytes,
+                   rcp_stream stream, rcp_factors** out) {
+  if (!out) return fail(RCP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!e) return fail(RCP_EINVAL, "engine is NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!grid->eps_dev) return fail(RCP_EINVAL, "eps_dev is NULL");
+  if (ceil_div(grid->ny, TB) < 2) return fail(RCP_EINVAL, "the engine needs ny > 32");
+  if (engine_active(e) >= MAX_BATCH) return fail(RCP_EINVAL, "engine full: 8 geometries in flight");
+  const int prec = engine_precision(e);
+  Layout L = compute_layout(grid->nx, grid->ny, prec);
+  if (!buf_dev) return fail(RCP_ENOMEM, "factor buffer is NULL");
+  if (buf_bytes < L.total)
+    return fail(RCP_ENOMEM, "factor buffer holds " + std::to_string(buf_bytes) + " bytes, needs " +
+                                std::to_string(L.total));
+  if (reinterpret_cast<uintptr_t>(buf_dev) % 256 != 0)
+    return fail(RCP_EINVAL, "factor buffer must be 256-byte aligned");
+  rcp_factors* f = nullptr;
+  rc = init_factors(grid, prec, L, buf_dev, stream, &f);
+  if (!rc) rc = engine_add(e, f);
+  if (rc) {
+    delete f;
+    return rc;
+  }
+  *out = f;
+  return RCP_OK;
+}
+
+int rcp_engine_step(rcp_engine* e, int32_t rounds, rcp_stream stream, rcp_factors** done,
+                    int32_t* status, int32_t cap, int32_t* n_done, int32_t* n_active) {
+  if (!e || !n_done) return fail(RCP_EINVAL, "NULL argument");
+  *n_done = 0;
+  if (rounds < 1) return fail(RCP_EINVAL, "rounds must be >= 1");
+  if (cap < MAX_BATCH || !done || !status)
+    return fail(RCP_EINVAL, "done and status must hold 8 entries");
+  int nd = 0;
+  int rc = engine_step(e, rounds, stream, done, status, cap, &nd);
+  *n_done = nd;
+  if (n_active) *n_active = engine_active(e);
+  return rc;
 }
 
 void rcp_factors_release(rcp_factors* f) { delete f; }

@@ -39,6 +39,34 @@
 namespace {
 using namespace rcp;
 
+// Placement of a launch's jobs on the 8 XCDs.  Workgroups are dealt to the
+// XCDs round robin (workgroup b runs on XCD b mod 8); each XCD's share is split
+// into two interleaved half-slots h = 2 x + (s mod 2), s = b / 8.  Half-slot h
+// serves job q[h]: its workgroups w = off[h], off[h] + stride[h], ... (a job on
+// u half-slots has offsets 0 .. u-1 and stride u; q[h] = -1: unused).  Keeping
+// a chain's workgroups on few XCDs keeps the panel buffers they all read in
+// those XCDs' L2; a job's share of half-slots follows its share of the work.
+constexpr int NHALF = 16;
+struct XMap {
+  int q[NHALF];
+  int off[NHALF];
+  int stride[NHALF];
+};
+#define RCP_SELA4(a, h, o) \
+  ((h) < (o) + 2 ? ((h) == (o) ? a[(o)] : a[(o) + 1]) : ((h) == (o) + 2 ? a[(o) + 2] : a[(o) + 3]))
+#define RCP_SELA16(a, h)                                                            \
+  ((h) < 8 ? ((h) < 4 ? RCP_SELA4(a, h, 0) : RCP_SELA4(a, h, 4))                    \
+           : ((h) < 12 ? RCP_SELA4(a, h, 8) : RCP_SELA4(a, h, 12)))
+
+__device__ __forceinline__ bool xjob(const XMap& m, int* q, int* w) {
+  const int b = blockIdx.x;
+  const int x = b & 7, s = b >> 3;
+  const int h = 2 * x + (s & 1);
+  *q = RCP_SELA16(m.q, h);
+  *w = RCP_SELA16(m.off, h) + (s >> 1) * RCP_SELA16(m.stride, h);
+  return *q >= 0;
+}
+
 struct GJJob {
   int k;         // panel index
   int last;      // update: final panel, negate the result
@@ -52,20 +80,18 @@ struct GJJob {
   void* Qn;
   double2* Pn;
   double* health;   // min |pivot| slot of the panel this job inverts
+  int tiles;        // packed tiles of the block (per job: chains may differ in size)
 };
 constexpr int MAXJ = 2 * MAX_BATCH;   // chains per launch: two per geometry
 struct GJJobs {
   GJJob j[MAXJ];
   int n;
+  XMap x;
 };
 
-// Job of this workgroup: every job of a launch has the same workgroup count;
-// fields are selected one at a time so that the table stays in kernel-argument
-// registers.
-__device__ __forceinline__ GJJob pick(const GJJobs& js, int* wg) {
-  const int per = js.j[0].wgs;
-  const int q = *wg / per;
-  *wg -= q * per;
+// Job q of a launch; fields are selected one at a time so that the table stays
+// in kernel-argument registers.
+__device__ __forceinline__ GJJob pick(const GJJobs& js, int q) {
 #define RCP_SEL(fld) RCP_SEL16(js, q, fld)
   GJJob jb;
   jb.k = RCP_SEL(k);
@@ -80,6 +106,7 @@ __device__ __forceinline__ GJJob pick(const GJJobs& js, int* wg) {
   jb.Qn = RCP_SEL(Qn);
   jb.Pn = RCP_SEL(Pn);
   jb.health = RCP_SEL(health);
+  jb.tiles = RCP_SEL(tiles);
 #undef RCP_SEL
   return jb;
 }
@@ -628,16 +655,18 @@ struct GJ2Job {
   void* Qb;
   double2* Pb;   // slot 0 of the chain's pivot-block inverses (TB x TB each)
   double* health;   // min |pivot| slots of this block, one per panel
+  int nt;        // tiles per block edge (per job: chains may differ in size)
+  int tiles;     // packed tiles per block
+  int open;      // k_gj2_step: 1 = this job opens its block (Schur complement
+                 // formed beside the pivot work of panels 0 and 1)
 };
 struct GJ2Jobs {
   GJ2Job j[MAXJ];
   int n;
+  XMap x;
 };
 
-__device__ __forceinline__ GJ2Job pick2(const GJ2Jobs& js, int* wg) {
-  const int per = js.j[0].wgs;
-  const int q = *wg / per;
-  *wg -= q * per;
+__device__ __forceinline__ GJ2Job pick2(const GJ2Jobs& js, int q) {
 #define RCP_SEL(fld) RCP_SEL16(js, q, fld)
   GJ2Job jb;
   jb.k = RCP_SEL(k);
@@ -650,6 +679,9 @@ __device__ __forceinline__ GJ2Job pick2(const GJ2Jobs& js, int* wg) {
   jb.Qb = RCP_SEL(Qb);
   jb.Pb = RCP_SEL(Pb);
   jb.health = RCP_SEL(health);
+  jb.nt = RCP_SEL(nt);
+  jb.tiles = RCP_SEL(tiles);
+  jb.open = RCP_SEL(open);
 #undef RCP_SEL
   return jb;
 }
@@ -1157,50 +1189,108 @@ __device__ void rows2_work(const GJ2Job& jb, int I, int nt, typename cplx<T>::t 
   q_quad_f<T>(c4re, c4im, p4, slot_ptr<T2>(jb.Qb, K4, nt) + I * TT, lr, lk, qa, qb);
 }
 
-// Workgroup -> (job q, index w within the job).  Workgroups are dealt to the 8
-// XCDs round robin.  When the job count n divides 8, job q gets the XCDs x with
-// x % n == q; when 8 divides n, XCD x serves jobs x, x + 8, ...; either way
-// the panel buffers a chain's workgroups all read stay in the L2 of its own
-// XCDs.  For n dividing 8 the grid is padded to a multiple of 8 (grid_size) and
-// the surplus workgroups return false.
-__device__ __forceinline__ bool job_of(int n, int per, int* q, int* w) {
-  const int b = blockIdx.x;
-  const int x = b & 7, slot = b >> 3;
-  if (8 % n == 0) {
-    *q = x % n;
-    *w = slot * (8 / n) + x / n;
-  } else if (n % 8 == 0) {
-    const int m = n / 8;
-    *q = x + 8 * (slot % m);
-    *w = slot / m;
-  } else {
-    *q = b / per;
-    *w = b - *q * per;
+// Host: the placement of n jobs whose workgroup counts are wgs[q] (a job's
+// share of the 16 half-slots follows its share of the workgroups, at least
+// one each; a job with an even share takes whole XCDs, the odd remainders are
+// paired largest with smallest), and the grid that covers it.
+int build_xmap(const int* wgs, int n, XMap* m) {
+  long long total = 0;
+  for (int q = 0; q < n; ++q) total += wgs[q] > 0 ? wgs[q] : 0;
+  int u[MAXJ] = {};
+  int used = 0;
+  double frac[MAXJ] = {};
+  for (int q = 0; q < n; ++q) {
+    const double ideal = total > 0 ? double(NHALF) * (wgs[q] > 0 ? wgs[q] : 0) / double(total) : 0.0;
+    u[q] = static_cast<int>(ideal);
+    if (u[q] < 1) u[q] = 1;
+    frac[q] = ideal - u[q];
+    used += u[q];
   }
-  return *w < per;
+  while (used > NHALF) {   // minimum shares overshot: take from the largest
+    int big = 0;
+    for (int q = 1; q < n; ++q) if (u[q] > u[big]) big = q;
+    --u[big];
+    --used;
+  }
+  while (used < NHALF) {   // largest remainders first
+    int best = 0;
+    for (int q = 1; q < n; ++q) if (frac[q] > frac[best]) best = q;
+    ++u[best];
+    frac[best] -= 1.0;
+    ++used;
+  }
+  int hq[NHALF], hoff[NHALF], hstr[NHALF];
+  int h = 0;
+  int single[MAXJ], ns = 0;
+  for (int q = 0; q < n; ++q) {   // whole XCDs
+    for (int i = 0; i + 1 < u[q]; i += 2) {
+      hq[h] = q; hoff[h] = i; hstr[h] = u[q]; ++h;
+      hq[h] = q; hoff[h] = i + 1; hstr[h] = u[q]; ++h;
+    }
+    if (u[q] & 1) single[ns++] = q;
+  }
+  // odd remainders: sort by load per half-slot, pair largest with smallest
+  for (int a = 1; a < ns; ++a)
+    for (int b = a; b > 0; --b) {
+      const int x = single[b], y = single[b - 1];
+      if (double(wgs[x]) / u[x] > double(wgs[y]) / u[y]) {
+        single[b] = y;
+        single[b - 1] = x;
+      } else {
+        break;
+      }
+    }
+  for (int a = 0, b = ns - 1; a <= b; ++a, --b) {
+    const int qa = single[a];
+    hq[h] = qa; hoff[h] = u[qa] - 1; hstr[h] = u[qa]; ++h;
+    if (a != b) {
+      const int qb = single[b];
+      hq[h] = qb; hoff[h] = u[qb] - 1; hstr[h] = u[qb]; ++h;
+    } else {
+      hq[h] = -1; hoff[h] = 0; hstr[h] = 1; ++h;
+    }
+  }
+  int slots = 0;   // per half-slot
+  for (int i = 0; i < NHALF; ++i) {
+    m->q[i] = i < h ? hq[i] : -1;
+    m->off[i] = i < h ? hoff[i] : 0;
+    m->stride[i] = i < h ? hstr[i] : 1;
+    if (m->q[i] >= 0) {
+      const int r = ceil_div(wgs[m->q[i]] - m->off[i], m->stride[i]);
+      if (r > slots) slots = r;
+    }
+  }
+  return 8 * 2 * slots;
 }
 
-int grid_size(int n, int per) { return 8 % n == 0 ? 8 * ceil_div(n * per, 8) : n * per; }
+// Places a job table's jobs (by their workgroup counts) and returns the grid.
+template <typename Jobs>
+int map_jobs(Jobs& js) {
+  int wgs[MAXJ];
+  for (int q = 0; q < js.n; ++q) wgs[q] = js.j[q].wgs;
+  return build_xmap(wgs, js.n, &js.x);
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj_panel(GJJobs jobs, int nt) {
   __shared__ double2 Ps[TB][TB + 1];
   __shared__ double2 xrow[4][TB], xcol[4][TB];
   int q, w;
-  if (!job_of(jobs.n, jobs.j[0].wgs, &q, &w)) return;
-  int wg = q * jobs.j[0].wgs + w;
-  GJJob jb = pick(jobs, &wg);
-  panel_work<T>(jb, wg, nt, Ps, xrow, xcol);
+  if (!xjob(jobs.x, &q, &w)) return;
+  GJJob jb = pick(jobs, q);
+  if (w >= jb.wgs) return;
+  panel_work<T>(jb, w, nt, Ps, xrow, xcol);
 }
 
-// Update k (all tiles; negated when last) -- the final panel of a block.
+// Update k (all tiles; negated when last) -- the final panel of a block.  The
+// jobs may differ in tile count (the grid covers the largest).
 template <typename T>
-__global__ __launch_bounds__(256) void k_gj_update(GJJobs jobs, size_t tiles) {
+__global__ __launch_bounds__(256) void k_gj_update(GJJobs jobs) {
   int q, w;
-  if (!job_of(jobs.n, jobs.j[0].wgs, &q, &w)) return;
-  int wg = q * jobs.j[0].wgs + w;
-  GJJob jb = pick(jobs, &wg);
-  update_work<T>(jb, wg, tiles, -1);
+  if (!xjob(jobs.x, &q, &w)) return;
+  GJJob jb = pick(jobs, q);
+  if (w >= jb.wgs) return;
+  update_work<T>(jb, w, size_t(jb.tiles), -1);
 }
 
 // Update k outside column k+1, plus the look-ahead panel k+1 (R row tiles per
@@ -1212,9 +1302,9 @@ __global__ __launch_bounds__(256, 2) void k_gj_fused(GJJobs jobs, int nt, size_t
   __shared__ double2 xrow[4][TB], xcol[4][TB];
   const int look = jobs.j[0].wgs - jobs.j[0].wgs_upd;   // look-ahead workgroups per job
   int q, w;
-  if (!job_of(jobs.n, jobs.j[0].wgs, &q, &w)) return;
-  int tmp = q * jobs.j[0].wgs + w;
-  GJJob jb = pick(jobs, &tmp);
+  if (!xjob(jobs.x, &q, &w)) return;
+  GJJob jb = pick(jobs, q);
+  if (w >= jb.wgs) return;
   if (w < look)
     lookahead_work<T, R>(jb, w, nt, Ps, xrow, xcol);
   else
@@ -1224,57 +1314,62 @@ __global__ __launch_bounds__(256, 2) void k_gj_fused(GJJobs jobs, int nt, size_t
 // Panels k and k+1 applied to all tiles outside the look-ahead columns, plus
 // the pivot work of panels k+2 (and k+3): one workgroup per job, first.
 template <typename T>
-__global__ __launch_bounds__(256, 2) void k_gj2_fused(GJ2Jobs jobs, int nt, size_t tiles) {
+__global__ __launch_bounds__(256, 2) void k_gj2_fused(GJ2Jobs jobs) {
   __shared__ double2 B1[TB][TB + 1];
   __shared__ double2 B2[TB][TB + 1];
   __shared__ double2 B3[TB][TB + 1];
-  const int look = jobs.j[0].wgs - jobs.j[0].wgs_upd;
   int q, w;
-  if (!job_of(jobs.n, jobs.j[0].wgs, &q, &w)) return;
-  int tmp = q * jobs.j[0].wgs + w;
-  GJ2Job jb = pick2(jobs, &tmp);
-  if (w < look)
-    pivot2_work<T>(jb, nt, B1, B2, B3);
+  if (!xjob(jobs.x, &q, &w)) return;
+  const GJ2Job jb = pick2(jobs, q);
+  if (w >= jb.wgs) return;
+  if (w < jb.wgs - jb.wgs_upd)
+    pivot2_work<T>(jb, jb.nt, B1, B2, B3);
   else
-    update2_work<T>(jb, w - look, nt, tiles);
+    update2_work<T>(jb, w - (jb.wgs - jb.wgs_upd), jb.nt, size_t(jb.tiles));
 }
 
 // The row tiles of panels k+2 (and k+3) outside the pivot rows, one per
-// workgroup.
+// workgroup (jb.wgs = nt - nlook of them).
 template <typename T>
-__global__ __launch_bounds__(256) void k_gj2_rows(GJ2Jobs jobs, int nt) {
+__global__ __launch_bounds__(256) void k_gj2_rows(GJ2Jobs jobs) {
   __shared__ typename cplx<T>::t lt[2][TB][TB + 1];
   __shared__ typename cplx<T>::t xch[4][4][64];
   int q, w;
-  if (!job_of(jobs.n, jobs.j[0].wgs, &q, &w)) return;
-  int tmp = q * jobs.j[0].wgs + w;
-  GJ2Job jb = pick2(jobs, &tmp);
+  if (!xjob(jobs.x, &q, &w)) return;
+  const GJ2Job jb = pick2(jobs, q);
+  if (w >= jb.wgs) return;
   const int K3 = jb.k + 2;   // rows K3 (and K4) come from the pivot work
-  rows2_work<T>(jb, w < K3 ? w : w + jb.nlook, nt, lt, xch);
+  rows2_work<T>(jb, w < K3 ? w : w + jb.nlook, jb.nt, lt, xch);
 }
 
-// Panel tiles p0 .. p0 + np - 1 (slot p mod 4) of each job's L and Q buffers
+// The tiles of panel p (slot p mod 4) of each job's L and Q buffers
 // transposed in place, one tile per workgroup: the one-panel kernels write
-// row-major tiles, the two-panel passes read and write k-major ones.
+// row-major tiles, the two-panel passes read and write k-major ones.  The grid
+// has 2 * maxnt workgroups per job; jobs may differ in nt.
 struct PanelTr {
   void* L;
   void* Q;
+  int nt;
+  int p;
 };
 struct PanelTrs {
   PanelTr j[MAXJ];
   int n;
+  int maxnt;
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_panel_transpose(PanelTrs js, int nt, int p0, int np) {
+__global__ __launch_bounds__(256) void k_panel_transpose(PanelTrs js) {
   using T2 = typename cplx<T>::t;
   __shared__ T2 buf[TB][TB + 1];
-  const int per = 2 * np * nt;
+  const int per = 2 * js.maxnt;
   const int q = blockIdx.x / per;
   int r = blockIdx.x - q * per;
-  const int which = r / (np * nt);
-  r -= which * np * nt;
-  const int p = p0 + r / nt, I = r % nt;
+  const int which = r / js.maxnt;
+  const int I = r - which * js.maxnt;
+  const int nt = RCP_SEL16(js, q, nt);
+  if (I >= nt) return;
+  const int p = RCP_SEL16(js, q, p);
   void* const base = which ? RCP_SEL16(js, q, Q) : RCP_SEL16(js, q, L);
   T2* const t = slot_ptr<T2>(base, p, nt) + size_t(I) * TB * TB;
   for (int e = threadIdx.x; e < TB * TB; e += 256) buf[e / TB][e % TB] = t[e];
@@ -1292,10 +1387,13 @@ struct SchurJob {
   const double2* eco;   // coupling j -> j+1 (ny)
   const double2* c1;    // x-couplings (ny) or null
   const double2* c2;
+  int ny;               // block size of this job's geometry
+  int tiles;            // its packed tiles per block
 };
 struct SchurJobs {
   SchurJob j[MAXJ];
   int n;
+  int maxtiles;   // k_schur: workgroups per job
 };
 
 template <typename T>
@@ -1308,6 +1406,8 @@ __device__ __forceinline__ SchurJob schur_job_of(const SchurJobs& jobs, int ji) 
   jb.eco = RCP_SEL16(jobs, ji, eco);
   jb.c1 = RCP_SEL16(jobs, ji, c1);
   jb.c2 = RCP_SEL16(jobs, ji, c2);
+  jb.ny = RCP_SEL16(jobs, ji, ny);
+  jb.tiles = RCP_SEL16(jobs, ji, tiles);
   return jb;
 }
 
@@ -1316,8 +1416,9 @@ __device__ __forceinline__ SchurJob schur_job_of(const SchurJobs& jobs, int ji) 
 // it stores any, so that all of its loads are in flight together (a store
 // might alias a later load otherwise).
 template <typename T, int NTL>
-__device__ __forceinline__ void schur_tiles(const SchurJob& jb, int ny, size_t t0, size_t tiles) {
+__device__ __forceinline__ void schur_tiles(const SchurJob& jb, size_t t0, size_t tiles) {
   using T2 = typename cplx<T>::t;
+  const int ny = jb.ny;
   constexpr int EPT = TB * TB / 256;
   double2 v[NTL][EPT];
 #pragma unroll
@@ -1358,10 +1459,11 @@ __device__ __forceinline__ void schur_tiles(const SchurJob& jb, int ny, size_t t
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_schur(SchurJobs jobs, int ny, size_t tiles) {
-  const size_t t = blockIdx.x % tiles;
-  const int ji = static_cast<int>(blockIdx.x / tiles);
-  schur_tiles<T, 1>(schur_job_of<T>(jobs, ji), ny, t, tiles);
+__global__ __launch_bounds__(256) void k_schur(SchurJobs jobs) {
+  const size_t t = blockIdx.x % jobs.maxtiles;
+  const int ji = static_cast<int>(blockIdx.x / jobs.maxtiles);
+  const SchurJob jb = schur_job_of<T>(jobs, ji);
+  schur_tiles<T, 1>(jb, t, size_t(jb.tiles));
 }
 
 // The Schur complements that start the next blocks of a two-panel sweep, and
@@ -1373,22 +1475,51 @@ __global__ __launch_bounds__(256) void k_schur(SchurJobs jobs, int ny, size_t ti
 // the same block; gj.j[q].wgs = 1 + ceil((tiles - 3) / OPEN_TILES).
 constexpr int OPEN_TILES = 2;
 template <typename T>
-__global__ __launch_bounds__(256, 2) void k_gj2_open(GJ2Jobs gj, SchurJobs sj, int ny, int nt,
-                                                     size_t tiles) {
+__device__ __forceinline__ void open_work(const GJ2Jobs& gj, const SchurJobs& sj, int q, int w,
+                                          double2 (*B1)[TB + 1], double2 (*B2)[TB + 1],
+                                          double2 (*B3)[TB + 1]) {
+  const SchurJob sjob = schur_job_of<T>(sj, q);
+  if (w == 0) {
+    schur_tiles<T, 3>(sjob, 0, 3);
+    __syncthreads();   // the tiles are read back by every wave of this workgroup
+    const GJ2Job jb = pick2(gj, q);
+    pivot2_work<T>(jb, jb.nt, B1, B2, B3);
+  } else {
+    schur_tiles<T, OPEN_TILES>(sjob, 3 + size_t(w - 1) * OPEN_TILES, size_t(sjob.tiles));
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_gj2_open(GJ2Jobs gj, SchurJobs sj) {
   __shared__ double2 B1[TB][TB + 1];
   __shared__ double2 B2[TB][TB + 1];
   __shared__ double2 B3[TB][TB + 1];
   int q, w;
-  if (!job_of(gj.n, gj.j[0].wgs, &q, &w)) return;
-  const SchurJob sjob = schur_job_of<T>(sj, q);
-  if (w == 0) {
-    schur_tiles<T, 3>(sjob, ny, 0, 3);
-    __syncthreads();   // the tiles are read back by every wave of this workgroup
-    int tmp = q * gj.j[0].wgs;
-    const GJ2Job jb = pick2(gj, &tmp);
-    pivot2_work<T>(jb, nt, B1, B2, B3);
+  if (!xjob(gj.x, &q, &w)) return;
+  if (w >= RCP_SEL16(gj, q, wgs)) return;
+  open_work<T>(gj, sj, q, w, B1, B2, B3);
+}
+
+// One step of every chain of a mixed launch (chains of different geometries,
+// each at its own place in its own sweep): a job either opens its block
+// (jb.open: the Schur complement beside the pivot work of panels 0 and 1, as
+// k_gj2_open) or applies its next pair of panels with the pivot work of the
+// pair after (as k_gj2_fused).
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_gj2_step(GJ2Jobs gj, SchurJobs sj) {
+  __shared__ double2 B1[TB][TB + 1];
+  __shared__ double2 B2[TB][TB + 1];
+  __shared__ double2 B3[TB][TB + 1];
+  int q, w;
+  if (!xjob(gj.x, &q, &w)) return;
+  const GJ2Job jb = pick2(gj, q);
+  if (w >= jb.wgs) return;
+  if (jb.open) {
+    open_work<T>(gj, sj, q, w, B1, B2, B3);
+  } else if (w < jb.wgs - jb.wgs_upd) {
+    pivot2_work<T>(jb, jb.nt, B1, B2, B3);
   } else {
-    schur_tiles<T, OPEN_TILES>(sjob, ny, 3 + size_t(w - 1) * OPEN_TILES, tiles);
+    update2_work<T>(jb, w - (jb.wgs - jb.wgs_upd), jb.nt, size_t(jb.tiles));
   }
 }
 
@@ -1419,8 +1550,13 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
     int nsrc = 0;
     for (int q = 0; q < js.n; ++q) nsrc += 1 + (js.j[q].src1 != nullptr) + (js.j[q].src2 != nullptr);
     KTimer kt(K_SCHUR, s, double(nsrc) * tiles * TB * TB * f0->elem_bytes);
+    for (int q = 0; q < js.n; ++q) {
+      js.j[q].ny = ny;
+      js.j[q].tiles = static_cast<int>(tiles);
+    }
+    js.maxtiles = static_cast<int>(tiles);
     if (!pairs || nt < 2) {
-      k_schur<T><<<static_cast<int>(tiles * js.n), 256, 0, s>>>(js, ny, tiles);
+      k_schur<T><<<static_cast<int>(tiles * js.n), 256, 0, s>>>(js);
       RCP_HIP(hipGetLastError());
       return RCP_OK;
     }
@@ -1438,10 +1574,13 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
       b.Qb = f->wsQ[4 * ch[q].c];
       b.Pb = f->wsP[4 * ch[q].c];
       b.health = f->health + size_t(ch[q].block) * nt;
+      b.nt = nt;
+      b.tiles = static_cast<int>(tiles);
+      b.open = 1;
       gj.j[gj.n++] = b;
       opened[q] = ch[q];
     }
-    k_gj2_open<T><<<grid_size(gj.n, per), 256, 0, s>>>(gj, js, ny, nt, tiles);
+    k_gj2_open<T><<<map_jobs(gj), 256, 0, s>>>(gj, js);
     RCP_HIP(hipGetLastError());
     nopened = js.n;
     return RCP_OK;
@@ -1470,6 +1609,7 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
       b.Qn = f->wsQ[nxt];
       b.Pn = f->wsP[nxt];
       b.health = f->health + size_t(x.block) * nt + (k + 1 < nt ? k + 1 : k);
+      b.tiles = static_cast<int>(tiles);
       return b;
     };
     if (!pairs || nt < 2) {   // panel 0 (the "next" slot of k = -1, i.e. slot 0)
@@ -1482,7 +1622,7 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
         js.j[js.n++] = b;
       }
       KTimer kt(K_GJ_PANEL, s, nch * cmac * nt);
-      k_gj_panel<T><<<grid_size(nch, pan_wgs), 256, 0, s>>>(js, nt);
+      k_gj_panel<T><<<map_jobs(js), 256, 0, s>>>(js, nt);
       RCP_HIP(hipGetLastError());
     }
     if (!pairs) {
@@ -1500,7 +1640,7 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
           js.j[js.n++] = b;
         }
         KTimer kt(K_GJ_UPDATE, s, nch * cmac * double(tiles));
-        const int grid = grid_size(nch, upd_wgs + look_wgs);
+        const int grid = map_jobs(js);
         if (R == 1)
           k_gj_fused<T, 1><<<grid, 256, 0, s>>>(js, nt, tiles);
         else
@@ -1516,13 +1656,14 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
         js.j[js.n++] = b;
       }
       KTimer kt(K_GJ_LAST, s, nch * cmac * double(tiles - nt));
-      k_gj_update<T><<<grid_size(nch, upd_wgs), 256, 0, s>>>(js, tiles);
+      k_gj_update<T><<<map_jobs(js), 256, 0, s>>>(js);
       RCP_HIP(hipGetLastError());
       return RCP_OK;
     }
     PanelTrs tr{};
     for (int q = 0; q < nch; ++q)
-      tr.j[tr.n++] = PanelTr{fs[ch[q].g]->wsL[4 * ch[q].c], fs[ch[q].g]->wsQ[4 * ch[q].c]};
+      tr.j[tr.n++] = PanelTr{fs[ch[q].g]->wsL[4 * ch[q].c], fs[ch[q].g]->wsQ[4 * ch[q].c], nt, nt - 1};
+    tr.maxnt = nt;
     // pairs (K, K+1); the look-ahead forms the next pair (or the last panel).
     // K = -2 opens the block: no panels to apply, only the pivot work and row
     // tiles of panels 0 and 1 on the untouched tiles
@@ -1545,12 +1686,14 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
         b.Qb = f->wsQ[4 * ch[q].c];
         b.Pb = f->wsP[4 * ch[q].c];
         b.health = f->health + size_t(ch[q].block) * nt;
+        b.nt = nt;
+        b.tiles = static_cast<int>(tiles);
         js.j[js.n++] = b;
       }
       if (K >= 0 || !open_done) {
         KTimer kt(K < 0 ? K_GJ_PANEL : (last ? K_GJ_LAST : K_GJ_UPDATE), s,
                   K < 0 ? nch * 6.0 * cmac : nch * 2.0 * cmac * double(tiles));
-        k_gj2_fused<T><<<grid_size(nch, upd + look_wgs), 256, 0, s>>>(js, nt, tiles);
+        k_gj2_fused<T><<<map_jobs(js), 256, 0, s>>>(js);
         RCP_HIP(hipGetLastError());
       }
       // row tiles of the next pair's panels; the pivot rows come from the
@@ -1559,13 +1702,13 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
       if (nlook > 0 && rows > 0) {
         for (int q = 0; q < js.n; ++q) js.j[q].wgs = rows;
         KTimer kt(K_GJ_PANEL, s, nch * cmac * nlook * rows);
-        k_gj2_rows<T><<<grid_size(nch, rows), 256, 0, s>>>(js, nt);
+        k_gj2_rows<T><<<map_jobs(js), 256, 0, s>>>(js);
         RCP_HIP(hipGetLastError());
       }
     }
     if (nt & 1) {   // odd panel count: the last panel alone, negated
       if (nt >= 3) {   // formed by the last pass: back to row-major
-        k_panel_transpose<T><<<nch * 2 * 1 * nt, 256, 0, s>>>(tr, nt, nt - 1, 1);
+        k_panel_transpose<T><<<nch * 2 * nt, 256, 0, s>>>(tr);
         RCP_HIP(hipGetLastError());
       }
       GJJobs js{};
@@ -1577,7 +1720,7 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
         js.j[js.n++] = b;
       }
       KTimer kt(K_GJ_LAST, s, nch * cmac * double(tiles - nt));
-      k_gj_update<T><<<grid_size(nch, upd_wgs), 256, 0, s>>>(js, tiles);
+      k_gj_update<T><<<map_jobs(js), 256, 0, s>>>(js);
       RCP_HIP(hipGetLastError());
     }
     return RCP_OK;
@@ -1589,12 +1732,13 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
     for (int g = 0; g < B; ++g) {
       if (lenL > 0) {
         nxt[js.n] = Chain{g, 0, 0};
-        js.j[js.n++] = SchurJob{block_ptr(fs[g], 0), nullptr, nullptr, D(g, 0), E(g, 0), nullptr, nullptr};
+        js.j[js.n++] = SchurJob{block_ptr(fs[g], 0), nullptr, nullptr, D(g, 0), E(g, 0), nullptr, nullptr,
+                                ny, static_cast<int>(tiles)};
       }
       if (lenR > 0) {
         nxt[js.n] = Chain{g, 1, N - 1};
         js.j[js.n++] = SchurJob{block_ptr(fs[g], N - 1), nullptr, nullptr, D(g, N - 1), E(g, N - 1),
-                                nullptr, nullptr};
+                                nullptr, nullptr, ny, static_cast<int>(tiles)};
       }
     }
     int rc = schur(js, nxt);
@@ -1617,12 +1761,14 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
       if (bL >= 0 && bL + 1 < m) {
         nxt[js.n] = Chain{g, 0, bL + 1};
         js.j[js.n++] = SchurJob{block_ptr(fs[g], bL + 1), block_ptr(fs[g], bL), nullptr,
-                                D(g, bL + 1), E(g, bL + 1), C(g, bL), nullptr};
+                                D(g, bL + 1), E(g, bL + 1), C(g, bL), nullptr, ny,
+                                static_cast<int>(tiles)};
       }
       if (bR >= 0 && bR - 1 > m) {
         nxt[js.n] = Chain{g, 1, bR - 1};
         js.j[js.n++] = SchurJob{block_ptr(fs[g], bR - 1), block_ptr(fs[g], bR), nullptr,
-                                D(g, bR - 1), E(g, bR - 1), C(g, bR - 1), nullptr};
+                                D(g, bR - 1), E(g, bR - 1), C(g, bR - 1), nullptr, ny,
+                                static_cast<int>(tiles)};
       }
     }
     rc = schur(js, nxt);
@@ -1633,7 +1779,8 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
     Chain ch[MAXJ];
     int nch = 0;
     for (int g = 0; g < B; ++g) {
-      SchurJob z{block_ptr(fs[g], m), nullptr, nullptr, D(g, m), E(g, m), nullptr, nullptr};
+      SchurJob z{block_ptr(fs[g], m), nullptr, nullptr, D(g, m), E(g, m), nullptr, nullptr, ny,
+                 static_cast<int>(tiles)};
       if (m - 1 >= 0) {
         z.src1 = block_ptr(fs[g], m - 1);
         z.c1 = C(g, m - 1);
@@ -1653,9 +1800,285 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
   return RCP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Factorisation engine: geometries of any size share launches.  Each chain
+// (left, right, then the middle block) advances one step per round: a round
+// is one k_gj2_step launch (every chain opens its next block or applies its
+// next pair of panels), the row tiles of the panels it formed, and for chains
+// that end a block with an odd panel the transpose and final update.  A new
+// geometry joins at the next round; a finished one leaves.  Every chain does
+// exactly what the batched two-panel sweep does to it, so the factors of a
+// geometry are the same bits whatever else shares the launches.
+struct EChain {
+  int g;       // geometry slot
+  int c;       // panel buffers of chain c (0: left and middle, 1: right)
+  int dir;     // +1 left, -1 right, 0 middle
+  int block;
+  int K;       // next pass; -2 opens the block
+};
+
+struct EGeom {
+  rcp_factors* f = nullptr;
+  int chains_left = 0;   // side chains still running (0..2); then the middle block
+  bool middle = false;
+};
+
+constexpr int kOpenTilesPerWg = OPEN_TILES;
+
+template <typename T>
+int engine_round(std::vector<EGeom>& geoms, std::vector<EChain>& chains, hipStream_t s,
+                 std::vector<int>* finished) {
+  const int nch = static_cast<int>(chains.size());
+  if (nch == 0) return RCP_OK;
+  if (nch > MAXJ) return fail(RCP_EINVAL, "internal: too many chains in a round");
+  const double cmac = 8.0 * TB * TB * TB;
+  GJ2Jobs gj{};
+  SchurJobs sj{};
+  int nlook_of[MAXJ];
+  double work = 0.0;
+  for (int q = 0; q < nch; ++q) {
+    const EChain& x = chains[q];
+    const rcp_factors* f = geoms[x.g].f;
+    const int nt = f->nt, N = f->nx, ny = f->ny;
+    const int tiles = static_cast<int>(f->tiles);
+    GJ2Job b{};
+    b.k = x.K;
+    b.nt = nt;
+    b.tiles = tiles;
+    b.X = block_ptr(f, x.block);
+    b.Lb = f->wsL[4 * x.c];
+    b.Qb = f->wsQ[4 * x.c];
+    b.Pb = f->wsP[4 * x.c];
+    b.health = f->health + size_t(x.block) * nt;
+    SchurJob z{};
+    z.dst = b.X;
+    z.ny = ny;
+    z.tiles = tiles;
+    if (x.K == -2) {   // open: Schur complement of this block + pivot work of panels 0, 1
+      b.open = 1;
+      b.nlook = 2;
+      b.wgs = 1 + ceil_div(tiles - 3, kOpenTilesPerWg);
+      z.dco = f->dco + size_t(x.block) * ny;
+      z.eco = f->eco + size_t(x.block) * ny;
+      if (x.dir > 0 && x.block > 0) {
+        z.src1 = block_ptr(f, x.block - 1);
+        z.c1 = f->cco + size_t(x.block - 1) * ny;
+      } else if (x.dir < 0 && x.block < N - 1) {
+        z.src1 = block_ptr(f, x.block + 1);
+        z.c1 = f->cco + size_t(x.block) * ny;
+      } else if (x.dir == 0) {
+        if (x.block - 1 >= 0) {
+          z.src1 = block_ptr(f, x.block - 1);
+          z.c1 = f->cco + size_t(x.block - 1) * ny;
+        }
+        if (x.block + 1 < N) {
+          z.src2 = block_ptr(f, x.block + 1);
+          z.c2 = f->cco + size_t(x.block) * ny;
+        }
+      }
+      work += 6.0 * cmac;
+    } else {
+      b.nlook = nt - (x.K + 2) >= 2 ? 2 : nt - (x.K + 2);
+      b.last = b.nlook == 0 ? 1 : 0;
+      b.wgs_upd = ceil_div(tiles, 4);
+      b.wgs = b.wgs_upd + (b.nlook > 0 ? 1 : 0);
+      work += 2.0 * cmac * tiles;
+    }
+    nlook_of[q] = b.nlook;
+    gj.j[gj.n++] = b;
+    sj.j[sj.n++] = z;
+  }
+  {
+    KTimer kt(K_ENGINE, s, work);
+    k_gj2_step<T><<<map_jobs(gj), 256, 0, s>>>(gj, sj);
+    RCP_HIP(hipGetLastError());
+  }
+  // row tiles of the panels the step formed (outside its pivot rows)
+  {
+    GJ2Jobs rj{};
+    double rw = 0.0;
+    for (int q = 0; q < nch; ++q) {
+      const int rows = gj.j[q].nt - nlook_of[q];
+      if (nlook_of[q] > 0 && rows > 0) {
+        GJ2Job b = gj.j[q];
+        b.open = 0;
+        b.wgs = rows;
+        rj.j[rj.n++] = b;
+        rw += cmac * nlook_of[q] * rows;
+      }
+    }
+    if (rj.n > 0) {
+      KTimer kt(K_ENGINE, s, rw);
+      k_gj2_rows<T><<<map_jobs(rj), 256, 0, s>>>(rj);
+      RCP_HIP(hipGetLastError());
+    }
+  }
+  // odd panel counts: the last panel alone, negated, after its rows
+  {
+    PanelTrs tr{};
+    GJJobs uj{};
+    double uw = 0.0;
+    for (int q = 0; q < nch; ++q) {
+      if (gj.j[q].open || nlook_of[q] != 1) continue;
+      const EChain& x = chains[q];
+      const rcp_factors* f = geoms[x.g].f;
+      const int nt = f->nt, k = nt - 1;
+      tr.j[tr.n++] = PanelTr{f->wsL[4 * x.c], f->wsQ[4 * x.c], nt, k};
+      if (nt > tr.maxnt) tr.maxnt = nt;
+      GJJob b{};
+      b.k = k;
+      b.last = 1;
+      b.X = block_ptr(f, x.block);
+      const int cur = 4 * x.c + (k & 3), nxt = 4 * x.c + ((k + 1) & 3);
+      b.L = f->wsL[cur];
+      b.Q = f->wsQ[cur];
+      b.P = f->wsP[cur];
+      b.Ln = f->wsL[nxt];
+      b.Qn = f->wsQ[nxt];
+      b.Pn = f->wsP[nxt];
+      b.health = f->health + size_t(x.block) * nt + k;
+      b.tiles = static_cast<int>(f->tiles);
+      b.wgs = ceil_div(b.tiles, 4);
+      b.wgs_upd = b.wgs;
+      uj.j[uj.n++] = b;
+      uw += cmac * double(f->tiles - nt);
+    }
+    if (uj.n > 0) {
+      k_panel_transpose<T><<<uj.n * 2 * tr.maxnt, 256, 0, s>>>(tr);
+      RCP_HIP(hipGetLastError());
+      KTimer kt(K_ENGINE, s, uw);
+      k_gj_update<T><<<map_jobs(uj), 256, 0, s>>>(uj);
+      RCP_HIP(hipGetLastError());
+    }
+  }
+  // advance
+  std::vector<EChain> next;
+  next.reserve(chains.size() + 2);
+  for (int q = 0; q < nch; ++q) {
+    EChain x = chains[q];
+    const GJ2Job& b = gj.j[q];
+    const bool block_done = !b.open && (b.last || nlook_of[q] == 1);
+    if (!block_done) {
+      x.K = b.open ? 0 : x.K + 2;
+      next.push_back(x);
+      continue;
+    }
+    EGeom& G = geoms[x.g];
+    const rcp_factors* f = G.f;
+    if (x.dir == 0) {   // middle block done: the geometry is factored
+      finished->push_back(x.g);
+      continue;
+    }
+    const int nb = x.block + x.dir;
+    const bool more = x.dir > 0 ? nb < f->m : nb > f->m;
+    if (more) {
+      x.block = nb;
+      x.K = -2;
+      next.push_back(x);
+      continue;
+    }
+    if (--G.chains_left == 0) {
+      G.middle = true;
+      next.push_back(EChain{x.g, 0, 0, f->m, -2});
+    }
+  }
+  chains.swap(next);
+  return RCP_OK;
+}
+
 }  // namespace
 
+struct rcp_engine {
+  int precision = 0;
+  std::vector<EGeom> geoms;     // slots; f == nullptr when free
+  std::vector<EChain> chains;
+  int active = 0;
+};
+
 namespace rcp {
+
+int engine_create(int precision, rcp_engine** out) {
+  rcp_engine* e = new (std::nothrow) rcp_engine();
+  if (!e) return fail(RCP_ENOMEM, "host allocation failed");
+  e->precision = precision;
+  e->geoms.resize(MAX_BATCH);
+  *out = e;
+  return RCP_OK;
+}
+
+void engine_destroy(rcp_engine* e) { delete e; }
+
+int engine_active(const rcp_engine* e) { return e->active; }
+
+int engine_precision(const rcp_engine* e) { return e->precision; }
+
+int engine_add(rcp_engine* e, rcp_factors* f) {
+  if (f->precision != e->precision) return fail(RCP_EINVAL, "precision differs from the engine's");
+  if (f->nt < 2) return fail(RCP_EINVAL, "the engine needs blocks of more than 32 rows");
+  int slot = -1;
+  for (int g = 0; g < MAX_BATCH; ++g)
+    if (!e->geoms[g].f) {
+      slot = g;
+      break;
+    }
+  if (slot < 0) return fail(RCP_EINVAL, "engine full: 8 geometries in flight");
+  EGeom& G = e->geoms[slot];
+  G.f = f;
+  G.middle = false;
+  G.chains_left = 0;
+  const int N = f->nx, m = f->m;
+  if (m > 0) {   // left chain: blocks 0 .. m-1
+    e->chains.push_back(EChain{slot, 0, +1, 0, -2});
+    ++G.chains_left;
+  }
+  if (N - 1 - m > 0) {   // right chain: blocks N-1 .. m+1
+    e->chains.push_back(EChain{slot, 1, -1, N - 1, -2});
+    ++G.chains_left;
+  }
+  if (G.chains_left == 0) {
+    G.middle = true;
+    e->chains.push_back(EChain{slot, 0, 0, m, -2});
+  }
+  ++e->active;
+  return RCP_OK;
+}
+
+// Health of a finished geometry: the smallest pivot modulus of every panel.
+static int check_health(const rcp_factors* f, hipStream_t s) {
+  const size_t nh = size_t(f->nx) * f->nt;
+  std::vector<double> h(nh);
+  RCP_HIP(hipMemcpyAsync(h.data(), f->health, nh * sizeof(double), hipMemcpyDeviceToHost, s));
+  RCP_HIP(hipStreamSynchronize(s));
+  const double tiny = 1e-13 * 4.0 / (f->h * f->h);
+  for (size_t q = 0; q < nh; ++q)
+    if (!(h[q] > tiny) || !std::isfinite(h[q]))
+      return fail(RCP_ESINGULAR, "pivot block " + std::to_string(q % f->nt) + " of column block " +
+                                     std::to_string(q / f->nt) + " has pivot modulus " +
+                                     std::to_string(h[q]));
+  return RCP_OK;
+}
+
+int engine_step(rcp_engine* e, int rounds, hipStream_t s, rcp_factors** done, int* status,
+                int cap, int* ndone) {
+  *ndone = 0;
+  std::vector<int> fin;
+  for (int r = 0; r < rounds && !e->chains.empty() && fin.empty(); ++r) {
+    int rc = e->precision == RCP_FP64 ? engine_round<double>(e->geoms, e->chains, s, &fin)
+                                      : engine_round<float>(e->geoms, e->chains, s, &fin);
+    if (rc) return rc;
+  }
+  for (int g : fin) {
+    rcp_factors* f = e->geoms[g].f;
+    e->geoms[g].f = nullptr;
+    --e->active;
+    if (*ndone < cap) {
+      done[*ndone] = f;
+      status[*ndone] = check_health(f, s);
+      ++*ndone;
+    }
+  }
+  return RCP_OK;
+}
 
 int factor_blocks(rcp_factors* const* fs, int B, hipStream_t s) {
   if (B < 1 || B > MAXJ / 2) return fail(RCP_EINVAL, "batch of 1 to 8 geometries");

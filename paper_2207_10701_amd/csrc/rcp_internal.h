@@ -99,7 +99,8 @@ enum KClass {
   K_GEMM = 4,
   K_GJ_LAST = 5,
   K_ZGEMM = 6,
-  K_NCLASS = 7
+  K_ENGINE = 7,   // launches of the factorisation engine (mixed geometries)
+  K_NCLASS = 8
 };
 void ktimer_begin(int cls, hipStream_t s, double work, void** token);
 void ktimer_end(void* token, hipStream_t s);
@@ -131,6 +132,15 @@ int launch_width_grad(const rcp_grid* g, const rcp_pillars* p, const double* gra
 // factor.hip
 // Factor B (1..MAX_BATCH) geometries of identical shape in the same launches.
 int factor_blocks(rcp_factors* const* fs, int B, hipStream_t s);
+// The factorisation engine (geometries of any size in shared launches, admitted
+// between rounds); see include/recip.h.
+int engine_create(int precision, rcp_engine** out);
+void engine_destroy(rcp_engine* e);
+int engine_active(const rcp_engine* e);
+int engine_precision(const rcp_engine* e);
+int engine_add(rcp_engine* e, rcp_factors* f);
+int engine_step(rcp_engine* e, int rounds, hipStream_t s, rcp_factors** done, int* status,
+                int cap, int* ndone);
 
 // solve.hip
 // u = A^{-1} f (conjop = 0) or conj(A)^{-1} f = A^{-dag} f (conjop = 1), one

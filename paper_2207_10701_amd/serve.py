@@ -1,29 +1,39 @@
 """Continuous-batching server for angle-averaged metasurface evaluations.
 
 Requests (a geometry, an objective, a light distribution, optionally a
-gradient) arrive over time.  The server keeps up to ``slots`` requests in
-flight, each on its own HIP stream driven by its own host thread, so their
-kernels overlap on the device.  A request is admitted when a slot is free and
-the device memory its factors need (``rcp_factor_bytes``) fits in the budget;
-factors of finished requests stay cached (keyed by geometry) until their
-memory is needed, so repeated geometries skip the factorisation.  When a
-request starts on cached factors, the requests for the same geometry that
-have already arrived (plain evaluations, up to ``group``) go with it: one
-multi-right-hand-side reciprocal sweep serves all of them.  Admission is
-first come, first served among requests that need memory for new factors; a request
-whose cached geometry is busy waits on it without holding back others.
-Latency is measured from arrival to result.
+gradient) arrive over time.  Their work has two parts:
+
+* factorisation of a geometry not in the cache: one host thread drives the
+  factorisation engine (``rcp_engine_*``), in which every geometry in flight
+  (up to ``factor_slots``, at most 8) advances one pass per round of shared
+  kernel launches, whatever its grid size; a geometry admitted while others
+  are in progress joins at the next round (continuous batching at the level of
+  the factorisation passes);
+* evaluation on factors that are ready: up to ``eval_slots`` evaluations run
+  at once, each on its own HIP stream, beside the engine's stream.  Plain
+  requests for the same geometry that are waiting go together (up to
+  ``group``): one multi-right-hand-side reciprocal sweep serves them all.
+
+A fresh geometry is admitted when the device memory its factors need
+(``rcp_factor_bytes``) fits in the budget (idle cached factors are evicted,
+least recently used first); a grouped evaluation's workspace counts against
+the same budget.  Requests that need new factors are admitted first come,
+first served; a request whose geometry is cached but busy (being factored or
+evaluated) waits on it without holding back others.  Factors stay cached
+(keyed by geometry) until their memory is needed.  Latency is measured from
+arrival to result.
 
 The device work goes through an executor: ``GpuExecutor`` calls librecip;
 ``FakeExecutor`` models costs and memory on the host so the scheduling logic
-can be tested without a GPU.
+can be tested without a GPU.  ``serve_sequential`` is the baseline: one
+request at a time, factored alone and evaluated, nothing cached.
 """
 from __future__ import annotations
 
 import math
 import threading
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 from typing import Any, Callable, Dict, List, Optional
 
 from workloads import Problem, Request
@@ -62,15 +72,17 @@ class ServerError(RuntimeError):
 
 
 class GpuExecutor:
-    """Runs a request on one HIP stream through librecip."""
+    """librecip on one GPU: the factorisation engine on its own stream, the
+    evaluations on the streams of the evaluation slots."""
 
-    def __init__(self, precision: int = 0, device: str = "cuda"):
+    def __init__(self, precision: int = 0, device: str = "cuda", ahead: int = 2):
         import torch
         import paper_2207_10701_amd as rcp
         self.torch = torch
         self.rcp = rcp
         self.precision = precision
         self.device = torch.device(device)
+        self.ahead = ahead           # engine steps enqueued ahead of the GPU
 
     def new_stream(self):
         return self.torch.cuda.Stream(device=self.device)
@@ -78,7 +90,39 @@ class GpuExecutor:
     def factor_bytes(self, p: Problem) -> int:
         return self.rcp.factor_bytes(p, self.precision)
 
+    # -- factorisation engine (one host thread) --
+    def new_engine(self):
+        eng = self.rcp.FactorEngine(self.precision, stream=self.new_stream())
+        eng._marks = []
+        return eng
+
+    def engine_add(self, eng, p: Problem):
+        torch, rcp = self.torch, self.rcp
+        with torch.cuda.stream(eng.stream):
+            widths = torch.tensor(p.widths, dtype=torch.float64, device=self.device)
+            eps = rcp.eps_from_widths(p, widths, device=self.device, stream=eng.stream)
+            return eng.add(p, eps)
+
+    def engine_step(self, eng, rounds: int):
+        """Enqueue up to `rounds` rounds; keep at most `ahead` steps queued on the
+        GPU, so that a geometry admitted now joins within a few rounds."""
+        done = eng.step(rounds)
+        ev = self.torch.cuda.Event()
+        ev.record(eng.stream)
+        eng._marks.append(ev)
+        if len(eng._marks) > self.ahead:
+            eng._marks.pop(0).synchronize()
+        return [(fac, None if err is None else str(err)) for fac, err in done]
+
+    def engine_size(self, eng) -> int:
+        return len(eng)
+
+    def engine_close(self, eng) -> None:
+        eng.close()
+
+    # -- evaluations --
     def factor(self, p: Problem, stream) -> Any:
+        """One geometry factored alone (the sequential baseline)."""
         torch, rcp = self.torch, self.rcp
         with torch.cuda.stream(stream):
             widths = torch.tensor(p.widths, dtype=torch.float64, device=self.device)
@@ -115,18 +159,28 @@ class GpuExecutor:
         fac.buf = None
 
 
+class _FakeEngine:
+    def __init__(self):
+        self.items: List[list] = []      # [fac, rounds left]
+
+
 class FakeExecutor:
-    """Host-only stand-in: modelled durations and memory, deterministic results."""
+    """Host-only stand-in: modelled durations and memory, deterministic results.
+    The engine model: a geometry needs factor_rounds(p) rounds; a round costs
+    round_seconds whatever shares it (the kernels' launches are shared)."""
 
     def __init__(self, factor_seconds: Callable[[Problem], float] = lambda p: 0.002,
                  eval_seconds: float = 0.0005, bytes_per_cell: int = 1000,
-                 fail_on: Optional[Callable[[Problem], bool]] = None):
+                 fail_on: Optional[Callable[[Problem], bool]] = None,
+                 round_seconds: float = 0.0005):
         self.factor_seconds = factor_seconds
         self.eval_seconds = eval_seconds
         self.bytes_per_cell = bytes_per_cell
         self.fail_on = fail_on
+        self.round_seconds = round_seconds
         self.factor_calls = 0
         self.group_sizes: List[int] = []
+        self.round_sizes: List[int] = []     # geometries sharing each engine round
         self.live = 0
         self.peak_live = 0
         self.lock = threading.Lock()
@@ -137,15 +191,51 @@ class FakeExecutor:
     def factor_bytes(self, p: Problem) -> int:
         return p.nx * p.ny * self.bytes_per_cell
 
-    def factor(self, p: Problem, stream):
-        if self.fail_on is not None and self.fail_on(p):
-            raise ServerError(f"RCP_ESINGULAR: modelled failure for {p.name}")
-        time.sleep(self.factor_seconds(p))
+    def _made(self, p: Problem):
         with self.lock:
             self.factor_calls += 1
             self.live += self.factor_bytes(p)
             self.peak_live = max(self.peak_live, self.live)
         return {"p": p, "bytes": self.factor_bytes(p)}
+
+    def new_engine(self):
+        return _FakeEngine()
+
+    def engine_add(self, eng, p: Problem):
+        fac = self._made(p)
+        rounds = max(1, int(round(self.factor_seconds(p) / self.round_seconds)))
+        eng.items.append([fac, rounds])
+        return fac
+
+    def engine_step(self, eng, rounds: int):
+        done = []
+        for _ in range(rounds):
+            if not eng.items or done:
+                break
+            time.sleep(self.round_seconds)
+            self.round_sizes.append(len(eng.items))
+            for it in eng.items:
+                it[1] -= 1
+            for it in [it for it in eng.items if it[1] <= 0]:
+                eng.items.remove(it)
+                p = it[0]["p"]
+                bad = self.fail_on is not None and self.fail_on(p)
+                done.append((it[0], f"RCP_ESINGULAR: modelled failure for {p.name}" if bad else None))
+        return done
+
+    def engine_size(self, eng) -> int:
+        return len(eng.items)
+
+    def engine_close(self, eng) -> None:
+        for it in eng.items:
+            self.release(it[0])
+        eng.items.clear()
+
+    def factor(self, p: Problem, stream):
+        if self.fail_on is not None and self.fail_on(p):
+            raise ServerError(f"RCP_ESINGULAR: modelled failure for {p.name}")
+        time.sleep(self.factor_seconds(p))
+        return self._made(p)
 
     def evaluate(self, fac, p: Problem, adjoint: bool, stream):
         time.sleep(self.eval_seconds)
@@ -174,36 +264,50 @@ class FakeExecutor:
 @dataclass
 class _Entry:
     key: Any
-    fac: Any
+    p: Problem
     nbytes: int
-    users: int = 0
+    fac: Any = None
+    users: int = 0               # evaluations running on it (one at a time)
     last_used: float = 0.0
-    ready: bool = False          # False while the first request is still factoring
+    ready: bool = False          # factors complete
+    error: Optional[str] = None  # factorisation failed
 
 
 class Server:
-    """Continuous batching with memory-ledger admission and a factor cache."""
+    """Continuous batching: the factorisation engine plus evaluation slots,
+    memory-ledger admission and a factor cache."""
 
-    def __init__(self, executor, slots: int = 4, hbm_budget: int = 200 << 30,
-                 cache: bool = True, group: int = 16):
-        if slots < 1:
-            raise ValueError("slots must be >= 1")
+    def __init__(self, executor, factor_slots: int = 8, eval_slots: int = 4,
+                 hbm_budget: int = 200 << 30, cache: bool = True, group: int = 16,
+                 rounds_per_step: int = 4):
+        if not 1 <= factor_slots <= 8:
+            raise ValueError("factor_slots must be 1 to 8")
+        if eval_slots < 1:
+            raise ValueError("eval_slots must be >= 1")
         if not 1 <= group <= 64:
             raise ValueError("group must be 1 to 64")
-        self.group = group
         self.ex = executor
-        self.nslots = slots
+        self.factor_slots = factor_slots
+        self.group = group
         self.budget = int(hbm_budget)
         self.cache_enabled = cache
+        self.rounds = rounds_per_step
         self.cache: Dict[Any, _Entry] = {}
-        self.used = 0                       # bytes of factors held (cached, in use, being made)
+        self.used = 0                       # bytes of factors held + group workspaces
         self.cv = threading.Condition()
-        self.free_slots = list(range(slots))
-        self.streams = [executor.new_stream() for _ in range(slots)]
+        self.free_slots = list(range(eval_slots))
+        self.streams = [executor.new_stream() for _ in range(eval_slots)]
         self.results: Dict[int, Result] = {}
+        self.to_factor: List[_Entry] = []   # admitted, not yet in the engine
+        self.factoring = 0                  # entries in the engine or queued for it
         self.peak_bytes = 0
-        self.max_inflight = 0
+        self.max_inflight = 0               # evaluations at once
+        self.max_factoring = 0              # geometries in the engine at once
         self.inflight = 0
+        self.engine = executor.new_engine()
+        self._stop = False
+        self._ft = threading.Thread(target=self._factor_loop, daemon=True)
+        self._ft.start()
 
     # -- memory ledger ----------------------------------------------------------------
     def _evict_for(self, need: int) -> bool:
@@ -218,76 +322,62 @@ class Server:
             self.ex.release(victim.fac)
         return True
 
-    _PARK = object()      # the request waits on its cached entry; later ones may start
-    _BLOCK = object()     # no memory for new factors: later fresh requests wait too
+    def _drop(self, entry: _Entry) -> None:
+        if self.cache.get(entry.key) is entry:
+            del self.cache[entry.key]
+        self.used -= entry.nbytes
+        if entry.fac is not None:
+            self.ex.release(entry.fac)
+            entry.fac = None
 
-    def _try_admit(self, req: Request, fresh_blocked: bool):
-        """(slot, entry) if req can start now, else _PARK or _BLOCK."""
-        key = geometry_key(req.problem)
-        entry = self.cache.get(key)
-        if entry is not None:
-            # factors hold per-call work vectors: one user at a time, and a
-            # geometry being factored is waited for rather than factored twice
-            if entry.users > 0 or not entry.ready:
-                return self._PARK
-            entry.users += 1
-            return self.free_slots.pop(0), entry
-        if fresh_blocked:      # first come, first served among requests needing memory
-            return self._BLOCK
-        need = self.ex.factor_bytes(req.problem)
-        if need > self.budget:
-            raise ServerError(f"request {req.rid} needs {need} bytes, budget {self.budget}")
-        if not self._evict_for(need):
-            return self._BLOCK
-        entry = _Entry(key, None, need, users=1, ready=False)
-        self.used += need
-        if self.cache_enabled:
-            self.cache[key] = entry
-        return self.free_slots.pop(0), entry
-
-    # -- per-request work (runs on the slot's thread) ----------------------------------------
-    def _run(self, req: Request, slot: int, entry: _Entry, t0: float, arrival: float):
-        res = Result(rid=req.rid, arrival=arrival, slot=slot)
-        res.start = time.perf_counter() - t0
-        stream = self.streams[slot]
-        fresh = not entry.ready
-        fac = entry.fac
-        try:
-            if fresh:
-                fac = self.ex.factor(req.problem, stream)
-            else:
-                res.cache_hit = True
-            res.F, res.grad_widths = self.ex.evaluate(fac, req.problem, req.adjoint, stream)
-        except Exception as e:      # a failed request frees its slot and memory only
-            res.error = str(e)
-        res.done = time.perf_counter() - t0
-        with self.cv:
-            entry.users -= 1
-            entry.last_used = res.done
-            if fresh:
-                keep = self.cache_enabled and fac is not None and res.error is None
-                if keep:
+    # -- the engine's thread ----------------------------------------------------------------
+    def _factor_loop(self):
+        made: Dict[int, _Entry] = {}
+        while True:
+            with self.cv:
+                while (not self._stop and not self.to_factor
+                       and self.ex.engine_size(self.engine) == 0):
+                    self.cv.wait()
+                if self._stop and not self.to_factor and self.ex.engine_size(self.engine) == 0:
+                    return
+                adds = self.to_factor[:]
+                self.to_factor.clear()
+            for entry in adds:
+                try:
+                    fac = self.ex.engine_add(self.engine, entry.p)
+                    made[id(fac)] = entry
                     entry.fac = fac
-                    entry.ready = True
-                else:
-                    if self.cache.get(entry.key) is entry:
-                        del self.cache[entry.key]
-                    self.used -= entry.nbytes
-                    if fac is not None:
-                        self.ex.release(fac)
-            self.free_slots.append(slot)
-            self.free_slots.sort()
-            self.inflight -= 1
-            self.results[req.rid] = res
-            self.cv.notify_all()
+                except Exception as e:     # bad geometry: fail its requests only
+                    with self.cv:
+                        entry.error = str(e)
+                        entry.ready = True
+                        self.factoring -= 1
+                        self.cv.notify_all()
+            with self.cv:
+                self.max_factoring = max(self.max_factoring, self.ex.engine_size(self.engine))
+            if self.ex.engine_size(self.engine) == 0:
+                continue
+            done = self.ex.engine_step(self.engine, self.rounds)
+            if done:
+                with self.cv:
+                    for fac, err in done:
+                        entry = made.pop(id(fac))
+                        entry.ready = True
+                        entry.error = err
+                        self.factoring -= 1
+                    self.cv.notify_all()
 
-    def _run_group(self, reqs: List[Request], slot: int, entry: _Entry, t0: float,
-                   arrivals: List[float], work_bytes: int):
-        """Plain evaluations of several requests on the same cached factors."""
+    # -- evaluations (run on a slot's thread) -----------------------------------------------
+    def _evaluate(self, reqs: List[Request], slot: int, entry: _Entry, t0: float,
+                  arrivals: List[float], work_bytes: int, fresh: List[bool]):
         start = time.perf_counter() - t0
-        err, Fs = None, [None] * len(reqs)
+        err, Fs, grads = None, [None] * len(reqs), [None] * len(reqs)
         try:
-            Fs = self.ex.evaluate_many(entry.fac, [r.problem for r in reqs], self.streams[slot])
+            if len(reqs) > 1:
+                Fs = self.ex.evaluate_many(entry.fac, [r.problem for r in reqs], self.streams[slot])
+            else:
+                Fs[0], grads[0] = self.ex.evaluate(entry.fac, reqs[0].problem, reqs[0].adjoint,
+                                                   self.streams[slot])
         except Exception as e:
             err = str(e)
         done = time.perf_counter() - t0
@@ -295,115 +385,172 @@ class Server:
             self.used -= work_bytes
             entry.users -= 1
             entry.last_used = done
+            if not self.cache_enabled and not self._wanted(entry):
+                self._drop(entry)
             self.free_slots.append(slot)
             self.free_slots.sort()
             self.inflight -= 1
-            for r, a, F in zip(reqs, arrivals, Fs):
-                self.results[r.rid] = Result(rid=r.rid, F=F, error=err, arrival=a, start=start,
-                                             done=done, cache_hit=True, slot=slot,
+            for r, a, F, g, fr in zip(reqs, arrivals, Fs, grads, fresh):
+                self.results[r.rid] = Result(rid=r.rid, F=F, grad_widths=g, error=err, arrival=a,
+                                             start=start, done=done, cache_hit=not fr, slot=slot,
                                              group=len(reqs))
             self.cv.notify_all()
+
+    def _wanted(self, entry: _Entry) -> bool:
+        return any(geometry_key(r.problem) == entry.key for r in self._waiting)
 
     # -- driver -----------------------------------------------------------------------------
     def run(self, requests: List[Request], realtime: bool = True) -> List[Result]:
         """Serve a request stream.  realtime: replay the arrival times; otherwise
-        every request is present at the start (latency counted from there).
-
-        Arrived requests are scanned in arrival order at every change.  A request
-        whose geometry is cached but busy (in use, or still being factored) is
-        parked and the scan goes on, so it never holds back unrelated requests;
-        it starts, or joins a group, once its entry is free.  A fresh request
-        that does not fit in memory holds back later fresh requests (first come,
-        first served for memory), not requests on cached factors."""
+        every request is present at the start (latency counted from there)."""
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
         t0 = time.perf_counter()
         threads = []
-        waiting: List[Request] = []
+        self._waiting: List[Request] = []
+        self._fresh: Dict[int, bool] = {}     # rid -> the request brought its geometry in
         nxt = 0
         with self.cv:
-            while nxt < len(pending) or waiting:
+            while nxt < len(pending) or self._waiting:
                 now = time.perf_counter() - t0
                 while nxt < len(pending) and (not realtime or pending[nxt].arrival <= now):
-                    waiting.append(pending[nxt])
+                    self._waiting.append(pending[nxt])
                     nxt += 1
-                started = self._admit_waiting(waiting, t0, now, realtime, threads)
-                if started:
+                if self._schedule(t0, realtime, threads):
                     continue
                 timeout = 0.05
                 if realtime and nxt < len(pending):
                     timeout = min(timeout, max(pending[nxt].arrival - now, 0.0))
-                if waiting or nxt < len(pending):
-                    self.cv.wait(timeout=timeout)
+                self.cv.wait(timeout=timeout)
         for th in threads:
             th.join()
         return [self.results[r.rid] for r in requests]
 
-    def _admit_waiting(self, waiting: List[Request], t0: float, now: float, realtime: bool,
-                       threads: list) -> bool:
-        """Start every waiting request that can start now; True if any did."""
-        started = False
+    def _schedule(self, t0: float, realtime: bool, threads: list) -> bool:
+        """Admit fresh geometries and start evaluations that can start; True if
+        anything changed."""
+        changed = False
         fresh_blocked = False
         i = 0
-        while i < len(waiting) and self.free_slots:
-            req = waiting[i]
+        while i < len(self._waiting):
+            req = self._waiting[i]
             arrival = req.arrival if realtime else 0.0
-            try:
-                adm = self._try_admit(req, fresh_blocked)
-            except ServerError as e:
-                self.results[req.rid] = Result(rid=req.rid, error=str(e), arrival=arrival,
-                                               done=time.perf_counter() - t0)
-                waiting.pop(i)
-                started = True
-                continue
-            if adm is self._PARK:
+            key = geometry_key(req.problem)
+            entry = self.cache.get(key)
+            if entry is None:
+                # needs new factors: memory and an engine slot, in arrival order
+                if fresh_blocked or self.factoring >= self.factor_slots:
+                    fresh_blocked = True
+                    i += 1
+                    continue
+                need = self.ex.factor_bytes(req.problem)
+                if need > self.budget:
+                    self.results[req.rid] = Result(
+                        rid=req.rid, error=f"request {req.rid} needs {need} bytes, budget "
+                                           f"{self.budget}", arrival=arrival,
+                        done=time.perf_counter() - t0)
+                    self._waiting.pop(i)
+                    changed = True
+                    continue
+                if not self._evict_for(need):
+                    fresh_blocked = True
+                    i += 1
+                    continue
+                entry = _Entry(key, req.problem, need)
+                self.used += need
+                self.peak_bytes = max(self.peak_bytes, self.used)
+                self.cache[key] = entry
+                self.to_factor.append(entry)
+                self.factoring += 1
+                self._fresh[req.rid] = True
+                changed = True
+                self.cv.notify_all()
                 i += 1
                 continue
-            if adm is self._BLOCK:
-                fresh_blocked = True
-                i += 1
+            if not entry.ready or entry.users > 0 or not self.free_slots:
+                i += 1           # parked on its geometry
                 continue
-            slot, entry = adm
-            waiting.pop(i)
-            started = True
-            self.inflight += 1
-            self.max_inflight = max(self.max_inflight, self.inflight)
+            if entry.error is not None:     # its factorisation failed
+                for r in [r for r in self._waiting if geometry_key(r.problem) == key]:
+                    self.results[r.rid] = Result(rid=r.rid, error=entry.error,
+                                                 arrival=r.arrival if realtime else 0.0,
+                                                 done=time.perf_counter() - t0)
+                self._waiting = [r for r in self._waiting if geometry_key(r.problem) != key]
+                self._drop(entry)
+                changed = True
+                i = 0
+                continue
+            # evaluate: this request and, for plain ones, others waiting on it
+            # (the entry is in use from here: eviction must not take it)
+            entry.users += 1
             group, work = [req], 0
-            if entry.ready and not req.adjoint and self.group > 1:
-                key = geometry_key(req.problem)
-                for other in waiting[i:]:
+            if not req.adjoint and self.group > 1:
+                for other in self._waiting[i + 1:]:
                     if len(group) >= self.group:
                         break
                     if not other.adjoint and geometry_key(other.problem) == key:
                         group.append(other)
-                # the grouped call's workspace comes out of the same memory budget
-                while len(group) > 1:
+                while len(group) > 1:       # the grouped call's workspace: same budget
                     work = self.ex.many_work_bytes(entry.fac, len(group))
                     if self._evict_for(work):
                         break
                     group.pop()
                     work = 0
-                if len(group) > 1:
-                    self.used += work
-                    taken = {r.rid for r in group[1:]}
-                    waiting[i:] = [r for r in waiting[i:] if r.rid not in taken]
+            taken = {r.rid for r in group}
+            self._waiting = [r for r in self._waiting if r.rid not in taken]
+            self.used += work
             self.peak_bytes = max(self.peak_bytes, self.used)
-            if len(group) > 1:
-                arrivals = [r.arrival if realtime else 0.0 for r in group]
-                th = threading.Thread(target=self._run_group,
-                                      args=(group, slot, entry, t0, arrivals, work), daemon=True)
-            else:
-                th = threading.Thread(target=self._run, args=(req, slot, entry, t0, arrival),
-                                      daemon=True)
+            slot = self.free_slots.pop(0)
+            self.inflight += 1
+            self.max_inflight = max(self.max_inflight, self.inflight)
+            arrivals = [r.arrival if realtime else 0.0 for r in group]
+            fresh = [self._fresh.pop(r.rid, False) for r in group]
+            th = threading.Thread(target=self._evaluate,
+                                  args=(group, slot, entry, t0, arrivals, work, fresh), daemon=True)
             th.start()
             threads.append(th)
-        return started
+            changed = True
+        return changed
 
     def close(self):
         with self.cv:
+            self._stop = True
+            self.cv.notify_all()
+        self._ft.join()
+        with self.cv:
             for e in list(self.cache.values()):
-                self.ex.release(e.fac)
+                if e.fac is not None:
+                    self.ex.release(e.fac)
             self.cache.clear()
             self.used = 0
+        self.ex.engine_close(self.engine)
+
+
+def serve_sequential(executor, requests: List[Request], realtime: bool = True) -> List[Result]:
+    """Baseline: one request at a time in arrival order, its geometry factored
+    alone, evaluated, and released (plain FP64 when the executor's precision
+    is)."""
+    stream = executor.new_stream()
+    t0 = time.perf_counter()
+    out = []
+    for req in sorted(requests, key=lambda r: (r.arrival, r.rid)):
+        if realtime:
+            wait = req.arrival - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+        res = Result(rid=req.rid, arrival=req.arrival if realtime else 0.0, slot=0)
+        res.start = time.perf_counter() - t0
+        fac = None
+        try:
+            fac = executor.factor(req.problem, stream)
+            res.F, res.grad_widths = executor.evaluate(fac, req.problem, req.adjoint, stream)
+        except Exception as e:
+            res.error = str(e)
+        if fac is not None:
+            executor.release(fac)
+        res.done = time.perf_counter() - t0
+        out.append(res)
+    by = {r.rid: r for r in out}
+    return [by[r.rid] for r in requests]
 
 
 def summarize(results: List[Result]) -> dict:

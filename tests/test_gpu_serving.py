@@ -12,11 +12,11 @@ def test_mix_equals_alone_and_oracle(rcp):
     from paper_2207_10701_amd.serve import GpuExecutor, Server, summarize
     reqs = W.serving_stream(8, rate=500.0, seed=5001, scale=0.04, geometry_pool=5)
     ex = GpuExecutor()
-    srv = Server(ex, slots=3, hbm_budget=8 << 30)
+    srv = Server(ex, eval_slots=3, hbm_budget=8 << 30)
     out = srv.run(reqs, realtime=True)
     srv.close()
     assert all(r.error is None for r in out), [r.error for r in out]
-    assert srv.max_inflight >= 2
+    assert srv.max_factoring >= 2
     s = summarize(out)
     assert s["ok"] == len(reqs)
     # each request alone, on the default stream, with fresh factors
@@ -71,7 +71,7 @@ def test_pool_requests_grouped_on_cached_factors(rcp):
     reqs = W.serving_stream(12, rate=500.0, seed=5003, scale=0.04, geometry_pool=2,
                             adjoint_frac=0.0)
     ex = GpuExecutor()
-    srv = Server(ex, slots=1, hbm_budget=8 << 30, group=8)
+    srv = Server(ex, eval_slots=1, hbm_budget=8 << 30, group=8)
     out = srv.run(reqs, realtime=False)
     srv.close()
     assert all(r.error is None for r in out), [r.error for r in out]
@@ -116,3 +116,42 @@ def test_misaligned_workspace_is_rejected(rcp):
     with pytest.raises(rcp.RecipError) as e:
         rcp.reciprocal_average_many(fac, [p, p], work=work[8:])
     assert e.value.code == _lib.RCP_EINVAL and "aligned" in str(e.value)
+
+
+@pytest.mark.timeout(600)
+def test_literal_serving_stream_mix_equals_alone(rcp):
+    """The serving stream as stated (64 requests at 200/s, widths 20-300 and
+    depths 10-60 wavelengths, fresh geometries, 20% adjoint) through the
+    engine server: the two largest requests give the same F (1e-10) as when
+    factored and evaluated alone, and the smallest matches the oracle."""
+    import numpy as np
+    import torch
+    from paper_2207_10701_amd.serve import GpuExecutor, Server
+    reqs = W.serving_stream(64, rate=200.0, seed=5001, scale=1.0, adjoint_frac=0.2)
+    work = np.array([4.0 * q.problem.ny ** 3 * q.problem.nx for q in reqs])
+    print(f"serving stream: {len(reqs)} requests, {work.sum() / 1e12:.0f} TFLOP", flush=True)
+    free, _ = torch.cuda.mem_get_info()
+    ex = GpuExecutor()
+    srv = Server(ex, hbm_budget=int(free - (24 << 30)))
+    out = srv.run(reqs, realtime=True)
+    srv.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    assert all(r.error is None for r in out), [r.error for r in out if r.error][:3]
+    assert srv.max_factoring >= 4
+    for k in np.argsort(-work)[:2]:
+        q, r = reqs[k], out[k]
+        fac = rcp.Factors(q.problem, rcp.eps_from_widths(q.problem))
+        if q.adjoint:
+            F, g = rcp.adjoint_grad(fac, q.problem)
+            gw = rcp.width_grad(q.problem, g).cpu().numpy()
+            assert np.linalg.norm(gw - r.grad_widths) <= 1e-9 * np.linalg.norm(gw)
+        else:
+            F = rcp.reciprocal_average(fac, q.problem)
+        assert abs(F.item() - r.F) <= 1e-10 * abs(F.item()), (k, F.item(), r.F)
+        del fac
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    k = int(np.argmin(work))
+    ref = ora.reciprocal(ora.setup(reqs[k].problem))
+    assert abs(out[k].F - ref) / ref < 1e-10
