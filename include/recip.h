@@ -357,8 +357,10 @@ int rcp_last_solve_stats(const rcp_factors* f, rcp_solve_stats* stats);
  *   4 multi-RHS block GEMM         work = algorithmic flops (8 per complex MAC)
  *   5 Gauss-Jordan last pass of a block (negated)    work = algorithmic flops
  *   6 dense complex product (W V, ensemble W)        work = algorithmic flops
+ *   7 launches of the factorisation engine (steps, row tiles, final
+ *     updates of mixed geometries)                   work = algorithmic flops
  * launches counts every launch, samples / ms / work only the timed ones. */
-#define RCP_NKCLASS 7
+#define RCP_NKCLASS 8
 typedef struct {
   int64_t launches, samples;
   double ms, work;
