@@ -24,6 +24,11 @@ large-area metasurfaces for incoherent light"):
                forward average of Eq. 5 over a finite ensemble of correlated
                planewaves.
 
+* ``fdfd3d``   the 3D vector (Yee) operator with a uniaxial PML, sheet-current
+               sources over two incidence angles and both polarisations, and the
+               3D reciprocal average with one solve per field component the
+               figure of merit reads (Sec. "Concluding remarks").
+
 All arithmetic is float64 / complex128; sparse solves use SciPy's SuperLU.
 """
-from . import fdfd, light, average  # noqa: F401
+from . import fdfd, light, average, fdfd3d  # noqa: F401

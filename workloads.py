@@ -335,3 +335,72 @@ def serving_stream(n_requests: int, rate: float = 200.0, seed: int = 5001, *,
                         focus_height=fh, monitor_y=min(d - 1.0, 1.5 + fh), **light)
         out.append(Request(rid=r, arrival=t, problem=p, adjoint=adj))
     return out
+
+
+# ----------------------------------------------------------------------------
+# 3D metasurfaces (vector fields on a Yee grid; inputs only)
+# ----------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class Problem3D:
+    """One 3D evaluation: a lattice of square pillars on a substrate, the
+    incidence plane below them, a focus (or a monitor plane) above.
+
+    Cells (i, j, k) have their centres at x = (i - npml + 1/2) h, likewise y and
+    z, origin at the lower corner of the physical region.  Incident light is
+    measured in the substrate (index n_source) by its polar angle theta from +z
+    and its azimuth; a cone of half-angle c around +z.
+    """
+
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    npml: int = 6
+    h: float = 0.125
+    wavelength: float = 1.0
+    pml_R: float = 1e-8
+    pml_m: int = 3
+    eps_bg: float = 1.0
+    eps_sub: float = 2.25
+    eps_pillar: float = 5.76
+    sub_layers: int = 14          # z-cells k < sub_layers hold substrate
+    pillar_k0: int = 14           # first pillar layer
+    pillar_layers: int = 4        # pillar height 0.5
+    pillar_centers: Tuple[Tuple[float, float], ...] = ()
+    widths: Tuple[float, ...] = ()
+    objective: int = CONCENTRATOR
+    focus: Tuple[int, int, int] = (0, 0, 0)
+    monitor_k: int = 0            # collimator: monitor plane
+    out_theta: float = 0.0        # collimator output direction (rad, in air)
+    out_azimuth: float = 0.0
+    source_k: int = 10            # incidence plane
+    n_source: float = 1.5
+    c: float = 0.0                # cone half-angle (rad)
+
+    @property
+    def n_cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+def metasurface3d(name: str, width_wl: int, height_wl: float, seed: int, *,
+                  h: float = 0.125, npml: int = 6, objective: int = CONCENTRATOR,
+                  focus_height: float = 1.0, monitor_y: float = 1.5, c_deg: float = 15.0,
+                  out_theta: float = 0.0, out_azimuth: float = 0.0) -> Problem3D:
+    """width_wl x width_wl pillars of period 1 (seeded widths U[0.1, 0.9]) on a
+    substrate 0.5 thick, pillar height 0.5; height_wl of physical depth."""
+    per = int(round(1.0 / h))
+    nxp = width_wl * per
+    nzp = int(round(height_wl * per))
+    sub = npml + per // 2
+    pk = sub
+    top = pk + per // 2
+    centers = tuple(((a + 0.5), (b + 0.5)) for a in range(width_wl) for b in range(width_wl))
+    return Problem3D(name=name, nx=nxp + 2 * npml, ny=nxp + 2 * npml, nz=nzp + 2 * npml,
+                     npml=npml, h=h, sub_layers=sub, pillar_k0=pk, pillar_layers=per // 2,
+                     pillar_centers=centers, widths=seeded_widths(len(centers), seed),
+                     objective=objective,
+                     focus=(npml + nxp // 2, npml + nxp // 2, top + int(round(focus_height * per))),
+                     monitor_k=npml + int(round(monitor_y * per)), out_theta=out_theta,
+                     out_azimuth=out_azimuth, source_k=npml + per // 4,
+                     c=math.radians(c_deg))
