@@ -90,6 +90,18 @@ class GpuExecutor:
     def factor_bytes(self, p: Problem) -> int:
         return self.rcp.factor_bytes(p, self.precision)
 
+    def _buffer(self, nbytes: int):
+        """A factor buffer.  The ledger has already admitted these bytes; when
+        the caching allocator cannot place them (its free blocks are cut to
+        other sizes), its unused blocks go back to the device and it tries once
+        more."""
+        torch = self.torch
+        try:
+            return torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        except torch.OutOfMemoryError:
+            torch.cuda.empty_cache()
+            return torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+
     # -- factorisation engine (one host thread) --
     def new_engine(self):
         eng = self.rcp.FactorEngine(self.precision, stream=self.new_stream())
@@ -101,7 +113,8 @@ class GpuExecutor:
         with torch.cuda.stream(eng.stream):
             widths = torch.tensor(p.widths, dtype=torch.float64, device=self.device)
             eps = rcp.eps_from_widths(p, widths, device=self.device, stream=eng.stream)
-            return eng.add(p, eps)
+            buf = self._buffer(self.factor_bytes(p))
+            return eng.add(p, eps, buffer=buf)
 
     def engine_step(self, eng, rounds: int):
         """Enqueue up to `rounds` rounds; keep at most `ahead` steps queued on the
@@ -127,7 +140,8 @@ class GpuExecutor:
         with torch.cuda.stream(stream):
             widths = torch.tensor(p.widths, dtype=torch.float64, device=self.device)
             eps = rcp.eps_from_widths(p, widths, device=self.device, stream=stream)
-            fac = rcp.Factors(p, eps, self.precision, stream=stream)
+            fac = rcp.Factors(p, eps, self.precision, stream=stream,
+                              buffer=self._buffer(self.factor_bytes(p)))
         return fac
 
     def evaluate(self, fac, p: Problem, adjoint: bool, stream):
