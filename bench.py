@@ -594,6 +594,36 @@ def main():
                 f"({out['lu_batch']['tflops_method_4n3']} TF/s on the method's count)")
             fac = facs_b[-1]      # geometry widths[-1] again, now in bufs[-1]
             del facs_b
+            # the same geometries through the factorisation engine (the launches
+            # serving shares between geometries of any size), then one alone
+            eng = rcp.FactorEngine(rcp.RCP_FP64, stream=stream)
+            del fac
+            torch.cuda.synchronize()
+            a.record(stream)
+            efacs = [eng.add(p, e, buffer=bb) for e, bb in zip(eps_b, bufs)]
+            eng.run()
+            b.record(stream)
+            torch.cuda.synchronize()
+            t_e = a.elapsed_time(b) * 1e-3
+            F_e = rcp.reciprocal_average(efacs[-1], p).item()
+            del efacs
+            torch.cuda.synchronize()
+            a.record(stream)
+            efac = eng.add(p, eps_b[-1], buffer=bufs[0])
+            eng.run()
+            b.record(stream)
+            torch.cuda.synchronize()
+            t_e1 = a.elapsed_time(b) * 1e-3
+            eng.close()
+            out["lu_engine"] = {"batch": {"geometries": B, "seconds": round(t_e, 5),
+                                          **lu_rates(p, t_e, B)},
+                                "single": {"seconds": round(t_e1, 5), **lu_rates(p, t_e1)},
+                                "F_last": F_e}
+            log(f"engine x{B}: {t_e * 1e3:.1f} ms, alone {t_e1 * 1e3:.1f} ms")
+            del efac
+            facs_b = rcp.factor_batch([p] * B, eps_b, rcp.RCP_FP64, buffers=bufs)
+            fac = facs_b[-1]
+            del facs_b
         # reciprocal average on cached factors
         reps = 10
         Fr = rcp.reciprocal_average(fac, p)
@@ -629,6 +659,22 @@ def main():
                               "end_to_end": round((t_bf + t_fac) / (t_rec + t_fac), 3)}
             log(f"brute force {args.bf_angles} angles: {t_bf:.3f} s, F={Fb.item():.10e}, "
                 f"rel diff {rel:.2e}")
+            # Sec. "Brute-force quadrature": the Gauss-Legendre rule against the
+            # reciprocal F on the same factors as the node count grows
+            sweep = []
+            for n in (16, 32, 64, 128, 256, 512, 1024):
+                torch.cuda.synchronize()
+                a.record(stream)
+                Fn = rcp.brute_force_average(fac, n, p, rhs_chunk=min(n, 1024)).item()
+                b.record(stream)
+                torch.cuda.synchronize()
+                sweep.append({"nodes": n, "rel_err_vs_reciprocal": abs(Fn - Fr.item()) / Fr.item(),
+                              "seconds": round(a.elapsed_time(b) * 1e-3, 4)})
+            out["gl_node_sweep"] = {"note": "F_bf(N) of the +-20 deg cone on the config-2 factors "
+                                            "against the reciprocal F; resolved once N exceeds "
+                                            "about K c L / 2 = 164",
+                                    "points": sweep}
+            log(f"GL sweep: {[(q['nodes'], '%.1e' % q['rel_err_vs_reciprocal']) for q in sweep]}")
         # any correlation W and many outputs on the same factors
         if args.dense_outputs > 0:
             out["dense_correlation"] = dense_extra(args, rcp, W, p, fac, t_rec, stream)
