@@ -260,6 +260,24 @@ int rcp_reciprocal_average_many(const rcp_factors* f, int32_t count, const rcp_o
                                 const rcp_light* lights, double* F_dev, void* work_dev,
                                 size_t work_bytes, rcp_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluations as rcp_reciprocal_average_many (same checks, same kernels, the
+ * same F to the bit) with the workspace taken from a static device array of
+ * RCP_NOALLOC_SCRATCH_BYTES bytes that the library holds on every GPU it runs
+ * on until the process ends, instead of work_dev.  Allocates nothing.  Its
+ * address on a device is looked up on the first call with that device
+ * current.  RCP_ENOMEM when rcp_reciprocal_many_work_bytes(f, count) exceeds
+ * the array (2 count nx ny complex128 values: e.g. count <= 3 on a 2040 x 1080
+ * grid).  All calls on one GPU share its array: calls that overlap in time on
+ * one GPU (other streams, other host threads) race and give wrong results;
+ * order them on one stream.  The workspace is written before it is read, so
+ * nothing carries over from the previous call. */
+#define RCP_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int rcp_reciprocal_average_many_noalloc(const rcp_factors* f, int32_t count,
+                                        const rcp_objective* objs, const rcp_light* lights,
+                                        double* F_dev, rcp_stream stream);
+
 /* ---- any correlation W and many outputs --------------------------------
  * Sec. "Incoherent light": the reciprocal identity of Eq. 7 holds for
  * arbitrarily correlated light, where W is a dense Hermitian M x M matrix on

@@ -87,6 +87,8 @@ def _load():
         "rcp_width_grad": (C.c_int, [P(Grid), P(Pillars), vp, vp, vp]),
         "rcp_reciprocal_many_work_bytes": (sz, [vp, i32]),
         "rcp_reciprocal_average_many": (C.c_int, [vp, i32, P(Objective), P(Light), vp, vp, sz, vp]),
+        "rcp_reciprocal_average_many_noalloc": (C.c_int, [vp, i32, P(Objective), P(Light), vp,
+                                                          vp]),
         "rcp_dense_work_bytes": (sz, [vp, i32, i32]),
         "rcp_reciprocal_average_dense": (C.c_int, [vp, i32, P(Objective), P(Light), vp, vp, vp,
                                                    vp, sz, vp]),

@@ -559,24 +559,31 @@ size_t rcp_reciprocal_many_work_bytes(const rcp_factors* f, int32_t count) {
   return align256(2 * size_t(count) * f->nx * f->ny * sizeof(double2));
 }
 
-int rcp_reciprocal_average_many(const rcp_factors* fc, int32_t count, const rcp_objective* objs,
-                                const rcp_light* lights, double* F_dev, void* work_dev,
-                                size_t work_bytes, rcp_stream stream) {
-  rcp_factors* f = const_cast<rcp_factors*>(fc);
-  if (reinterpret_cast<uintptr_t>(work_dev) % 256 != 0)
-    return fail(RCP_EINVAL, "workspace must be 256-byte aligned");
+}  // extern "C"
+
+namespace {
+
+// Checks shared by rcp_reciprocal_average_many and its allocation-free variant.
+int check_many(const rcp_factors* f, int32_t count, const rcp_objective* objs,
+               const rcp_light* lights, const double* F_dev) {
   if (!f) return fail(RCP_EINVAL, "factors is NULL");
   if (count < 1 || count > 64) return fail(RCP_EINVAL, "count must be 1 to 64");
-  if (!objs || !lights || !F_dev || !work_dev) return fail(RCP_EINVAL, "NULL argument");
+  if (!objs || !lights || !F_dev) return fail(RCP_EINVAL, "NULL argument");
   for (int k = 0; k < count; ++k) {
     int rc = check_objective(f, &objs[k]);
     if (!rc) rc = check_light(f, &lights[k], false);
     if (rc) return rc;
   }
-  const size_t need = rcp_reciprocal_many_work_bytes(f, count);
-  if (work_bytes < need) return fail(RCP_ENOMEM, "work buffer: need " + std::to_string(need) + " bytes");
+  return RCP_OK;
+}
+
+// The evaluations of rcp_reciprocal_average_many on a workspace of at least
+// rcp_reciprocal_many_work_bytes(f, count) bytes (every byte of it is written
+// before it is read).
+int reciprocal_many(rcp_factors* f, int32_t count, const rcp_objective* objs,
+                    const rcp_light* lights, double* F_dev, void* work, hipStream_t stream) {
   const size_t N = size_t(f->nx) * f->ny;
-  double2* B = static_cast<double2*>(work_dev);
+  double2* B = static_cast<double2*>(work);
   double2* Z = B + size_t(count) * N;
   int lo, hi, rc = RCP_OK;
   if (f->precision == RCP_FP64 && count >= 2) {   // all objectives in one multi-RHS sweep
@@ -593,6 +600,68 @@ int rcp_reciprocal_average_many(const rcp_factors* fc, int32_t count, const rcp_
   for (int k = 0; k < count && !rc; ++k)
     rc = toeplitz_form(f, &lights[k], Z + k * N, F_dev + k, nullptr, nullptr, stream);
   return rc;
+}
+
+}  // namespace
+
+// Workspace of the allocation-free entry point: one array per GPU, held until
+// the process ends.  In host code `scratch` only names the array (a host-side
+// stand-in, not a device address); its address on each device comes from
+// hipGetSymbolAddress with that device current and is kept per device.
+static __device__ __align__(256) unsigned char scratch[RCP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+int scratch_address(void** out) {
+  int dev = -1;
+  RCP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(RCP_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    RCP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(RCP_EHIP, "no device address for the scratch array");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return RCP_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int rcp_reciprocal_average_many(const rcp_factors* fc, int32_t count, const rcp_objective* objs,
+                                const rcp_light* lights, double* F_dev, void* work_dev,
+                                size_t work_bytes, rcp_stream stream) {
+  rcp_factors* f = const_cast<rcp_factors*>(fc);
+  if (reinterpret_cast<uintptr_t>(work_dev) % 256 != 0)
+    return fail(RCP_EINVAL, "workspace must be 256-byte aligned");
+  int rc = check_many(f, count, objs, lights, F_dev);
+  if (rc) return rc;
+  if (!work_dev) return fail(RCP_EINVAL, "NULL argument");
+  const size_t need = rcp_reciprocal_many_work_bytes(f, count);
+  if (work_bytes < need) return fail(RCP_ENOMEM, "work buffer: need " + std::to_string(need) + " bytes");
+  return reciprocal_many(f, count, objs, lights, F_dev, work_dev, stream);
+}
+
+int rcp_reciprocal_average_many_noalloc(const rcp_factors* fc, int32_t count,
+                                        const rcp_objective* objs, const rcp_light* lights,
+                                        double* F_dev, rcp_stream stream) {
+  rcp_factors* f = const_cast<rcp_factors*>(fc);
+  int rc = check_many(f, count, objs, lights, F_dev);
+  if (rc) return rc;
+  const size_t need = rcp_reciprocal_many_work_bytes(f, count);
+  if (need > RCP_NOALLOC_SCRATCH_BYTES)
+    return fail(RCP_ENOMEM, std::to_string(count) + " evaluations on this grid need " +
+                                std::to_string(need) + " bytes of workspace; the scratch array holds " +
+                                std::to_string(size_t(RCP_NOALLOC_SCRATCH_BYTES)));
+  void* work = nullptr;
+  rc = scratch_address(&work);
+  if (rc) return rc;
+  return reciprocal_many(f, count, objs, lights, F_dev, work, stream);
 }
 
 int rcp_adjoint_grad(const rcp_factors* fc, const rcp_objective* obj, const rcp_light* light,
