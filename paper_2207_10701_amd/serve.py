@@ -67,6 +67,50 @@ class ServerError(RuntimeError):
     pass
 
 
+class Arena:
+    """First-fit placement of byte ranges in [0, size), 256-byte aligned, free
+    neighbours merged.  The server's memory ledger: every factor set and group
+    workspace gets an explicit offset in one device region, so an admitted
+    request never meets an allocator that cannot place its buffer."""
+
+    ALIGN = 256
+
+    def __init__(self, size: int):
+        self.size = int(size)
+        self.free = [(0, self.size)]     # sorted (offset, length)
+        self.used = 0
+
+    @classmethod
+    def aligned(cls, n: int) -> int:
+        return (int(n) + cls.ALIGN - 1) // cls.ALIGN * cls.ALIGN
+
+    def place(self, n: int) -> Optional[int]:
+        n = self.aligned(n)
+        for k, (o, length) in enumerate(self.free):
+            if length >= n:
+                if length == n:
+                    del self.free[k]
+                else:
+                    self.free[k] = (o + n, length - n)
+                self.used += n
+                return o
+        return None
+
+    def release(self, off: int, n: int) -> None:
+        n = self.aligned(n)
+        self.used -= n
+        k = 0
+        while k < len(self.free) and self.free[k][0] < off:
+            k += 1
+        self.free.insert(k, (off, n))
+        if k + 1 < len(self.free) and off + n == self.free[k + 1][0]:
+            self.free[k] = (off, n + self.free[k + 1][1])
+            del self.free[k + 1]
+        if k > 0 and self.free[k - 1][0] + self.free[k - 1][1] == off:
+            self.free[k - 1] = (self.free[k - 1][0], self.free[k - 1][1] + self.free[k][1])
+            del self.free[k]
+
+
 # ---------------------------------------------------------------------------
 # executors
 
@@ -90,17 +134,15 @@ class GpuExecutor:
     def factor_bytes(self, p: Problem) -> int:
         return self.rcp.factor_bytes(p, self.precision)
 
-    def _buffer(self, nbytes: int):
-        """A factor buffer.  The ledger has already admitted these bytes; when
-        the caching allocator cannot place them (its free blocks are cut to
-        other sizes), its unused blocks go back to the device and it tries once
-        more."""
-        torch = self.torch
-        try:
-            return torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        except torch.OutOfMemoryError:
-            torch.cuda.empty_cache()
-            return torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+    def open_arena(self, nbytes: int) -> None:
+        """The device region the server's ledger places buffers in."""
+        self.arena = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device=self.device)
+
+    def close_arena(self) -> None:
+        self.arena = None
+
+    def _view(self, off: int, nbytes: int):
+        return self.arena[off:off + nbytes]
 
     # -- factorisation engine (one host thread) --
     def new_engine(self):
@@ -108,13 +150,12 @@ class GpuExecutor:
         eng._marks = []
         return eng
 
-    def engine_add(self, eng, p: Problem):
+    def engine_add(self, eng, p: Problem, off: int):
         torch, rcp = self.torch, self.rcp
         with torch.cuda.stream(eng.stream):
             widths = torch.tensor(p.widths, dtype=torch.float64, device=self.device)
             eps = rcp.eps_from_widths(p, widths, device=self.device, stream=eng.stream)
-            buf = self._buffer(self.factor_bytes(p))
-            return eng.add(p, eps, buffer=buf)
+            return eng.add(p, eps, buffer=self._view(off, self.factor_bytes(p)))
 
     def engine_step(self, eng, rounds: int):
         """Enqueue up to `rounds` rounds; keep at most `ahead` steps queued on the
@@ -140,8 +181,7 @@ class GpuExecutor:
         with torch.cuda.stream(stream):
             widths = torch.tensor(p.widths, dtype=torch.float64, device=self.device)
             eps = rcp.eps_from_widths(p, widths, device=self.device, stream=stream)
-            fac = rcp.Factors(p, eps, self.precision, stream=stream,
-                              buffer=self._buffer(self.factor_bytes(p)))
+            fac = rcp.Factors(p, eps, self.precision, stream=stream)
         return fac
 
     def evaluate(self, fac, p: Problem, adjoint: bool, stream):
@@ -160,11 +200,14 @@ class GpuExecutor:
         """Device workspace of a grouped evaluation of count requests."""
         return int(self.rcp.lib.rcp_reciprocal_many_work_bytes(fac.handle, count))
 
-    def evaluate_many(self, fac, problems, stream):
-        """Plain evaluations of several requests on one factor set."""
+    def evaluate_many(self, fac, problems, stream, work_off: int):
+        """Plain evaluations of several requests on one factor set (workspace
+        at work_off in the arena)."""
         torch, rcp = self.torch, self.rcp
+        need = self.many_work_bytes(fac, len(problems))
         with torch.cuda.stream(stream):
-            F = rcp.reciprocal_average_many(fac, problems, stream=stream)
+            F = rcp.reciprocal_average_many(fac, problems, stream=stream,
+                                            work=self._view(work_off, need))
             stream.synchronize()
         return [float(v) for v in F.cpu().numpy()]
 
@@ -212,10 +255,16 @@ class FakeExecutor:
             self.peak_live = max(self.peak_live, self.live)
         return {"p": p, "bytes": self.factor_bytes(p)}
 
+    def open_arena(self, nbytes: int) -> None:
+        pass
+
+    def close_arena(self) -> None:
+        pass
+
     def new_engine(self):
         return _FakeEngine()
 
-    def engine_add(self, eng, p: Problem):
+    def engine_add(self, eng, p: Problem, off: int):
         fac = self._made(p)
         rounds = max(1, int(round(self.factor_seconds(p) / self.round_seconds)))
         eng.items.append([fac, rounds])
@@ -260,7 +309,7 @@ class FakeExecutor:
         p = fac["p"]
         return 32 * count * p.nx * p.ny
 
-    def evaluate_many(self, fac, problems, stream):
+    def evaluate_many(self, fac, problems, stream, work_off: int):
         time.sleep(self.eval_seconds)   # one sweep for all of them
         with self.lock:
             self.group_sizes.append(len(problems))
@@ -280,6 +329,7 @@ class _Entry:
     key: Any
     p: Problem
     nbytes: int
+    off: int = 0                 # place in the arena
     fac: Any = None
     users: int = 0               # evaluations running on it (one at a time)
     last_used: float = 0.0
@@ -307,7 +357,8 @@ class Server:
         self.cache_enabled = cache
         self.rounds = rounds_per_step
         self.cache: Dict[Any, _Entry] = {}
-        self.used = 0                       # bytes of factors held + group workspaces
+        self.arena = Arena(self.budget)     # factor sets and group workspaces
+        executor.open_arena(self.budget)
         self.cv = threading.Condition()
         self.free_slots = list(range(eval_slots))
         self.streams = [executor.new_stream() for _ in range(eval_slots)]
@@ -324,25 +375,30 @@ class Server:
         self._ft.start()
 
     # -- memory ledger ----------------------------------------------------------------
-    def _evict_for(self, need: int) -> bool:
-        """Free idle cached factors (least recently used first) until need fits."""
-        while self.used + need > self.budget:
+    @property
+    def used(self) -> int:
+        return self.arena.used
+
+    def _place(self, need: int) -> Optional[int]:
+        """An offset for need bytes, evicting idle cached factors (least recently
+        used first) until they fit; None if they cannot."""
+        while True:
+            off = self.arena.place(need)
+            if off is not None:
+                self.peak_bytes = max(self.peak_bytes, self.arena.used)
+                return off
             idle = [e for e in self.cache.values() if e.users == 0 and e.ready]
             if not idle:
-                return False
-            victim = min(idle, key=lambda e: e.last_used)
-            del self.cache[victim.key]
-            self.used -= victim.nbytes
-            self.ex.release(victim.fac)
-        return True
+                return None
+            self._drop(min(idle, key=lambda e: e.last_used))
 
     def _drop(self, entry: _Entry) -> None:
         if self.cache.get(entry.key) is entry:
             del self.cache[entry.key]
-        self.used -= entry.nbytes
         if entry.fac is not None:
             self.ex.release(entry.fac)
             entry.fac = None
+        self.arena.release(entry.off, entry.nbytes)
 
     # -- the engine's thread ----------------------------------------------------------------
     def _factor_loop(self):
@@ -358,7 +414,7 @@ class Server:
                 self.to_factor.clear()
             for entry in adds:
                 try:
-                    fac = self.ex.engine_add(self.engine, entry.p)
+                    fac = self.ex.engine_add(self.engine, entry.p, entry.off)
                     made[id(fac)] = entry
                     entry.fac = fac
                 except Exception as e:     # bad geometry: fail its requests only
@@ -383,12 +439,13 @@ class Server:
 
     # -- evaluations (run on a slot's thread) -----------------------------------------------
     def _evaluate(self, reqs: List[Request], slot: int, entry: _Entry, t0: float,
-                  arrivals: List[float], work_bytes: int, fresh: List[bool]):
+                  arrivals: List[float], work: tuple, fresh: List[bool]):
         start = time.perf_counter() - t0
         err, Fs, grads = None, [None] * len(reqs), [None] * len(reqs)
         try:
             if len(reqs) > 1:
-                Fs = self.ex.evaluate_many(entry.fac, [r.problem for r in reqs], self.streams[slot])
+                Fs = self.ex.evaluate_many(entry.fac, [r.problem for r in reqs], self.streams[slot],
+                                           work[0])
             else:
                 Fs[0], grads[0] = self.ex.evaluate(entry.fac, reqs[0].problem, reqs[0].adjoint,
                                                    self.streams[slot])
@@ -396,7 +453,8 @@ class Server:
             err = str(e)
         done = time.perf_counter() - t0
         with self.cv:
-            self.used -= work_bytes
+            if work[1]:
+                self.arena.release(*work)
             entry.users -= 1
             entry.last_used = done
             if not self.cache_enabled and not self._wanted(entry):
@@ -457,7 +515,7 @@ class Server:
                     i += 1
                     continue
                 need = self.ex.factor_bytes(req.problem)
-                if need > self.budget:
+                if Arena.aligned(need) > self.budget:
                     self.results[req.rid] = Result(
                         rid=req.rid, error=f"request {req.rid} needs {need} bytes, budget "
                                            f"{self.budget}", arrival=arrival,
@@ -465,13 +523,12 @@ class Server:
                     self._waiting.pop(i)
                     changed = True
                     continue
-                if not self._evict_for(need):
+                off = self._place(need)
+                if off is None:
                     fresh_blocked = True
                     i += 1
                     continue
-                entry = _Entry(key, req.problem, need)
-                self.used += need
-                self.peak_bytes = max(self.peak_bytes, self.used)
+                entry = _Entry(key, req.problem, need, off)
                 self.cache[key] = entry
                 self.to_factor.append(entry)
                 self.factoring += 1
@@ -496,23 +553,22 @@ class Server:
             # evaluate: this request and, for plain ones, others waiting on it
             # (the entry is in use from here: eviction must not take it)
             entry.users += 1
-            group, work = [req], 0
+            group, work = [req], (0, 0)
             if not req.adjoint and self.group > 1:
                 for other in self._waiting[i + 1:]:
                     if len(group) >= self.group:
                         break
                     if not other.adjoint and geometry_key(other.problem) == key:
                         group.append(other)
-                while len(group) > 1:       # the grouped call's workspace: same budget
-                    work = self.ex.many_work_bytes(entry.fac, len(group))
-                    if self._evict_for(work):
+                while len(group) > 1:       # the grouped call's workspace: same ledger
+                    wb = self.ex.many_work_bytes(entry.fac, len(group))
+                    woff = self._place(wb)
+                    if woff is not None:
+                        work = (woff, wb)
                         break
                     group.pop()
-                    work = 0
             taken = {r.rid for r in group}
             self._waiting = [r for r in self._waiting if r.rid not in taken]
-            self.used += work
-            self.peak_bytes = max(self.peak_bytes, self.used)
             slot = self.free_slots.pop(0)
             self.inflight += 1
             self.max_inflight = max(self.max_inflight, self.inflight)
@@ -535,8 +591,9 @@ class Server:
                 if e.fac is not None:
                     self.ex.release(e.fac)
             self.cache.clear()
-            self.used = 0
+            self.arena = Arena(self.budget)
         self.ex.engine_close(self.engine)
+        self.ex.close_arena()
 
 
 def serve_sequential(executor, requests: List[Request], realtime: bool = True) -> List[Result]:

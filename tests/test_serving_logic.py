@@ -5,8 +5,8 @@ import time
 import pytest
 
 import workloads as W
-from paper_2207_10701_amd.serve import (FakeExecutor, Server, geometry_key, serve_sequential,
-                                        summarize)
+from paper_2207_10701_amd.serve import (Arena, FakeExecutor, Server, geometry_key,
+                                        serve_sequential, summarize)
 
 
 def stream(n, **kw):
@@ -200,10 +200,11 @@ def test_group_workspace_counts_against_the_budget():
     ex = FakeExecutor()
     fb = ex.factor_bytes(p)
     one = 32 * p.nx * p.ny
-    srv, out = serve(ex, reqs, realtime=False, eval_slots=1, hbm_budget=fb + 4 * one, group=8)
+    budget = Arena.aligned(fb) + Arena.aligned(4 * one)
+    srv, out = serve(ex, reqs, realtime=False, eval_slots=1, hbm_budget=budget, group=8)
     assert all(r.error is None for r in out)
     assert max(r.group for r in out) == 4
-    assert srv.peak_bytes <= fb + 4 * one
+    assert srv.peak_bytes <= budget
 
 
 def test_sequential_baseline_serves_one_at_a_time():
@@ -221,3 +222,18 @@ def test_server_arguments():
         Server(FakeExecutor(), factor_slots=9)
     with pytest.raises(ValueError):
         Server(FakeExecutor(), eval_slots=0)
+
+
+def test_arena_places_first_fit_and_merges_free_neighbours():
+    a = Arena(10 * 256)
+    x = a.place(300)            # two units
+    y = a.place(256)
+    z = a.place(5 * 256)
+    assert (x, y, z) == (0, 512, 768) and a.used == 8 * 256
+    assert a.place(3 * 256) is None
+    a.release(y, 256)
+    assert a.place(2 * 256) == 2048          # the hole of one unit is too small
+    a.release(x, 300)
+    a.release(z, 5 * 256)
+    assert a.free == [(0, 2048)]             # 0..512, 512..768 and 768..2048 merged
+    assert a.place(8 * 256) == 0 and a.used == 10 * 256
