@@ -206,8 +206,17 @@ def serving(args):
     res = conc.run(reqs, realtime=True)
     conc.close()
     s_con = summarize(res)
-    log(f"serving: engine {s_con}")
+    log(f"serving: engine {s_con}, occupancy {conc.engine_occupancy():.2f}")
     errors = sorted({r.error for r in res if r.error})[:3]
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    # the same stream with the largest factorisations admitted first
+    lpt = Server(ex, factor_slots=8, eval_slots=4, hbm_budget=budget, cache=True,
+                 order="largest_first")
+    res_l = lpt.run(reqs, realtime=True)
+    lpt.close()
+    s_lpt = summarize(res_l)
+    log(f"serving: engine, largest first {s_lpt}, occupancy {lpt.engine_occupancy():.2f}")
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     seq = serve_sequential(ex, reqs, realtime=True)
@@ -225,6 +234,13 @@ def serving(args):
            "factor_tflops_method": round(work / s_con["makespan_s"] / 1e12, 2)
            if s_con["makespan_s"] > 0 else None,
            "max_geometries_factoring": conc.max_factoring, "max_evaluations": conc.max_inflight,
+           "engine_mean_geometries": round(conc.engine_occupancy(), 2),
+           "admission": "arrival order (first come, first served for memory and engine slots)",
+           "largest_first": {"p50_ms": round(s_lpt["p50_ms"], 2), "p99_ms": round(s_lpt["p99_ms"], 2),
+                             "evals_per_s": round(s_lpt["evals_per_s"], 3),
+                             "makespan_s": round(s_lpt["makespan_s"], 3),
+                             "engine_mean_geometries": round(lpt.engine_occupancy(), 2),
+                             "failed": s_lpt["failed"]},
            "peak_ledger_gb": round(conc.peak_bytes / 2 ** 30, 2),
            "failed": s_con["failed"], "errors": errors,
            "latency_note": "from arrival to result; the stream offers far more work than one GPU "

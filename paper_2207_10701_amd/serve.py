@@ -343,13 +343,16 @@ class Server:
 
     def __init__(self, executor, factor_slots: int = 8, eval_slots: int = 4,
                  hbm_budget: int = 200 << 30, cache: bool = True, group: int = 16,
-                 rounds_per_step: int = 4):
+                 rounds_per_step: int = 4, order: str = "arrival"):
         if not 1 <= factor_slots <= 8:
             raise ValueError("factor_slots must be 1 to 8")
         if eval_slots < 1:
             raise ValueError("eval_slots must be >= 1")
         if not 1 <= group <= 64:
             raise ValueError("group must be 1 to 64")
+        if order not in ("arrival", "largest_first"):
+            raise ValueError("order is 'arrival' or 'largest_first'")
+        self.order = order
         self.ex = executor
         self.factor_slots = factor_slots
         self.group = group
@@ -368,6 +371,8 @@ class Server:
         self.peak_bytes = 0
         self.max_inflight = 0               # evaluations at once
         self.max_factoring = 0              # geometries in the engine at once
+        self.engine_time = 0.0              # wall time with geometries in the engine
+        self.engine_geom_time = 0.0         # ... times the geometries in it
         self.inflight = 0
         self.engine = executor.new_engine()
         self._stop = False
@@ -387,7 +392,9 @@ class Server:
             if off is not None:
                 self.peak_bytes = max(self.peak_bytes, self.arena.used)
                 return off
-            idle = [e for e in self.cache.values() if e.users == 0 and e.ready]
+            # idle: ready, not in use, and no waiting request needs it
+            idle = [e for e in self.cache.values()
+                    if e.users == 0 and e.ready and not self._wanted(e)]
             if not idle:
                 return None
             self._drop(min(idle, key=lambda e: e.last_used))
@@ -427,7 +434,12 @@ class Server:
                 self.max_factoring = max(self.max_factoring, self.ex.engine_size(self.engine))
             if self.ex.engine_size(self.engine) == 0:
                 continue
+            n_in = self.ex.engine_size(self.engine)
+            t_step = time.perf_counter()
             done = self.ex.engine_step(self.engine, self.rounds)
+            dt = time.perf_counter() - t_step
+            self.engine_time += dt
+            self.engine_geom_time += dt * n_in
             if done:
                 with self.cv:
                     for fac, err in done:
@@ -469,7 +481,7 @@ class Server:
             self.cv.notify_all()
 
     def _wanted(self, entry: _Entry) -> bool:
-        return any(geometry_key(r.problem) == entry.key for r in self._waiting)
+        return any(geometry_key(r.problem) == entry.key for r in getattr(self, "_waiting", ()))
 
     # -- driver -----------------------------------------------------------------------------
     def run(self, requests: List[Request], realtime: bool = True) -> List[Result]:
@@ -497,47 +509,55 @@ class Server:
             th.join()
         return [self.results[r.rid] for r in requests]
 
+    def _admit_fresh(self, t0: float, realtime: bool) -> bool:
+        """Start the factorisation of geometries not in the cache, in the order of
+        the policy (arrival, or the largest factorisation first), while engine
+        slots and memory last: the first that does not fit holds back the rest
+        (no request overtakes one it is ordered behind)."""
+        fresh, seen = [], set()
+        for r in self._waiting:
+            key = geometry_key(r.problem)
+            if key not in self.cache and key not in seen:
+                seen.add(key)
+                fresh.append(r)
+        if self.order == "largest_first":
+            fresh.sort(key=lambda r: -float(r.problem.ny) ** 3 * r.problem.nx)
+        changed = False
+        for req in fresh:
+            if self.factoring >= self.factor_slots:
+                break
+            need = self.ex.factor_bytes(req.problem)
+            if Arena.aligned(need) > self.budget:
+                self.results[req.rid] = Result(
+                    rid=req.rid, error=f"request {req.rid} needs {need} bytes, budget "
+                                       f"{self.budget}",
+                    arrival=req.arrival if realtime else 0.0, done=time.perf_counter() - t0)
+                self._waiting = [r for r in self._waiting if r.rid != req.rid]
+                changed = True
+                continue
+            off = self._place(need)
+            if off is None:
+                break
+            key = geometry_key(req.problem)
+            entry = _Entry(key, req.problem, need, off)
+            self.cache[key] = entry
+            self.to_factor.append(entry)
+            self.factoring += 1
+            self._fresh[req.rid] = True
+            changed = True
+            self.cv.notify_all()
+        return changed
+
     def _schedule(self, t0: float, realtime: bool, threads: list) -> bool:
         """Admit fresh geometries and start evaluations that can start; True if
         anything changed."""
         changed = False
-        fresh_blocked = False
         i = 0
         while i < len(self._waiting):
             req = self._waiting[i]
-            arrival = req.arrival if realtime else 0.0
             key = geometry_key(req.problem)
             entry = self.cache.get(key)
-            if entry is None:
-                # needs new factors: memory and an engine slot, in arrival order
-                if fresh_blocked or self.factoring >= self.factor_slots:
-                    fresh_blocked = True
-                    i += 1
-                    continue
-                need = self.ex.factor_bytes(req.problem)
-                if Arena.aligned(need) > self.budget:
-                    self.results[req.rid] = Result(
-                        rid=req.rid, error=f"request {req.rid} needs {need} bytes, budget "
-                                           f"{self.budget}", arrival=arrival,
-                        done=time.perf_counter() - t0)
-                    self._waiting.pop(i)
-                    changed = True
-                    continue
-                off = self._place(need)
-                if off is None:
-                    fresh_blocked = True
-                    i += 1
-                    continue
-                entry = _Entry(key, req.problem, need, off)
-                self.cache[key] = entry
-                self.to_factor.append(entry)
-                self.factoring += 1
-                self._fresh[req.rid] = True
-                changed = True
-                self.cv.notify_all()
-                i += 1
-                continue
-            if not entry.ready or entry.users > 0 or not self.free_slots:
+            if entry is None or not entry.ready or entry.users > 0 or not self.free_slots:
                 i += 1           # parked on its geometry
                 continue
             if entry.error is not None:     # its factorisation failed
@@ -579,7 +599,12 @@ class Server:
             th.start()
             threads.append(th)
             changed = True
+        changed |= self._admit_fresh(t0, realtime)
         return changed
+
+    def engine_occupancy(self) -> float:
+        """Time-weighted mean number of geometries in the engine while it ran."""
+        return self.engine_geom_time / self.engine_time if self.engine_time > 0 else 0.0
 
     def close(self):
         with self.cv:

@@ -237,3 +237,25 @@ def test_arena_places_first_fit_and_merges_free_neighbours():
     a.release(z, 5 * 256)
     assert a.free == [(0, 2048)]             # 0..512, 512..768 and 768..2048 merged
     assert a.place(8 * 256) == 0 and a.used == 10 * 256
+
+
+def test_largest_first_order_starts_the_biggest_factorisation_first():
+    reqs = [W.Request(rid=i, arrival=0.0, problem=W.small_problem(2 + i, 4, seed=60 + i),
+                      adjoint=False) for i in range(4)]
+    for order, first in (("arrival", 0), ("largest_first", 3)):
+        ex = FakeExecutor(factor_seconds=lambda p: 0.01, round_seconds=0.001)
+        srv, out = serve(ex, reqs, realtime=False, factor_slots=1, hbm_budget=10 ** 12, order=order)
+        assert all(r.error is None for r in out)
+        assert min(out, key=lambda r: r.done).rid == first
+
+
+def test_factors_a_waiting_request_needs_are_not_evicted():
+    """With memory for two factor sets and no free evaluation slot, factors that
+    completed for a waiting request stay until it is served (no re-factoring)."""
+    reqs = [W.Request(rid=i, arrival=0.0, problem=W.small_problem(2, 4, seed=80 + i),
+                      adjoint=True) for i in range(5)]
+    ex = FakeExecutor(factor_seconds=lambda p: 0.005, eval_seconds=0.03, round_seconds=0.001)
+    one = ex.factor_bytes(reqs[0].problem)
+    _, out = serve(ex, reqs, realtime=False, eval_slots=1, hbm_budget=2 * Arena.aligned(one))
+    assert all(r.error is None for r in out)
+    assert ex.factor_calls == 5
