@@ -388,11 +388,23 @@ __global__ __launch_bounds__(256, 3) void k_gemm_sweep(MmJobs jobs, int R, int n
                                                         size_t rstride, int jline, int conjop) {
   __shared__ double2 As[MT][KC + 1];
   __shared__ double2 Bs[KC][MT + 1];
-  const int ntile_r = ceil_div(R, MT), ntile_j = ceil_div(nt * TB, MT);
-  const int per_job = ntile_r * ntile_j;
-  const int ji = blockIdx.x / per_job;
-  const int w = blockIdx.x % per_job;
-  const int rt = w / ntile_j, jt = w % ntile_j;
+  // Tiles with all MT right-hand-side rows come first (for all jobs), the
+  // partial row tile (R mod MT rows) last: a launch holds a little over two
+  // workgroups per CU, and the CUs that take a third one then take a short one.
+  const int ntile_j = ceil_div(nt * TB, MT);
+  const int nfull = R / MT;
+  const int b = blockIdx.x, nfb = jobs.n * nfull * ntile_j;
+  int ji, rt, jt;
+  if (b < nfb) {
+    ji = b / (nfull * ntile_j);
+    const int w = b - ji * nfull * ntile_j;
+    rt = w / ntile_j;
+    jt = w - rt * ntile_j;
+  } else {
+    ji = (b - nfb) / ntile_j;
+    rt = nfull;
+    jt = (b - nfb) - ji * ntile_j;
+  }
   MmJob jb = jobs.j[0];
   if (ji == 1) jb = jobs.j[1];
   const int r0 = rt * MT, j0 = jt * MT;
