@@ -348,6 +348,94 @@ int rcp_broadband_grad(int32_t count, rcp_factors* const* factors, const rcp_obj
 int rcp_width_grad(const rcp_grid* grid, const rcp_pillars* pillars, const double* grad_eps_dev,
                    double* grad_w_dev, rcp_stream stream);
 
+/* ---- 3D (Sec. "Concluding remarks") -------------------------------------
+ * curl curl E - k0^2 eps E = i k0 J on a Yee grid of nx x ny x nz cells
+ * (E_x at ((i+1/2)h, jh, kh), E_y at (ih, (j+1/2)h, kh), E_z at (ih, jh,
+ * (k+1/2)h), tangential E zero beyond the grid) with the uniaxial form of the
+ * stretched-coordinate PML (same profile as the 2D operator on every axis);
+ * A is complex symmetric.  Fields and eps are in slice order: index
+ * i n + (c ny + j) nz + k with n = 3 ny nz (x-slice i, component c).  The
+ * factorisation is the same two-ended block elimination over the x-slices
+ * (blocks of n unknowns, 33 <= n <= 65536) with sparse couplings between
+ * slices.  FP64 only.  In 3D the reciprocal average takes one solve per field
+ * component the objective reads: three for the intensity |E|^2 at a focal
+ * spot, two for the power in an output planewave mode. */
+typedef struct {
+  int32_t nx, ny, nz, npml;
+  double h, k0, pml_R;
+  int32_t pml_m;
+  const double* eps_dev;   /* 3 nx ny nz float64, slice order (device) */
+} rcp_grid3d;
+
+/* Square pillars of side widths_dev[p] centred at (centers_dev[2p],
+ * centers_dev[2p+1]) (physical coordinates, origin at the lower corner of the
+ * physical region) in the z-layers [pillar_k0, pillar_k0 + pillar_layers) (cell
+ * units, grid index), substrate below sub_layers; each E component takes the
+ * mean of eps over the h x h square around its (x, y). */
+typedef struct {
+  int32_t n;
+  const double* centers_dev;
+  const double* widths_dev;
+  double eps_bg, eps_sub, eps_pillar;
+  int32_t sub_layers, pillar_k0, pillar_layers;
+} rcp_pillars3d;
+
+/* CONCENTRATOR: F reads the three components on the edges of cell (i_f, j_f,
+ * k_f): |E|^2 there.  COLLIMATOR: the two polarisations (s, p) of the output
+ * planewave in direction (theta, azimuth) (medium index n_m) on plane k_m,
+ * w = (h^2 / area) e_pol exp(i k0 n_m sin theta (cos az x + sin az y)) on the
+ * tangential components of the physical cells. */
+typedef struct {
+  int32_t kind;
+  int32_t i_f, j_f, k_f;
+  int32_t k_m;
+  double theta, azimuth, n_m;
+} rcp_objective3d;
+
+/* Incoherent light on plane k_s (medium index n_s): ndir directions with
+ * dirs_dev[3d .. 3d+2] = (theta, azimuth, weight), the weight including the
+ * mean-square amplitude <|a|^2> of the direction; both polarisations carry
+ * the same weight and are uncorrelated.  The unit-power sheet currents are
+ * |J_s| = 2 sqrt(n_s cos theta) (normal to the plane of incidence) and
+ * |J_p| = 2 sqrt(n_s / cos theta) (along the tangential wavevector), with the
+ * phase exp(i k0 n_s sin theta (cos az x + sin az y)); b = i k0 J / h. */
+typedef struct {
+  int32_t k_s;
+  double n_s;
+  int32_t ndir;
+  const double* dirs_dev;
+} rcp_light3d;
+
+/* 3D permittivity from pillars (eps_out_dev: 3 nx ny nz float64, slice order). */
+int rcp_eps3d_from_pillars(const rcp_grid3d* grid, const rcp_pillars3d* pillars,
+                           double* eps_out_dev, rcp_stream stream);
+/* Bytes of the caller buffer rcp_factor3d needs (0 for an invalid grid). */
+size_t rcp_factor3d_bytes(const rcp_grid3d* grid);
+/* Assemble and factor; waits for the stream once (pivot check, RCP_ESINGULAR). */
+int rcp_factor3d(const rcp_grid3d* grid, void* buf_dev, size_t buf_bytes, rcp_stream stream,
+                 rcp_factors** out);
+/* x = A^{-1} b, or A^{-dag} b = conj(A)^{-1} b when conj_transpose != 0 (nx n
+ * complex128 each, slice order, not aliased). */
+int rcp_solve3d(const rcp_factors* f, const void* b_dev, void* x_dev, int32_t conj_transpose,
+                rcp_stream stream);
+/* Workspace of the two 3D averages (256-byte aligned). */
+size_t rcp_average3d_work_bytes(const rcp_factors* f, const rcp_objective3d* obj,
+                                const rcp_light3d* light);
+/* Eq. 7 in 3D: one reciprocal solve z_c = A^{-dag} w_c per component the
+ * objective reads, then F = sum_c v_c^dag W v_c on the incidence plane with
+ * W = sum_d weight_d (b_s b_s^dag + b_p b_p^dag), evaluated as
+ * sum_c sum_d weight_d (|b_s^dag v_c|^2 + |b_p^dag v_c|^2).  F_dev: one float64. */
+int rcp_reciprocal_average3d(const rcp_factors* f, const rcp_objective3d* obj,
+                             const rcp_light3d* light, double* F_dev, void* work_dev,
+                             size_t work_bytes, rcp_stream stream);
+/* Eq. 6 in 3D: one forward solve per direction and polarisation (2 ndir),
+ * F = sum_d weight_d sum_pol sum_c |w_c^dag E_(d,pol)|^2.  per_dev (optional,
+ * 2 ndir float64): the value of each (direction, polarisation).  Waits for the
+ * stream once to read the directions. */
+int rcp_brute_force_average3d(const rcp_factors* f, const rcp_objective3d* obj,
+                              const rcp_light3d* light, double* F_dev, double* per_dev,
+                              void* work_dev, size_t work_bytes, rcp_stream stream);
+
 /* Releases the host handle only; buf_dev stays with the caller. */
 void rcp_factors_release(rcp_factors* f);
 

@@ -44,6 +44,29 @@ class Light(C.Structure):
                 ("th1", C.c_double), ("th2", C.c_double), ("symbol_dev", C.c_void_p)]
 
 
+class Grid3D(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("npml", C.c_int32),
+                ("h", C.c_double), ("k0", C.c_double), ("pml_R", C.c_double),
+                ("pml_m", C.c_int32), ("eps_dev", C.c_void_p)]
+
+
+class Pillars3D(C.Structure):
+    _fields_ = [("n", C.c_int32), ("centers_dev", C.c_void_p), ("widths_dev", C.c_void_p),
+                ("eps_bg", C.c_double), ("eps_sub", C.c_double), ("eps_pillar", C.c_double),
+                ("sub_layers", C.c_int32), ("pillar_k0", C.c_int32), ("pillar_layers", C.c_int32)]
+
+
+class Objective3D(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("i_f", C.c_int32), ("j_f", C.c_int32), ("k_f", C.c_int32),
+                ("k_m", C.c_int32), ("theta", C.c_double), ("azimuth", C.c_double),
+                ("n_m", C.c_double)]
+
+
+class Light3D(C.Structure):
+    _fields_ = [("k_s", C.c_int32), ("n_s", C.c_double), ("ndir", C.c_int32),
+                ("dirs_dev", C.c_void_p)]
+
+
 class SolveStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("rel_residual", C.c_double)]
 
@@ -100,6 +123,14 @@ def _load():
         "rcp_engine_destroy": (None, [vp]),
         "rcp_engine_add": (C.c_int, [vp, P(Grid), vp, sz, vp, P(vp)]),
         "rcp_engine_step": (C.c_int, [vp, i32, vp, P(vp), P(i32), i32, P(i32), P(i32)]),
+        "rcp_eps3d_from_pillars": (C.c_int, [P(Grid3D), P(Pillars3D), vp, vp]),
+        "rcp_factor3d_bytes": (sz, [P(Grid3D)]),
+        "rcp_factor3d": (C.c_int, [P(Grid3D), vp, sz, vp, P(vp)]),
+        "rcp_solve3d": (C.c_int, [vp, vp, vp, i32, vp]),
+        "rcp_average3d_work_bytes": (sz, [vp, P(Objective3D), P(Light3D)]),
+        "rcp_reciprocal_average3d": (C.c_int, [vp, P(Objective3D), P(Light3D), vp, vp, sz, vp]),
+        "rcp_brute_force_average3d": (C.c_int, [vp, P(Objective3D), P(Light3D), vp, vp, vp, sz,
+                                                vp]),
         "rcp_factors_release": (None, [vp]),
         "rcp_last_error": (C.c_char_p, []),
         "rcp_last_solve_stats": (C.c_int, [vp, P(SolveStats)]),

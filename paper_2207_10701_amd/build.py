@@ -15,7 +15,8 @@ CSRC = HERE / "csrc"
 INCLUDE = HERE.parent / "include"
 LIB = HERE / "librecip.so"
 
-SOURCES = ["api.hip", "assembly.hip", "factor.hip", "solve.hip", "form.hip", "dense.hip"]
+SOURCES = ["api.hip", "assembly.hip", "factor.hip", "solve.hip", "form.hip", "dense.hip",
+           "maxwell3d.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

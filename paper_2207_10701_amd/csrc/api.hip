@@ -137,6 +137,7 @@ bool in_phys_x(const rcp_factors* f, int i) { return i >= f->npml && i < f->nx -
 bool in_phys_y(const rcp_factors* f, int j) { return j >= f->npml && j < f->ny - f->npml; }
 
 int check_objective(const rcp_factors* f, const rcp_objective* o) {
+  if (f->dim3) return fail(RCP_EINVAL, "factors of a 3D grid: use the rcp_*3d calls");
   if (!o) return fail(RCP_EINVAL, "objective is NULL");
   if (o->kind == RCP_CONCENTRATOR) {
     if (!in_phys_x(f, o->i_f) || !in_phys_y(f, o->j_f))
@@ -504,6 +505,7 @@ int rcp_solve_multi_rhs(const rcp_factors* fc, int32_t nrhs, const void* B_dev, 
                         rcp_solve_stats* stats) {
   rcp_factors* f = const_cast<rcp_factors*>(fc);
   if (!f) return fail(RCP_EINVAL, "factors is NULL");
+  if (f->dim3) return fail(RCP_EINVAL, "factors of a 3D grid: use rcp_solve3d");
   if (nrhs < 1) return fail(RCP_EINVAL, "nrhs must be >= 1");
   if (!B_dev || !X_dev) return fail(RCP_EINVAL, "NULL right-hand side or solution");
   const size_t N = size_t(f->nx) * f->ny;

@@ -1836,6 +1836,37 @@ int engine_round(std::vector<EGeom>& geoms, std::vector<EChain>& chains, hipStre
   SchurJobs sj{};
   int nlook_of[MAXJ];
   double work = 0.0;
+  // 3D geometries open their blocks here: the Schur complement with the sparse
+  // slice couplings, then a step that only does the pivot work of panels 0, 1
+  Schur3dJob s3[MAXJ];
+  int n3 = 0;
+  for (int q = 0; q < nch; ++q) {
+    const EChain& x = chains[q];
+    const rcp_factors* f = geoms[x.g].f;
+    if (!f->dim3 || x.K != -2) continue;
+    const int n = f->ny, N = f->nx;
+    Schur3dJob z{};
+    z.dst = block_ptr(f, x.block);
+    z.d_idx = f->d_idx + size_t(x.block) * n * K3D_DW;
+    z.d_val = f->d_val + size_t(x.block) * n * K3D_DW;
+    z.n = n;
+    z.tiles = static_cast<int>(f->tiles);
+    if ((x.dir > 0 || x.dir == 0) && x.block > 0) {   // from block - 1: column lists of boundary block - 1
+      z.src1 = block_ptr(f, x.block - 1);
+      z.c1_idx = f->cl_idx + size_t(x.block - 1) * n * K3D_CW;
+      z.c1_val = f->cl_val + size_t(x.block - 1) * n * K3D_CW;
+    }
+    if ((x.dir < 0 || x.dir == 0) && x.block < N - 1) {   // from block + 1: row lists of boundary block
+      z.src2 = block_ptr(f, x.block + 1);
+      z.c2_idx = f->cr_idx + size_t(x.block) * n * K3D_CW;
+      z.c2_val = f->cr_val + size_t(x.block) * n * K3D_CW;
+    }
+    s3[n3++] = z;
+  }
+  if (n3 > 0) {
+    int rc = schur3d(s3, n3, s);
+    if (rc) return rc;
+  }
   for (int q = 0; q < nch; ++q) {
     const EChain& x = chains[q];
     const rcp_factors* f = geoms[x.g].f;
@@ -1854,7 +1885,12 @@ int engine_round(std::vector<EGeom>& geoms, std::vector<EChain>& chains, hipStre
     z.dst = b.X;
     z.ny = ny;
     z.tiles = tiles;
-    if (x.K == -2) {   // open: Schur complement of this block + pivot work of panels 0, 1
+    if (x.K == -2 && f->dim3) {   // Schur complement formed above: pivot work only
+      b.nlook = 2;
+      b.wgs_upd = 0;
+      b.wgs = 1;
+      work += 6.0 * cmac;
+    } else if (x.K == -2) {   // open: Schur complement of this block + pivot work of panels 0, 1
       b.open = 1;
       b.nlook = 2;
       b.wgs = 1 + ceil_div(tiles - 3, kOpenTilesPerWg);
@@ -1919,7 +1955,7 @@ int engine_round(std::vector<EGeom>& geoms, std::vector<EChain>& chains, hipStre
     GJJobs uj{};
     double uw = 0.0;
     for (int q = 0; q < nch; ++q) {
-      if (gj.j[q].open || nlook_of[q] != 1) continue;
+      if (chains[q].K == -2 || nlook_of[q] != 1) continue;
       const EChain& x = chains[q];
       const rcp_factors* f = geoms[x.g].f;
       const int nt = f->nt, k = nt - 1;
@@ -1957,9 +1993,10 @@ int engine_round(std::vector<EGeom>& geoms, std::vector<EChain>& chains, hipStre
   for (int q = 0; q < nch; ++q) {
     EChain x = chains[q];
     const GJ2Job& b = gj.j[q];
-    const bool block_done = !b.open && (b.last || nlook_of[q] == 1);
+    const bool opening = x.K == -2;
+    const bool block_done = !opening && (b.last || nlook_of[q] == 1);
     if (!block_done) {
-      x.K = b.open ? 0 : x.K + 2;
+      x.K = opening ? 0 : x.K + 2;
       next.push_back(x);
       continue;
     }

@@ -63,6 +63,20 @@ struct rcp_factors {
   // statistics of the last refined solve
   int last_iters;
   double last_residual;
+  // 3D vector operator (maxwell3d.hip): blocks are x-slices of n = 3 gy gz
+  // edge unknowns (component c, then j, k); ny holds n.  The couplings between
+  // slices are sparse, not diagonal: per slice row the entries of the
+  // diagonal block (column in the slice) and of the couplings to the next
+  // slice (by row of slice i) and from the previous one (by column of slice
+  // i+1), each a fixed number of (index, value) slots, index -1 when unused.
+  int dim3 = 0;
+  int gy = 0, gz = 0;
+  int32_t* d_idx = nullptr;
+  double2* d_val = nullptr;
+  int32_t* cr_idx = nullptr;   // A_{i,i+1}(a, .) for row a of slice i
+  double2* cr_val = nullptr;
+  int32_t* cl_idx = nullptr;   // A_{i,i+1}(., b) for column b of slice i+1
+  double2* cl_val = nullptr;
 };
 
 namespace rcp {
@@ -146,6 +160,12 @@ int engine_step(rcp_engine* e, int rounds, hipStream_t s, rcp_factors** done, in
 // u = A^{-1} f (conjop = 0) or conj(A)^{-1} f = A^{-dag} f (conjop = 1), one
 // right-hand side, f and u complex128 nx*ny, f != u.  Blocks outside
 // [nz_lo, nz_hi] of f are known to be zero.
+// out[q] = base[q] + X_{blocks[q]} g[q] (block size f->ny; base may be null),
+// for one or two blocks in one launch, by the single-RHS sweep's kernels
+// (part_area[q]: which of the two partial-sum areas a job uses).  FP64.
+int block_products(rcp_factors* f, int count, const int* blocks, const double2* const* g,
+                   const double2* const* base, double2* const* out, const int* part_area,
+                   int conjop, hipStream_t s);
 int solve_vec(rcp_factors* f, const double2* rhs, double2* u, int conjop, int nz_lo, int nz_hi,
               hipStream_t s);
 // The same for B (1..MAX_BATCH) factor sets of identical shape and precision,
@@ -161,6 +181,25 @@ int solve_multi_fp64(rcp_factors* f, int nrhs, const double2* B, const double2* 
                      double2* X, int conjop, hipStream_t s);
 int residual_norms(rcp_factors* f, const double2* b, const double2* x, double2* r, int conjop,
                    hipStream_t s, double* rnorm, double* bnorm);
+
+// maxwell3d.hip -- Schur complements of 3D blocks for the engine (chains
+// whose geometry is 3D form them here before their pivot work).  Slots per
+// slice row: in-slice entries, and entries of a coupling to a neighbour slice.
+constexpr int K3D_DW = 12;
+constexpr int K3D_CW = 4;
+struct Schur3dJob {
+  void* dst;
+  const void* src1;     // X of the previous block (left chain or middle), or null
+  const void* src2;     // X of the next block (right chain or middle), or null
+  const int32_t* d_idx;  // rows of this block's diagonal block
+  const double2* d_val;
+  const int32_t* c1_idx; // couplings to src1's slice, by row of this slice
+  const double2* c1_val;
+  const int32_t* c2_idx; // couplings to src2's slice
+  const double2* c2_val;
+  int n, tiles;
+};
+int schur3d(const Schur3dJob* jobs, int count, hipStream_t s);
 
 // form.hip
 int objective_rhs(rcp_factors* f, const rcp_objective* o, double2* w, int* nz_lo, int* nz_hi,

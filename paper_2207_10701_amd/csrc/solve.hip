@@ -745,6 +745,35 @@ int solve_vec(rcp_factors* f, const double2* rhs, double2* u, int conjop, int nz
   return solve_vec_batch(&f, 1, &rhs, &u, conjop, &nz_lo, &nz_hi, s);
 }
 
+int block_products(rcp_factors* f, int count, const int* blocks, const double2* const* g,
+                   const double2* const* base, double2* const* out, const int* part_area,
+                   int conjop, hipStream_t s) {
+  if (count < 1 || count > 2) return fail(RCP_EINVAL, "internal: one or two block products");
+  if (f->precision != RCP_FP64) return fail(RCP_EINVAL, "internal: FP64 factors only");
+  SvJobs<2> js{};
+  for (int q = 0; q < count; ++q)
+    js.j[js.n++] = SvJob{block_ptr(f, blocks[q]), out[q], base[q], g[q], nullptr, nullptr,
+                         nullptr, nullptr, f->part[part_area[q]]};
+  const int nt = f->nt, ny = f->ny;
+  KTimer kt(K_GEMV, s, double(js.n) * f->tiles * TB * TB * sizeof(double2));
+  if (nt <= GEMV_NT_MAX) {
+    const dim3 grid(4 * nt * js.n);
+    switch ((nt + 7) / 8) {
+      case 1: k_gemv<double, 1, 2><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+      case 2: k_gemv<double, 2, 2><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+      default: k_gemv<double, 3, 2><<<grid, 512, 0, s>>>(js, nt, ny, conjop); break;
+    }
+    RCP_HIP(hipGetLastError());
+    return RCP_OK;
+  }
+  const int tiles = static_cast<int>(f->tiles);
+  k_symv_tiles<double, 2><<<((tiles + 3) / 4) * js.n, 256, 0, s>>>(js, ny, tiles, conjop);
+  RCP_HIP(hipGetLastError());
+  k_symv_reduce<2><<<nt * js.n, 256, 0, s>>>(js, nt, ny);
+  RCP_HIP(hipGetLastError());
+  return RCP_OK;
+}
+
 int residual_norms(rcp_factors* f, const double2* b, const double2* x, double2* r, int conjop,
                    hipStream_t s, double* rnorm, double* bnorm) {
   size_t N = size_t(f->nx) * f->ny;

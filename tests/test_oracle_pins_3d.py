@@ -20,7 +20,7 @@ import pytest
 import workloads as W
 from oracle import fdfd3d as F3
 
-CONC = W.metasurface3d("conc3d", 1, 1.5, 31, npml=4, focus_height=0.5, c_deg=20.0)
+CONC = W.metasurface3d("conc3d", 1, 1.5, 31, npml=4, focus_height=0.25, c_deg=20.0)
 COLL = W.metasurface3d("coll3d", 1, 1.5, 32, npml=4, objective=W.COLLIMATOR, monitor_y=1.25,
                        c_deg=20.0, out_theta=0.2, out_azimuth=0.7)
 

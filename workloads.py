@@ -396,11 +396,33 @@ def metasurface3d(name: str, width_wl: int, height_wl: float, seed: int, *,
     pk = sub
     top = pk + per // 2
     centers = tuple(((a + 0.5), (b + 0.5)) for a in range(width_wl) for b in range(width_wl))
+    fk = top + int(round(focus_height * per))
+    mk = npml + int(round(monitor_y * per))
+    what, k = ("focus", fk) if objective == CONCENTRATOR else ("monitor plane", mk)
+    if not npml <= k < nzp + npml:
+        raise ValueError(f"{what} at z cell {k} lies outside the physical cells "
+                         f"[{npml}, {nzp + npml})")
     return Problem3D(name=name, nx=nxp + 2 * npml, ny=nxp + 2 * npml, nz=nzp + 2 * npml,
                      npml=npml, h=h, sub_layers=sub, pillar_k0=pk, pillar_layers=per // 2,
                      pillar_centers=centers, widths=seeded_widths(len(centers), seed),
                      objective=objective,
-                     focus=(npml + nxp // 2, npml + nxp // 2, top + int(round(focus_height * per))),
-                     monitor_k=npml + int(round(monitor_y * per)), out_theta=out_theta,
+                     focus=(npml + nxp // 2, npml + nxp // 2, fk),
+                     monitor_k=mk, out_theta=out_theta,
                      out_azimuth=out_azimuth, source_k=npml + per // 4,
                      c=math.radians(c_deg))
+
+
+def cone_directions3d(p: Problem3D, n_theta: int, n_az: int):
+    """The incident light of a 3D cone as sampled directions: polar angles at the
+    Gauss-Legendre nodes of [0, c] (weighted by sin theta, the solid angle),
+    azimuths evenly spaced over the circle; each weight includes the uniform
+    mean-square amplitude 1 / Omega, Omega = 2 pi (1 - cos c).  Returns
+    (thetas, azimuths, weights) of n_theta * n_az directions."""
+    x, w = np.polynomial.legendre.leggauss(n_theta)
+    th = 0.5 * p.c * (x + 1.0)
+    wt = 0.5 * p.c * w * np.sin(th)
+    az = 2.0 * math.pi * np.arange(n_az) / n_az
+    T, A = np.meshgrid(th, az, indexing="ij")
+    Wt = np.outer(wt, np.full(n_az, 2.0 * math.pi / n_az))
+    omega = 2.0 * math.pi * (1.0 - math.cos(p.c))
+    return T.ravel(), A.ravel(), Wt.ravel() / omega
