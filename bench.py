@@ -69,9 +69,9 @@ DESCR = {
 # for the kernel source it was measured on: reported when factor.hip still has
 # this hash.
 TRAFFIC = {"config": "config2", "batch": 8,
-           "sha256": "e1028bf2792498d6f320f140a3eb45b6f84bbc5000c5fefbaa64f0a71716751b",
-           "fetch_bytes": 212189500,     # 103611.0 KiB FETCH_SIZE x 1.99995
-           "write_bytes": 156782592}    # 153108.0 KiB WRITE_SIZE x 1.00000
+           "sha256": "5855cde44615b08c2ca963cadd59df072035a10f96ad42f6613391425180a561",
+           "fetch_bytes": 213067399,     # 104039.9 KiB FETCH_SIZE x 1.99994
+           "write_bytes": 156783411}    # 153108.8 KiB WRITE_SIZE x 1.00000
 
 
 def factor_source_sha256():
