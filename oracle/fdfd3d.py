@@ -33,9 +33,9 @@ Index of component c at cell (i, j, k): c N + (i ny + j) nz + k, N = nx ny nz.
 Pinned (tests/test_oracle_pins_3d.py): A = A^T and reciprocity of its inverse;
 the reciprocal form with one solve per component equal to the forward average
 over directions and both polarisations; the divergence-free displacement field
-of the curl-curl operator; the polarisation vectors.  Parity unpinned: the
-absolute scale of the unit-power sheet currents in 3D (``sheet_amplitudes``),
-which follows the derivation of the 2D constant but has no check of its own.
+of the curl-curl operator; the polarisation vectors; the absolute scale of the
+unit-power sheet currents (``sheet_amplitudes``): a full-width s or p sheet
+sends a flux of 1 per unit area to each side at 0, 20 and 40 degrees.
 """
 from __future__ import annotations
 
