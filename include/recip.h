@@ -214,7 +214,9 @@ int rcp_reciprocal_average(const rcp_factors* f, const rcp_objective* obj,
                            rcp_stream stream);
 
 /* Device workspace rcp_brute_force_average needs for nangles nodes solved
- * rhs_chunk at a time (node tables, line sources, one chunk of fields). */
+ * rhs_chunk at a time (node tables, line sources, one chunk of fields and,
+ * for rhs_chunk >= 64, 64 MiB of partial sums that balance each block
+ * product's tiles over the compute units). */
 size_t rcp_brute_force_work_bytes(const rcp_factors* f, int32_t nangles, int32_t rhs_chunk);
 
 /* a8 -- Eq. 6 by nangles-point Gauss-Legendre quadrature in theta (split evenly

@@ -105,6 +105,23 @@ void ktimer_end(void* token, hipStream_t s) {
   (void)hipEventRecord(static_cast<TimerSample*>(token)->e1, s);
 }
 
+KSample ktimer_sample(int cls, double work) {
+  KSample out;
+  if (g_timer.every <= 0) return out;
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  long long n = g_timer.launches[cls]++;
+  if (n % g_timer.every) return out;
+  TimerSample* ts = new TimerSample{cls, g_timer.get(), g_timer.get(), work};
+  if (!ts->e0 || !ts->e1) {
+    delete ts;
+    return out;
+  }
+  g_timer.pending.push_back(ts);
+  out.e0 = ts->e0;
+  out.e1 = ts->e1;
+  return out;
+}
+
 static size_t fft_capacity(int nx) {
   size_t cap = 2;
   while (cap < 2 * size_t(nx)) cap <<= 1;
@@ -787,6 +804,7 @@ size_t rcp_brute_force_work_bytes(const rcp_factors* f, int32_t nangles, int32_t
   o = align256(o + 3 * size_t(nangles) * 8);
   o = align256(o + size_t(rhs_chunk) * f->nx * 16);
   o = align256(o + size_t(rhs_chunk) * N * 16);
+  if (rhs_chunk >= 64) o = align256(o + GEMM_SPLIT_BYTES);   // k-split partial tiles of the sweep
   return o;
 }
 
@@ -815,13 +833,15 @@ int rcp_brute_force_average(const rcp_factors* fc, const rcp_objective* obj, con
   double2* fline = reinterpret_cast<double2*>(w + o);
   o = align256(o + size_t(rhs_chunk) * f->nx * 16);
   double2* U = reinterpret_cast<double2*>(w + o);
+  o = align256(o + size_t(rhs_chunk) * size_t(f->nx) * f->ny * 16);
+  double2* split = rhs_chunk >= 64 ? reinterpret_cast<double2*>(w + o) : nullptr;
   rc = gl_nodes(light, nangles, theta, wts, stream);
   if (rc) return rc;
   for (int r0 = 0; r0 < nangles; r0 += rhs_chunk) {
     int R = nangles - r0 < rhs_chunk ? nangles - r0 : rhs_chunk;
     rc = planewave_lines(f, light, theta + r0, R, fline, stream);
     if (rc) return rc;
-    rc = solve_multi_fp64(f, R, nullptr, fline, light->j_s, U, 0, stream);
+    rc = solve_multi_fp64(f, R, nullptr, fline, light->j_s, U, 0, stream, split);
     if (rc) return rc;
     rc = bf_per_angle_at(f, obj, U, R, pa, r0, stream);
     if (rc) return rc;

@@ -1549,15 +1549,15 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
     if (js.n == 0) return RCP_OK;
     int nsrc = 0;
     for (int q = 0; q < js.n; ++q) nsrc += 1 + (js.j[q].src1 != nullptr) + (js.j[q].src2 != nullptr);
-    KTimer kt(K_SCHUR, s, double(nsrc) * tiles * TB * TB * f0->elem_bytes);
+    const double sbytes = double(nsrc) * tiles * TB * TB * f0->elem_bytes;
     for (int q = 0; q < js.n; ++q) {
       js.j[q].ny = ny;
       js.j[q].tiles = static_cast<int>(tiles);
     }
     js.maxtiles = static_cast<int>(tiles);
     if (!pairs || nt < 2) {
-      k_schur<T><<<static_cast<int>(tiles * js.n), 256, 0, s>>>(js);
-      RCP_HIP(hipGetLastError());
+      RCP_HIP(klaunch(K_SCHUR, sbytes, k_schur<T>, dim3(static_cast<int>(tiles * js.n)), dim3(256), s,
+                      js));
       return RCP_OK;
     }
     GJ2Jobs gj{};
@@ -1580,8 +1580,8 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
       gj.j[gj.n++] = b;
       opened[q] = ch[q];
     }
-    k_gj2_open<T><<<map_jobs(gj), 256, 0, s>>>(gj, js);
-    RCP_HIP(hipGetLastError());
+    const int grid = map_jobs(gj);
+    RCP_HIP(klaunch(K_SCHUR, sbytes, k_gj2_open<T>, dim3(grid), dim3(256), s, gj, js));
     nopened = js.n;
     return RCP_OK;
   };
@@ -1621,9 +1621,8 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
         b.wgs = pan_wgs;
         js.j[js.n++] = b;
       }
-      KTimer kt(K_GJ_PANEL, s, nch * cmac * nt);
-      k_gj_panel<T><<<map_jobs(js), 256, 0, s>>>(js, nt);
-      RCP_HIP(hipGetLastError());
+      const int grid = map_jobs(js);
+      RCP_HIP(klaunch(K_GJ_PANEL, nch * cmac * nt, k_gj_panel<T>, dim3(grid), dim3(256), s, js, nt));
     }
     if (!pairs) {
       // one panel per launch: update k of every tile outside column k+1 fused
@@ -1639,13 +1638,12 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
           b.wgs = upd_wgs + look_wgs;
           js.j[js.n++] = b;
         }
-        KTimer kt(K_GJ_UPDATE, s, nch * cmac * double(tiles));
         const int grid = map_jobs(js);
+        const double w = nch * cmac * double(tiles);
         if (R == 1)
-          k_gj_fused<T, 1><<<grid, 256, 0, s>>>(js, nt, tiles);
+          RCP_HIP(klaunch(K_GJ_UPDATE, w, k_gj_fused<T, 1>, dim3(grid), dim3(256), s, js, nt, tiles));
         else
-          k_gj_fused<T, 2><<<grid, 256, 0, s>>>(js, nt, tiles);
-        RCP_HIP(hipGetLastError());
+          RCP_HIP(klaunch(K_GJ_UPDATE, w, k_gj_fused<T, 2>, dim3(grid), dim3(256), s, js, nt, tiles));
       }
       GJJobs js{};   // final update, negated
       for (int q = 0; q < nch; ++q) {
@@ -1655,9 +1653,9 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
         b.wgs_upd = upd_wgs;
         js.j[js.n++] = b;
       }
-      KTimer kt(K_GJ_LAST, s, nch * cmac * double(tiles - nt));
-      k_gj_update<T><<<map_jobs(js), 256, 0, s>>>(js);
-      RCP_HIP(hipGetLastError());
+      const int grid = map_jobs(js);
+      RCP_HIP(klaunch(K_GJ_LAST, nch * cmac * double(tiles - nt), k_gj_update<T>, dim3(grid), dim3(256),
+                      s, js));
       return RCP_OK;
     }
     PanelTrs tr{};
@@ -1691,19 +1689,19 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
         js.j[js.n++] = b;
       }
       if (K >= 0 || !open_done) {
-        KTimer kt(K < 0 ? K_GJ_PANEL : (last ? K_GJ_LAST : K_GJ_UPDATE), s,
-                  K < 0 ? nch * 6.0 * cmac : nch * 2.0 * cmac * double(tiles));
-        k_gj2_fused<T><<<map_jobs(js), 256, 0, s>>>(js);
-        RCP_HIP(hipGetLastError());
+        const int grid = map_jobs(js);
+        RCP_HIP(klaunch(K < 0 ? K_GJ_PANEL : (last ? K_GJ_LAST : K_GJ_UPDATE),
+                        K < 0 ? nch * 6.0 * cmac : nch * 2.0 * cmac * double(tiles), k_gj2_fused<T>,
+                        dim3(grid), dim3(256), s, js));
       }
       // row tiles of the next pair's panels; the pivot rows come from the
       // pivot work, and with two tiles per edge nothing else is left
       const int rows = nt - nlook;
       if (nlook > 0 && rows > 0) {
         for (int q = 0; q < js.n; ++q) js.j[q].wgs = rows;
-        KTimer kt(K_GJ_PANEL, s, nch * cmac * nlook * rows);
-        k_gj2_rows<T><<<map_jobs(js), 256, 0, s>>>(js);
-        RCP_HIP(hipGetLastError());
+        const int grid = map_jobs(js);
+        RCP_HIP(klaunch(K_GJ_PANEL, nch * cmac * nlook * rows, k_gj2_rows<T>, dim3(grid), dim3(256), s,
+                        js));
       }
     }
     if (nt & 1) {   // odd panel count: the last panel alone, negated
@@ -1719,9 +1717,9 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
         b.wgs_upd = upd_wgs;
         js.j[js.n++] = b;
       }
-      KTimer kt(K_GJ_LAST, s, nch * cmac * double(tiles - nt));
-      k_gj_update<T><<<map_jobs(js), 256, 0, s>>>(js);
-      RCP_HIP(hipGetLastError());
+      const int grid = map_jobs(js);
+      RCP_HIP(klaunch(K_GJ_LAST, nch * cmac * double(tiles - nt), k_gj_update<T>, dim3(grid), dim3(256),
+                      s, js));
     }
     return RCP_OK;
   };
@@ -1925,9 +1923,8 @@ int engine_round(std::vector<EGeom>& geoms, std::vector<EChain>& chains, hipStre
     sj.j[sj.n++] = z;
   }
   {
-    KTimer kt(K_ENGINE, s, work);
-    k_gj2_step<T><<<map_jobs(gj), 256, 0, s>>>(gj, sj);
-    RCP_HIP(hipGetLastError());
+    const int grid = map_jobs(gj);
+    RCP_HIP(klaunch(K_ENGINE, work, k_gj2_step<T>, dim3(grid), dim3(256), s, gj, sj));
   }
   // row tiles of the panels the step formed (outside its pivot rows)
   {
@@ -1944,9 +1941,8 @@ int engine_round(std::vector<EGeom>& geoms, std::vector<EChain>& chains, hipStre
       }
     }
     if (rj.n > 0) {
-      KTimer kt(K_ENGINE, s, rw);
-      k_gj2_rows<T><<<map_jobs(rj), 256, 0, s>>>(rj);
-      RCP_HIP(hipGetLastError());
+      const int grid = map_jobs(rj);
+      RCP_HIP(klaunch(K_ENGINE, rw, k_gj2_rows<T>, dim3(grid), dim3(256), s, rj));
     }
   }
   // odd panel counts: the last panel alone, negated, after its rows
@@ -1982,9 +1978,8 @@ int engine_round(std::vector<EGeom>& geoms, std::vector<EChain>& chains, hipStre
     if (uj.n > 0) {
       k_panel_transpose<T><<<uj.n * 2 * tr.maxnt, 256, 0, s>>>(tr);
       RCP_HIP(hipGetLastError());
-      KTimer kt(K_ENGINE, s, uw);
-      k_gj_update<T><<<map_jobs(uj), 256, 0, s>>>(uj);
-      RCP_HIP(hipGetLastError());
+      const int grid = map_jobs(uj);
+      RCP_HIP(klaunch(K_ENGINE, uw, k_gj_update<T>, dim3(grid), dim3(256), s, uj));
     }
   }
   // advance

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 #include <cstddef>
@@ -126,6 +127,25 @@ struct KTimer {
     if (tok) ktimer_end(tok, s);
   }
 };
+// A launch of one kernel that is timed when sampled: the two events are handed
+// to the launch itself (hipExtLaunchKernel), so they take the kernel's own
+// start and end and not the dispatch around it.  Launches of several kernels
+// timed as one sample keep the events bracketing them (KTimer).
+struct KSample {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+KSample ktimer_sample(int cls, double work);
+template <typename... P, typename... A>
+hipError_t klaunch(int cls, double work, void (*kernel)(P...), dim3 grid, dim3 block, hipStream_t s,
+                   A... args) {
+  const KSample t = ktimer_sample(cls, work);
+  if (t.e0) {
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, t.e0, t.e1, 0, static_cast<P>(args)...);
+  } else {
+    kernel<<<grid, block, 0, s>>>(static_cast<P>(args)...);
+  }
+  return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 // launchers (assembly.hip)
@@ -157,6 +177,10 @@ int engine_step(rcp_engine* e, int rounds, hipStream_t s, rcp_factors** done, in
                 int cap, int* ndone);
 
 // solve.hip
+// Workspace of the many-right-hand-side sweep's k-split tiles (optional): up
+// to GEMM_SPLIT_TILES partial 64 x 64 complex128 tiles.
+constexpr int GEMM_SPLIT_TILES = 1024;
+constexpr size_t GEMM_SPLIT_BYTES = size_t(GEMM_SPLIT_TILES) * 64 * 64 * 16;
 // u = A^{-1} f (conjop = 0) or conj(A)^{-1} f = A^{-dag} f (conjop = 1), one
 // right-hand side, f and u complex128 nx*ny, f != u.  Blocks outside
 // [nz_lo, nz_hi] of f are known to be zero.
@@ -178,7 +202,8 @@ int solve_vec_refined(rcp_factors* f, const double2* rhs, double2* u, int conjop
 // nrhs right-hand sides in (R, nx, ny) layout, FP64 factors.  If fline != null
 // the right-hand sides are line sources: fline[r * nx + i] on row jline.
 int solve_multi_fp64(rcp_factors* f, int nrhs, const double2* B, const double2* fline, int jline,
-                     double2* X, int conjop, hipStream_t s);
+                     double2* X, int conjop, hipStream_t s,
+                     double2* split_ws = nullptr);
 int residual_norms(rcp_factors* f, const double2* b, const double2* x, double2* r, int conjop,
                    hipStream_t s, double* rnorm, double* bnorm);
 

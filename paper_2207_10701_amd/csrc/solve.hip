@@ -311,6 +311,7 @@ struct MmJobs {
 
 constexpr int MT = 64;   // workgroup tile (rows r) x (columns j)
 constexpr int KC = 16;   // k chunk staged in LDS
+static_assert(GEMM_SPLIT_TILES * MT * MT * 16 == GEMM_SPLIT_BYTES, "split workspace size");
 
 // Staging of one k chunk: every thread fetches 4 elements of the right-hand
 // side tile (formed on the fly: f + line source - C1 v1 - C2 v2) and 4 of the
@@ -381,30 +382,50 @@ __device__ __forceinline__ void mm_store(const MmStage& st, double2 (*As)[KC + 1
   }
 }
 
+// Tile t of a sweep step: its job, row tile and column tile.  Tiles with all
+// MT right-hand-side rows come first (for all jobs), the partial row tiles
+// (R mod MT rows) last.
+__device__ __forceinline__ void gemm_tile_of(int t, int njobs, int R, int ntile_j, int* ji, int* rt,
+                                             int* jt) {
+  const int nfull = R / MT;
+  const int nfb = njobs * nfull * ntile_j;
+  if (t < nfb) {
+    *ji = t / (nfull * ntile_j);
+    const int w = t - *ji * nfull * ntile_j;
+    *rt = w / ntile_j;
+    *jt = w - *rt * ntile_j;
+  } else {
+    *ji = (t - nfb) / ntile_j;
+    *rt = nfull;
+    *jt = (t - nfb) - *ji * ntile_j;
+  }
+}
+
 // One sweep step of the many-right-hand-side solve: out = base + RHS X_i for
 // every (job, 64-row, 64-column) tile, RHS formed on the fly, X_i read from
 // its packed symmetric tiles; four waves, each a 32 x 32 quarter.
+// Workgroups b < nwhole take tile b whole.  The tiles after them (the ones that
+// would leave a few CUs a tile more than the rest) are split along k into
+// nsplit parts, workgroup nwhole + s taking part s % nsplit of tile
+// nwhole + s / nsplit; a part writes its 64 x 64 partial sum to ws[s] and
+// k_gemm_fixup adds the parts in order.
 __global__ __launch_bounds__(256, 3) void k_gemm_sweep(MmJobs jobs, int R, int nx, int ny, int nt,
-                                                        size_t rstride, int jline, int conjop) {
+                                                        size_t rstride, int jline, int conjop,
+                                                        int nwhole, int nsplit, double2* ws) {
   __shared__ double2 As[MT][KC + 1];
   __shared__ double2 Bs[KC][MT + 1];
-  // Tiles with all MT right-hand-side rows come first (for all jobs), the
-  // partial row tile (R mod MT rows) last: a launch holds a little over two
-  // workgroups per CU, and the CUs that take a third one then take a short one.
   const int ntile_j = ceil_div(nt * TB, MT);
-  const int nfull = R / MT;
-  const int b = blockIdx.x, nfb = jobs.n * nfull * ntile_j;
-  int ji, rt, jt;
-  if (b < nfb) {
-    ji = b / (nfull * ntile_j);
-    const int w = b - ji * nfull * ntile_j;
-    rt = w / ntile_j;
-    jt = w - rt * ntile_j;
-  } else {
-    ji = (b - nfb) / ntile_j;
-    rt = nfull;
-    jt = (b - nfb) - ji * ntile_j;
+  const int b = blockIdx.x;
+  const int nk = nt * TB / KC;
+  int tile = b, kc0 = 0, kc1 = nk;
+  if (b >= nwhole) {
+    const int sp = b - nwhole, part = sp % nsplit;
+    tile = nwhole + sp / nsplit;
+    kc0 = part * nk / nsplit;
+    kc1 = (part + 1) * nk / nsplit;
   }
+  int ji, rt, jt;
+  gemm_tile_of(tile, jobs.n, R, ntile_j, &ji, &rt, &jt);
   MmJob jb = jobs.j[0];
   if (ji == 1) jb = jobs.j[1];
   const int r0 = rt * MT, j0 = jt * MT;
@@ -420,14 +441,13 @@ __global__ __launch_bounds__(256, 3) void k_gemm_sweep(MmJobs jobs, int R, int n
       cre[a][b] = v4d{0, 0, 0, 0};
       cim[a][b] = v4d{0, 0, 0, 0};
     }
-  const int nk = nt * TB / KC;
   MmStage st;
-  mm_fetch(jb, st, 0, r0, j0, R, nx, ny, nt, rstride, boff, jline, conjop);
-  for (int kc = 0; kc < nk; ++kc) {
+  mm_fetch(jb, st, kc0, r0, j0, R, nx, ny, nt, rstride, boff, jline, conjop);
+  for (int kc = kc0; kc < kc1; ++kc) {
     __syncthreads();
     mm_store(st, As, Bs, kc, j0, nt);
     __syncthreads();
-    if (kc + 1 < nk) mm_fetch(jb, st, kc + 1, r0, j0, R, nx, ny, nt, rstride, boff, jline, conjop);
+    if (kc + 1 < kc1) mm_fetch(jb, st, kc + 1, r0, j0, R, nx, ny, nt, rstride, boff, jline, conjop);
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
       double2 av[2], bv[2];
@@ -448,6 +468,19 @@ __global__ __launch_bounds__(256, 3) void k_gemm_sweep(MmJobs jobs, int R, int n
       }
     }
   }
+  if (b >= nwhole) {   // a k part: the whole 64 x 64 partial sum, row-major
+    double2* P = ws + size_t(b - nwhole) * MT * MT;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int rr = 32 * wr + 16 * a + mfma_row<double>(lk, q), cc = 32 * wc + 16 * bb + lr;
+          P[rr * MT + cc] = make_double2(cre[a][bb][q], cim[a][bb][q]);
+        }
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -463,6 +496,29 @@ __global__ __launch_bounds__(256, 3) void k_gemm_sweep(MmJobs jobs, int R, int n
           jb.out[o] = v;
         }
       }
+}
+
+// out = base + the nsplit partial sums of split tile nwhole + blockIdx.x, added
+// in part order.
+__global__ __launch_bounds__(256) void k_gemm_fixup(MmJobs jobs, int R, int ny, int nt,
+                                                     size_t rstride, int nwhole, int nsplit,
+                                                     const double2* __restrict__ ws) {
+  const int ntile_j = ceil_div(nt * TB, MT);
+  int ji, rt, jt;
+  gemm_tile_of(nwhole + blockIdx.x, jobs.n, R, ntile_j, &ji, &rt, &jt);
+  MmJob jb = jobs.j[0];
+  if (ji == 1) jb = jobs.j[1];
+  const size_t boff = size_t(jb.block) * ny;
+  const double2* P = ws + size_t(blockIdx.x) * nsplit * MT * MT;
+  for (int e = threadIdx.x; e < MT * MT; e += 256) {
+    const int r = rt * MT + e / MT, j = jt * MT + e % MT;
+    if (r >= R || j >= ny) continue;
+    double2 v = P[e];
+    for (int q = 1; q < nsplit; ++q) v = cadd(v, P[size_t(q) * MT * MT + e]);
+    const size_t o = size_t(r) * rstride + boff + j;
+    if (jb.base) v = cadd(v, jb.base[o]);
+    jb.out[o] = v;
+  }
 }
 
 // A few right-hand sides (R < 64): the 64 x 64 tiles above would leave most of
@@ -842,8 +898,40 @@ int solve_vec_refined(rcp_factors* f, const double2* rhs, double2* u, int conjop
   return RCP_OK;
 }
 
+// How a sweep step's tiles are split (see k_gemm_sweep): the tiles beyond the
+// last whole round over the CUs are cut into the number of k parts (at most
+// 8, at most GEMM_SPLIT_TILES partial tiles in all) that gives the busiest CU
+// the least work, ceil(rem * parts / cus) / parts tiles.
+struct GemmSplit {
+  int nwhole, nsplit;
+};
+GemmSplit gemm_split(int tiles, int nk, bool have_ws) {
+  GemmSplit g{tiles, 1};
+  if (!have_ws) return g;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return g;
+  const int rem = tiles % cus;
+  if (rem == 0) return g;
+  int best = 1;
+  double best_load = 1.0;
+  for (int P = 2; P <= 8 && P <= nk && rem * P <= GEMM_SPLIT_TILES; ++P) {
+    const double load = double(ceil_div(rem * P, cus)) / P;
+    if (load < best_load - 1e-12) {
+      best_load = load;
+      best = P;
+    }
+  }
+  if (best > 1) {
+    g.nwhole = tiles - rem;
+    g.nsplit = best;
+  }
+  return g;
+}
+
 int solve_multi_fp64(rcp_factors* f, int R, const double2* B, const double2* fline, int jline,
-                     double2* Xo, int conjop, hipStream_t s) {
+                     double2* Xo, int conjop, hipStream_t s, double2* split_ws) {
   const int N = f->nx, ny = f->ny, nt = f->nt, m = f->m;
   const size_t rs = size_t(N) * ny;
   const int lenL = m, lenR = N - 1 - m;
@@ -854,12 +942,21 @@ int solve_multi_fp64(rcp_factors* f, int R, const double2* B, const double2* fli
   const int per_job = narrow ? ceil_div(R, 16) * 2 * nt : ceil_div(R, MT) * ceil_div(nt * TB, MT);
   auto launch = [&](MmJobs& js) -> int {
     if (js.n == 0) return RCP_OK;
-    KTimer kt(K_GEMM, s, 8.0 * js.n * double(R) * ny * ny);
+    const double w = 8.0 * js.n * double(R) * ny * ny;
     if (narrow)
-      k_mm_narrow<<<per_job * js.n, 64 * MW_WAVES, 0, s>>>(js, R, N, ny, nt, rs, jline, conjop);
-    else
-      k_gemm_sweep<<<per_job * js.n, 256, 0, s>>>(js, R, N, ny, nt, rs, jline, conjop);
-    RCP_HIP(hipGetLastError());
+      RCP_HIP(klaunch(K_GEMM, w, k_mm_narrow, dim3(per_job * js.n), dim3(64 * MW_WAVES), s, js, R, N,
+                      ny, nt, rs, jline, conjop));
+    else {
+      const int tiles = per_job * js.n;
+      const GemmSplit g = gemm_split(tiles, nt * TB / KC, split_ws != nullptr);
+      const int grid = g.nwhole + (tiles - g.nwhole) * g.nsplit;
+      RCP_HIP(klaunch(K_GEMM, w, k_gemm_sweep, dim3(grid), dim3(256), s, js, R, N, ny, nt, rs, jline,
+                      conjop, g.nwhole, g.nsplit, split_ws));
+      if (g.nwhole < tiles) {
+        k_gemm_fixup<<<tiles - g.nwhole, 256, 0, s>>>(js, R, ny, nt, rs, g.nwhole, g.nsplit, split_ws);
+        RCP_HIP(hipGetLastError());
+      }
+    }
     return RCP_OK;
   };
   // job pointers address block i inside row 0; the kernel adds r * rstride
