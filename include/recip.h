@@ -36,8 +36,9 @@
  *     library never frees caller memory.  The library owns only the small host
  *     handle returned by rcp_factor.
  *   - Every call enqueues on `stream` and returns without waiting, except
- *     where stated (rcp_factor waits once to check pivot health; refined
- *     solves wait once per refinement step to test convergence).
+ *     where stated (rcp_factor and rcp_factor_batch wait once to read the
+ *     pivot check, which rcp_factor_batch_async leaves on the device;
+ *     refined solves wait once per refinement step to test convergence).
  *   - Calls that use the same rcp_factors must be ordered on one stream: they
  *     share work vectors inside the factor buffer.
  *   - Return value: 0 on success, or a negative RCP_E* code; the message of
@@ -148,7 +149,8 @@ size_t rcp_factor_bytes(const rcp_grid* grid, int32_t precision);
  * RCP_FP32_REFINED).  buf_dev: caller buffer of at least
  * rcp_factor_bytes(grid, precision) bytes, 256-byte aligned; it must stay
  * alive and untouched while *out is used.  Waits for the stream once at the
- * end to check pivots (RCP_ESINGULAR names the first bad block). */
+ * end to read the device pivot check (RCP_ESINGULAR names the first bad
+ * block); rcp_factor_batch_async does not wait. */
 int rcp_factor(const rcp_grid* grid, int32_t precision, void* buf_dev, size_t buf_bytes,
                rcp_stream stream, rcp_factors** out);
 
@@ -162,6 +164,24 @@ int rcp_factor(const rcp_grid* grid, int32_t precision, void* buf_dev, size_t bu
  * handle is returned and the message names the geometry. */
 int rcp_factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, void* const* bufs,
                      size_t buf_bytes, rcp_stream stream, rcp_factors** out);
+
+/* a2 + a3 as rcp_factor_batch, enqueued only: returns the handles at once and
+ * never waits.  The pivot check runs on the device after the factorisation
+ * and leaves each set's status word (0 when every pivot passed, else 1 + the
+ * first failing panel, block-major); until it has been read the results of
+ * calls on the set are those of a factorisation that may have failed (a
+ * singular block gives infinite or NaN fields).  Argument checks and errors
+ * as rcp_factor_batch. */
+int rcp_factor_batch_async(int32_t count, const rcp_grid* grids, int32_t precision,
+                           void* const* bufs, size_t buf_bytes, rcp_stream stream,
+                           rcp_factors** out);
+/* The pivot check of set f: waits for `stream` (on which its factorisation was
+ * enqueued), then RCP_OK or RCP_ESINGULAR (naming the panel and its block). */
+int rcp_factors_status(const rcp_factors* f, rcp_stream stream);
+/* Device address of f's status word (int32, inside the factor buffer), for
+ * callers that read it on their own stream or in their own kernels; valid
+ * after the factorisation's launches on its stream.  NULL for NULL f. */
+const int32_t* rcp_factors_status_dev(const rcp_factors* f);
 
 /* a3 + a11 -- the factorisation engine: geometries of any grid size factored
  * in shared kernel launches, admitted while others are in progress

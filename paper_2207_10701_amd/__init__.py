@@ -148,6 +148,15 @@ class Factors:
         except Exception:
             pass
 
+    def status(self, stream=None) -> None:
+        """The pivot check of this set (waits for the stream; raises RecipError
+        with RCP_ESINGULAR when a pivot failed)."""
+        check(lib.rcp_factors_status(self.handle, _stream(stream)))
+
+    def status_dev(self) -> int:
+        """Device address of the set's int32 status word (0: every pivot passed)."""
+        return int(lib.rcp_factors_status_dev(self.handle) or 0)
+
     def last_solve_stats(self) -> Tuple[int, float]:
         st = _lib.SolveStats()
         check(lib.rcp_last_solve_stats(self.handle, C.byref(st)))
@@ -155,8 +164,12 @@ class Factors:
 
 
 @_on_stream
-def factor_batch(problems, eps_list, precision: int = RCP_FP64, buffers=None, stream=None):
-    """Factor 1-8 same-grid geometries in the same kernel launches (chains side by side)."""
+def factor_batch(problems, eps_list, precision: int = RCP_FP64, buffers=None, stream=None,
+                 wait: bool = True):
+    """Factor 1-8 same-grid geometries in the same kernel launches (chains side by side).
+
+    wait=False enqueues only (rcp_factor_batch_async): the pivot check stays on
+    the device until status() or status_dev() of a returned Factors reads it."""
     B = len(problems)
     if B < 1 or B > 8 or len(eps_list) != B:
         raise ValueError("factor_batch takes 1 to 8 problems with one eps map each")
@@ -168,7 +181,8 @@ def factor_batch(problems, eps_list, precision: int = RCP_FP64, buffers=None, st
     grids = (_lib.Grid * B)(*[grid_struct(p, e) for p, e in zip(problems, eps_c)])
     bufs = (C.c_void_p * B)(*[b.data_ptr() for b in buffers])
     outs = (C.c_void_p * B)()
-    check(lib.rcp_factor_batch(B, grids, precision, bufs, nbytes, _stream(stream), outs))
+    fn = lib.rcp_factor_batch if wait else lib.rcp_factor_batch_async
+    check(fn(B, grids, precision, bufs, nbytes, _stream(stream), outs))
     return [Factors._wrap(p, precision, b, C.c_void_p(h)) for p, b, h in zip(problems, buffers, outs)]
 
 

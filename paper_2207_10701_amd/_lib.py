@@ -99,6 +99,9 @@ def _load():
         "rcp_factor_bytes": (sz, [P(Grid), i32]),
         "rcp_factor": (C.c_int, [P(Grid), i32, vp, sz, vp, P(vp)]),
         "rcp_factor_batch": (C.c_int, [i32, P(Grid), i32, P(vp), sz, vp, P(vp)]),
+        "rcp_factor_batch_async": (C.c_int, [i32, P(Grid), i32, P(vp), sz, vp, P(vp)]),
+        "rcp_factors_status": (C.c_int, [vp, vp]),
+        "rcp_factors_status_dev": (vp, [vp]),
         "rcp_solve_multi_rhs": (C.c_int, [vp, i32, vp, vp, i32, f64, i32, vp, P(SolveStats)]),
         "rcp_reciprocal_average": (C.c_int, [vp, P(Objective), P(Light), vp, vp, vp, vp]),
         "rcp_brute_force_work_bytes": (sz, [vp, i32, i32]),

@@ -55,6 +55,7 @@ Layout compute_layout(int nx, int ny, int precision) {
   while (cap < 2 * size_t(nx)) cap <<= 1;
   L.off_fft = take(4 * cap * 16);
   L.off_part = take(2 * 2 * tiles * TB * 16);
+  L.off_status = take(4);
   L.total = o;
   return L;
 }
@@ -311,6 +312,7 @@ int init_factors(const rcp_grid* grid, int32_t precision, const Layout& L, void*
     f->wsP[c] = reinterpret_cast<double2*>(b + L.off_P) + c * TB * TB;
   }
   f->health = reinterpret_cast<double*>(b + L.off_health);
+  f->status = reinterpret_cast<int32_t*>(b + L.off_status);
   const size_t N = size_t(f->nx) * f->ny;
   for (int v = 0; v < NVEC; ++v) f->vec[v] = reinterpret_cast<double2*>(b + L.off_vec) + v * N;
   f->red = reinterpret_cast<double*>(b + L.off_red);
@@ -391,8 +393,11 @@ size_t rcp_factor_bytes(const rcp_grid* grid, int32_t precision) {
   return compute_layout(grid->nx, grid->ny, precision).total;
 }
 
-int rcp_factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, void* const* bufs,
-                     size_t buf_bytes, rcp_stream stream, rcp_factors** out) {
+}  // extern "C"
+
+namespace {
+int factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, void* const* bufs,
+                 size_t buf_bytes, rcp_stream stream, rcp_factors** out, bool wait) {
   if (!out || !grids || !bufs) return fail(RCP_EINVAL, "NULL argument");
   if (count < 1 || count > MAX_BATCH) return fail(RCP_EINVAL, "count must be 1 to 8");
   for (int g = 0; g < count; ++g) out[g] = nullptr;
@@ -425,7 +430,7 @@ int rcp_factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, vo
   rcp_factors* fs[MAX_BATCH] = {};   // count <= MAX_BATCH checked above
   int rc = RCP_OK;
   for (int g = 0; g < count && !rc; ++g) rc = init_factors(&grids[g], precision, L, bufs[g], stream, &fs[g]);
-  if (!rc) rc = factor_blocks(fs, count, stream);
+  if (!rc) rc = wait ? factor_blocks(fs, count, stream) : factor_blocks_async(fs, count, stream);
   if (rc) {
     for (int g = 0; g < count; ++g) delete fs[g];
     return rc;
@@ -433,6 +438,27 @@ int rcp_factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, vo
   for (int g = 0; g < count; ++g) out[g] = fs[g];
   return RCP_OK;
 }
+}  // namespace
+
+extern "C" {
+
+int rcp_factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, void* const* bufs,
+                     size_t buf_bytes, rcp_stream stream, rcp_factors** out) {
+  return factor_batch(count, grids, precision, bufs, buf_bytes, stream, out, true);
+}
+
+int rcp_factor_batch_async(int32_t count, const rcp_grid* grids, int32_t precision,
+                           void* const* bufs, size_t buf_bytes, rcp_stream stream,
+                           rcp_factors** out) {
+  return factor_batch(count, grids, precision, bufs, buf_bytes, stream, out, false);
+}
+
+int rcp_factors_status(const rcp_factors* f, rcp_stream stream) {
+  if (!f) return fail(RCP_EINVAL, "factors is NULL");
+  return read_pivot_check(f, stream, "");
+}
+
+const int32_t* rcp_factors_status_dev(const rcp_factors* f) { return f ? f->status : nullptr; }
 
 int rcp_factor(const rcp_grid* grid, int32_t precision, void* buf_dev, size_t buf_bytes,
                rcp_stream stream, rcp_factors** out) {

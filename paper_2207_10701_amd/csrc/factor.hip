@@ -1798,6 +1798,41 @@ int run_factor(rcp_factors* const* fs, int B, hipStream_t s, bool pairs) {
   return RCP_OK;
 }
 
+// The pivot check of a finished factorisation on the device: status = 0 when
+// every panel's smallest pivot modulus is finite and above tiny, else 1 + the
+// first panel (block-major) that is not.  One workgroup per factor set.
+struct PivotCheck {
+  const double* health;
+  int count;
+  double tiny;
+  int32_t* status;
+};
+struct PivotChecks {
+  PivotCheck j[MAX_BATCH];
+  int n;
+};
+__global__ __launch_bounds__(256) void k_pivot_check(PivotChecks pc) {
+  __shared__ int first[256];
+  PivotCheck c = pc.j[0];
+  for (int q = 1; q < MAX_BATCH; ++q)
+    if (q == static_cast<int>(blockIdx.x)) c = pc.j[q];
+  int f = 0x7fffffff;
+  for (int q = threadIdx.x; q < c.count; q += 256) {
+    const double h = c.health[q];
+    if (!(h > c.tiny) || !isfinite(h)) {
+      f = q;
+      break;
+    }
+  }
+  first[threadIdx.x] = f;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (static_cast<int>(threadIdx.x) < w) first[threadIdx.x] = min(first[threadIdx.x], first[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *c.status = first[0] == 0x7fffffff ? 0 : first[0] + 1;
+}
+
 // ---------------------------------------------------------------------------
 // Factorisation engine: geometries of any size share launches.  Each chain
 // (left, right, then the middle block) advances one step per round: a round
@@ -2075,19 +2110,11 @@ int engine_add(rcp_engine* e, rcp_factors* f) {
   return RCP_OK;
 }
 
-// Health of a finished geometry: the smallest pivot modulus of every panel.
-static int check_health(const rcp_factors* f, hipStream_t s) {
-  const size_t nh = size_t(f->nx) * f->nt;
-  std::vector<double> h(nh);
-  RCP_HIP(hipMemcpyAsync(h.data(), f->health, nh * sizeof(double), hipMemcpyDeviceToHost, s));
-  RCP_HIP(hipStreamSynchronize(s));
-  const double tiny = 1e-13 * 4.0 / (f->h * f->h);
-  for (size_t q = 0; q < nh; ++q)
-    if (!(h[q] > tiny) || !std::isfinite(h[q]))
-      return fail(RCP_ESINGULAR, "pivot block " + std::to_string(q % f->nt) + " of column block " +
-                                     std::to_string(q / f->nt) + " has pivot modulus " +
-                                     std::to_string(h[q]));
-  return RCP_OK;
+// Health of a finished geometry: the device pivot check, then one wait.
+static int check_health(rcp_factors* f, hipStream_t s) {
+  rcp_factors* one[1] = {f};
+  int rc = enqueue_pivot_check(one, 1, s);
+  return rc ? rc : read_pivot_check(f, s, "");
 }
 
 int engine_step(rcp_engine* e, int rounds, hipStream_t s, rcp_factors** done, int* status,
@@ -2112,7 +2139,7 @@ int engine_step(rcp_engine* e, int rounds, hipStream_t s, rcp_factors** done, in
   return RCP_OK;
 }
 
-int factor_blocks(rcp_factors* const* fs, int B, hipStream_t s) {
+int factor_blocks_async(rcp_factors* const* fs, int B, hipStream_t s) {
   if (B < 1 || B > MAXJ / 2) return fail(RCP_EINVAL, "batch of 1 to 8 geometries");
   const int prec = fs[0]->precision;
   // Batches take two panels per pass (each tile read and written once per two
@@ -2120,31 +2147,42 @@ int factor_blocks(rcp_factors* const* fs, int B, hipStream_t s) {
   // alone is bound by the chain of pivot inversions, which one panel per
   // launch keeps shortest.
   const bool pairs = B >= 2;
-  auto run = [&](rcp_factors* const* f, int n, hipStream_t st) {
-    return (prec == RCP_FP64) ? run_factor<double>(f, n, st, pairs)
-                              : run_factor<float>(f, n, st, pairs);
-  };
-  int rc = run(fs, B, s);
+  int rc = (prec == RCP_FP64) ? run_factor<double>(fs, B, s, pairs) : run_factor<float>(fs, B, s, pairs);
   if (rc) return rc;
-  // pivot health: one wait, then scan the smallest pivot modulus of every panel
-  RCP_HIP(hipStreamSynchronize(s));
+  return enqueue_pivot_check(fs, B, s);
+}
+
+int factor_blocks(rcp_factors* const* fs, int B, hipStream_t s) {
+  int rc = factor_blocks_async(fs, B, s);
+  for (int g = 0; g < B && !rc; ++g)
+    rc = read_pivot_check(fs[g], s, B > 1 ? "geometry " + std::to_string(g) + ": " : "");
+  return rc;
+}
+
+int enqueue_pivot_check(rcp_factors* const* fs, int B, hipStream_t s) {
+  if (B < 1 || B > MAX_BATCH) return fail(RCP_EINVAL, "internal: pivot check of 1 to 8 sets");
+  PivotChecks pc{};
   for (int g = 0; g < B; ++g) {
     const rcp_factors* f = fs[g];
-    const size_t nh = size_t(f->nx) * f->nt;
-    std::vector<double> h(nh);
-    RCP_HIP(hipMemcpy(h.data(), f->health, nh * sizeof(double), hipMemcpyDeviceToHost));
-    // diagonal entries are O(4/h^2); a pivot below 1e-13 of that scale is treated as singular
-    const double tiny = 1e-13 * 4.0 / (f->h * f->h);
-    for (size_t q = 0; q < nh; ++q) {
-      if (!(h[q] > tiny) || !std::isfinite(h[q])) {
-        return fail(RCP_ESINGULAR, "geometry " + std::to_string(g) + ": pivot block " +
-                                       std::to_string(q % f->nt) + " of column block " +
-                                       std::to_string(q / f->nt) + " has pivot modulus " +
-                                       std::to_string(h[q]));
-      }
-    }
+    // diagonal entries are O(4/h^2); a pivot below 1e-13 of that scale is
+    // treated as singular
+    pc.j[pc.n++] = PivotCheck{f->health, f->nx * f->nt, 1e-13 * 4.0 / (f->h * f->h), f->status};
   }
+  k_pivot_check<<<pc.n, 256, 0, s>>>(pc);
+  RCP_HIP(hipGetLastError());
   return RCP_OK;
+}
+
+int read_pivot_check(const rcp_factors* f, hipStream_t s, const std::string& prefix) {
+  int32_t st = 0;
+  RCP_HIP(hipMemcpyAsync(&st, f->status, sizeof(st), hipMemcpyDeviceToHost, s));
+  RCP_HIP(hipStreamSynchronize(s));
+  if (st == 0) return RCP_OK;
+  const int q = st - 1;
+  double h = 0.0;
+  RCP_HIP(hipMemcpy(&h, f->health + q, sizeof(h), hipMemcpyDeviceToHost));
+  return fail(RCP_ESINGULAR, prefix + "pivot block " + std::to_string(q % f->nt) + " of column block " +
+                                 std::to_string(q / f->nt) + " has pivot modulus " + std::to_string(h));
 }
 
 }  // namespace rcp

@@ -477,7 +477,7 @@ namespace {
 
 struct Layout3 {
   size_t off_X, off_eps, off_didx, off_dval, off_cridx, off_crval, off_clidx, off_clval;
-  size_t off_L, off_Q, off_P, off_health, off_vec, off_part, total;
+  size_t off_L, off_Q, off_P, off_health, off_vec, off_part, off_status, total;
 };
 
 Layout3 layout3(const rcp_grid3d* g) {
@@ -506,6 +506,7 @@ Layout3 layout3(const rcp_grid3d* g) {
   L.off_health = take(size_t(g->nx) * nt * 8);
   L.off_vec = take(4 * N * 16);
   L.off_part = take(2 * 2 * tiles * TB * 16);
+  L.off_status = take(4);
   L.total = o;
   return L;
 }
@@ -726,6 +727,7 @@ int rcp_factor3d(const rcp_grid3d* grid, void* buf_dev, size_t buf_bytes, rcp_st
     f->wsP[c] = reinterpret_cast<double2*>(b + L.off_P) + c * TB * TB;
   }
   f->health = reinterpret_cast<double*>(b + L.off_health);
+  f->status = reinterpret_cast<int32_t*>(b + L.off_status);
   const size_t N = size_t(f->nx) * n;
   for (int v = 0; v < NVEC; ++v) f->vec[v] = nullptr;
   for (int v = 0; v < 4; ++v) f->vec[v] = reinterpret_cast<double2*>(b + L.off_vec) + v * N;

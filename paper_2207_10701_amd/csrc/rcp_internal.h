@@ -31,6 +31,7 @@ struct Layout {
   size_t off_L, off_Q, off_P;     // GJ panel workspace, 4 slots for each of 2 chains
   size_t off_health, off_vec, off_red, off_fft;
   size_t off_part;                // per-tile partial sums of the vector sweep, 2 chains
+  size_t off_status;              // pivot check of the last factorisation (int32)
   size_t total;
 };
 
@@ -57,6 +58,7 @@ struct rcp_factors {
   void* wsQ[8];
   double2* wsP[8];
   double* health;
+  int32_t* status;            // 0: every pivot passed; else 1 + first failing panel (device)
   double2* vec[rcp::NVEC];
   double* red;
   double2* fft[4];            // symbol spectrum, work, temp, W v
@@ -166,6 +168,15 @@ int launch_width_grad(const rcp_grid* g, const rcp_pillars* p, const double* gra
 // factor.hip
 // Factor B (1..MAX_BATCH) geometries of identical shape in the same launches.
 int factor_blocks(rcp_factors* const* fs, int B, hipStream_t s);
+// The same without waiting: the factorisation and the pivot check on the
+// device (each set's status word), enqueued on s.
+int factor_blocks_async(rcp_factors* const* fs, int B, hipStream_t s);
+// Enqueues the pivot check of B finished factor sets into their status words.
+int enqueue_pivot_check(rcp_factors* const* fs, int B, hipStream_t s);
+// Waits for s and turns set f's status word into RCP_OK or RCP_ESINGULAR
+// (the message names the panel, its block and its pivot modulus); prefix
+// starts the message.
+int read_pivot_check(const rcp_factors* f, hipStream_t s, const std::string& prefix);
 // The factorisation engine (geometries of any size in shared launches, admitted
 // between rounds); see include/recip.h.
 int engine_create(int precision, rcp_engine** out);
