@@ -131,67 +131,70 @@ template <> __device__ __forceinline__ int acc_k<float>(int s, int lk) {
 
 __device__ __forceinline__ double2 cneg(double2 a) { return make_double2(-a.x, -a.y); }
 
-// Gauss-Jordan inversion of the TB x TB block in Ps (FP64), result back in Ps,
+// Gauss-Jordan inversion of the TB x TB block in A (FP64), result back in A,
 // eliminating two columns per step with the 2 x 2 diagonal block B of rows and
 // columns p, p+1 as pivot (inverted in closed form; no row exchanges):
 //   pivot rows      R <- B^{-1} R,       their pivot columns <- B^{-1}
 //   other rows r    m_r <- m_r - F_r B^{-1} R,   their pivot columns <- -F_r B^{-1}
 // with F_r = (m_rp, m_r,p+1).  256 threads; thread owns row r, columns
-// c0..c0+3 in registers; pivot rows/columns are exchanged through
-// double-buffered LDS, one barrier per step.  Returns min |det B|^(1/2).
-__device__ double invert_pivot_block(double2 (*Ps)[TB + 1], double2 (*xr)[TB],
-                                     double2 (*xc)[TB]) {
+// c0..c0+3, kept in registers.  The block lives in A and W in turn: a step
+// reads everything it needs from one (the pivot block, its row's pivot
+// columns, its columns of the pivot rows, all at once), writes its four
+// values to the other, then one barrier; sixteen steps end in A (a loop, not
+// unrolled: the steps would hold registers the update path of the same
+// kernels needs).  Returns min |det B|^(1/2).
+__device__ __forceinline__ void pivot_step(int P, double2 (&m)[4], const double2 (*S)[TB + 1],
+                                           double2 (*D)[TB + 1], int r, int c0, double& mindet2) {
+  const double2 a = S[P][P], bb = S[P][P + 1], cc = S[P + 1][P], d = S[P + 1][P + 1];
+  const double2 f0 = S[r][P], f1 = S[r][P + 1];
+  double2 q0[4], q1[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    q0[c] = S[P][c0 + c];
+    q1[c] = S[P + 1][c0 + c];
+  }
+  const double2 det = csub(cmul(a, d), cmul(bb, cc));
+  const double dd = det.x * det.x + det.y * det.y;
+  mindet2 = (dd < mindet2 || dd != dd) ? dd : mindet2;
+  const double rd = recip_pos(dd);
+  const double2 idet = make_double2(det.x * rd, -det.y * rd);
+  const double2 i00 = cmul(d, idet), i01 = cneg(cmul(bb, idet)), i10 = cneg(cmul(cc, idet)),
+                i11 = cmul(a, idet);
+  const bool r0 = (r == P), r1 = (r == P + 1);
+  const double2 g0 = cadd(cmul(f0, i00), cmul(f1, i10));
+  const double2 g1 = cadd(cmul(f0, i01), cmul(f1, i11));
+  const double2 b0 = r0 ? cneg(i00) : r1 ? cneg(i10) : g0;
+  const double2 b1 = r0 ? cneg(i01) : r1 ? cneg(i11) : g1;
+  const bool keep = !(r0 || r1);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int col = c0 + c;
+    double2 v = keep ? m[c] : make_double2(0.0, 0.0);
+    v = csub(v, cmul(b0, q0[c]));
+    v = csub(v, cmul(b1, q1[c]));
+    m[c] = (col == P) ? cneg(b0) : (col == P + 1) ? cneg(b1) : v;
+    D[r][col] = m[c];
+  }
+  __syncthreads();
+}
+
+__device__ double invert_pivot_block(double2 (*A)[TB + 1], double2 (*W)[TB + 1]) {
+  static_assert((TB / 2) % 2 == 0, "an even number of steps ends in A");
   const int tid = threadIdx.x;
   const int r = tid >> 3, c0 = (tid & 7) * 4;
   double2 m[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) m[c] = Ps[r][c0 + c];
+  for (int c = 0; c < 4; ++c) m[c] = A[r][c0 + c];
   double mindet2 = INFINITY;
-  for (int p = 0; p < TB; p += 2) {
-    const int b = (p >> 1) & 1;
-    if (r == p) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) xr[2 * b][c0 + c] = m[c];
-    }
-    if (r == p + 1) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) xr[2 * b + 1][c0 + c] = m[c];
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      if (c0 + c == p) xc[2 * b][r] = m[c];
-      if (c0 + c == p + 1) xc[2 * b + 1][r] = m[c];
-    }
-    __syncthreads();
-    const double2 a = xr[2 * b][p], bb = xr[2 * b][p + 1], cc = xr[2 * b + 1][p],
-                  d = xr[2 * b + 1][p + 1];
-    const double2 det = csub(cmul(a, d), cmul(bb, cc));
-    const double dd = det.x * det.x + det.y * det.y;
-    mindet2 = (dd < mindet2 || dd != dd) ? dd : mindet2;
-    const double rd = recip_pos(dd);
-    const double2 idet = make_double2(det.x * rd, -det.y * rd);
-    const double2 i00 = cmul(d, idet), i01 = cneg(cmul(bb, idet)), i10 = cneg(cmul(cc, idet)),
-                  i11 = cmul(a, idet);
-    const bool r0 = (r == p), r1 = (r == p + 1);
-    const double2 f0 = xc[2 * b][r], f1 = xc[2 * b + 1][r];
-    const double2 g0 = cadd(cmul(f0, i00), cmul(f1, i10));
-    const double2 g1 = cadd(cmul(f0, i01), cmul(f1, i11));
-    const double2 b0 = r0 ? cneg(i00) : r1 ? cneg(i10) : g0;
-    const double2 b1 = r0 ? cneg(i01) : r1 ? cneg(i11) : g1;
-    const bool keep = !(r0 || r1);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int col = c0 + c;
-      double2 v = keep ? m[c] : make_double2(0.0, 0.0);
-      v = csub(v, cmul(b0, xr[2 * b][col]));
-      v = csub(v, cmul(b1, xr[2 * b + 1][col]));
-      m[c] = (col == p) ? cneg(b0) : (col == p + 1) ? cneg(b1) : v;
-    }
+  double2 (*S)[TB + 1] = A;
+  double2 (*D)[TB + 1] = W;
+#pragma unroll 1
+  for (int P = 0; P < TB; P += 2) {
+    pivot_step(P, m, S, D, r, c0, mindet2);
+    double2 (*t)[TB + 1] = S;
+    S = D;
+    D = t;
   }
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < 4; ++c) Ps[r][c0 + c] = m[c];
-  __syncthreads();
   return sqrt(sqrt(mindet2));   // |det B|^(1/2): same scale as a scalar pivot
 }
 
@@ -398,7 +401,7 @@ __device__ __forceinline__ void zero_acc(typename v4of<T>::t (*cre)[2],
 // forms one row tile I of L (copied out) and Q = L P.
 template <typename T>
 __device__ void panel_work(const GJJob& jb, int wg, int nt, double2 (*Ps)[TB + 1],
-                           double2 (*xrow)[TB], double2 (*xcol)[TB]) {
+                           double2 (*Ws)[TB + 1]) {
   using T2 = typename cplx<T>::t;
   using V4 = typename v4of<T>::t;
   T2* X = static_cast<T2*>(jb.X);
@@ -425,7 +428,7 @@ __device__ void panel_work(const GJJob& jb, int wg, int nt, double2 (*Ps)[TB + 1
       }
   }
   __syncthreads();
-  const double minpiv = invert_pivot_block(Ps, xrow, xcol);
+  const double minpiv = invert_pivot_block(Ps, Ws);
   if (wg == 0) {
     for (int e = tid; e < TB * TB; e += 256) jb.Pn[e] = Ps[e / TB][e % TB];
     if (tid == 0) *jb.health = minpiv;
@@ -580,7 +583,7 @@ __device__ __forceinline__ void q_row(const GJJob& jb, int I, const typename v4o
 
 template <typename T, int R>
 __device__ void lookahead_work(const GJJob& jb, int g, int nt, double2 (*Ps)[TB + 1],
-                               double2 (*xrow)[TB], double2 (*xcol)[TB]) {
+                               double2 (*Ws)[TB + 1]) {
   using T2 = typename cplx<T>::t;
   using V4 = typename v4of<T>::t;
   const T2* X = static_cast<const T2*>(jb.X);
@@ -613,7 +616,7 @@ __device__ void lookahead_work(const GJJob& jb, int g, int nt, double2 (*Ps)[TB 
           make_double2(static_cast<double>(dre[0][0][q]), static_cast<double>(dim[0][0][q]));
   }
   __syncthreads();
-  const double minpiv = invert_pivot_block(Ps, xrow, xcol);
+  const double minpiv = invert_pivot_block(Ps, Ws);
   if (g == 0) {
     for (int e = tid; e < TB * TB; e += 256) jb.Pn[e] = Ps[e / TB][e % TB];
     if (tid == 0) *jb.health = minpiv;
@@ -985,14 +988,13 @@ __device__ void pivot2_work(const GJ2Job& jb, int nt, double2 (*B1)[TB + 1],
   const int lr = lane & 15, lk = lane >> 4;
   const int qa = wave >> 1, qb = wave & 1;
   const size_t TT = size_t(TB) * TB;
-  double2 (*x3r)[TB] = reinterpret_cast<double2 (*)[TB]>(&B3[0][0]);
   // one quadrant product at a time keeps the registers of this path within
   // those of the update path
   V4 dre[1][2], dim[1][2];
   quad2<T>(jb, nt, K3, K3, dre, dim, lr, lk, qa, qb);
   quad_to_lds<T>(dre, dim, B1, lr, lk, qa, qb);
   __syncthreads();
-  const double min3 = invert_pivot_block(B1, x3r, x3r + 4);   // P3
+  const double min3 = invert_pivot_block(B1, B3);   // P3
   double2* P3 = jb.Pb + size_t(K3 & 3) * TT;
   for (int e = tid; e < TB * TB; e += 256) P3[e] = B1[e / TB][e % TB];
   if (tid == 0) jb.health[K3] = min3;
@@ -1052,8 +1054,7 @@ __device__ void pivot2_work(const GJ2Job& jb, int nt, double2 (*B1)[TB + 1],
   __syncthreads();
   quad_to_lds<T>(fre, fim, B2, lr, lk, qa, qb);
   __syncthreads();
-  double2 (*x1r)[TB] = reinterpret_cast<double2 (*)[TB]>(&B1[0][0]);
-  const double min4 = invert_pivot_block(B2, x1r, x1r + 4);   // P4
+  const double min4 = invert_pivot_block(B2, B1);   // P4
   double2* P4 = jb.Pb + size_t(K4 & 3) * TT;
   for (int e = tid; e < TB * TB; e += 256) P4[e] = B2[e / TB][e % TB];
   if (tid == 0) jb.health[K4] = min4;
@@ -1274,12 +1275,12 @@ int map_jobs(Jobs& js) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj_panel(GJJobs jobs, int nt) {
   __shared__ double2 Ps[TB][TB + 1];
-  __shared__ double2 xrow[4][TB], xcol[4][TB];
+  __shared__ double2 Ws[TB][TB + 1];
   int q, w;
   if (!xjob(jobs.x, &q, &w)) return;
   GJJob jb = pick(jobs, q);
   if (w >= jb.wgs) return;
-  panel_work<T>(jb, w, nt, Ps, xrow, xcol);
+  panel_work<T>(jb, w, nt, Ps, Ws);
 }
 
 // Update k (all tiles; negated when last) -- the final panel of a block.  The
@@ -1299,14 +1300,14 @@ __global__ __launch_bounds__(256) void k_gj_update(GJJobs jobs) {
 template <typename T, int R>
 __global__ __launch_bounds__(256, 2) void k_gj_fused(GJJobs jobs, int nt, size_t tiles) {
   __shared__ double2 Ps[TB][TB + 1];
-  __shared__ double2 xrow[4][TB], xcol[4][TB];
+  __shared__ double2 Ws[TB][TB + 1];
   const int look = jobs.j[0].wgs - jobs.j[0].wgs_upd;   // look-ahead workgroups per job
   int q, w;
   if (!xjob(jobs.x, &q, &w)) return;
   GJJob jb = pick(jobs, q);
   if (w >= jb.wgs) return;
   if (w < look)
-    lookahead_work<T, R>(jb, w, nt, Ps, xrow, xcol);
+    lookahead_work<T, R>(jb, w, nt, Ps, Ws);
   else
     update_work<T>(jb, w - look, tiles, jb.k + 1);
 }
