@@ -988,21 +988,19 @@ __device__ void pivot2_work(const GJ2Job& jb, int nt, double2 (*B1)[TB + 1],
   const int lr = lane & 15, lk = lane >> 4;
   const int qa = wave >> 1, qb = wave & 1;
   const size_t TT = size_t(TB) * TB;
-  // one quadrant product at a time keeps the registers of this path within
-  // those of the update path
-  V4 dre[1][2], dim[1][2];
+  // The three quadrants of the pivot area (K3 K3, K4 K3, K4 K4) are formed
+  // before the first inversion, so that their loads overlap one another and
+  // the inversion, not the chain of pivot work; E waits in B2, D4 in registers.
+  V4 dre[1][2], dim[1][2], ere[1][2], eim[1][2], fre[1][2], fim[1][2];
   quad2<T>(jb, nt, K3, K3, dre, dim, lr, lk, qa, qb);
+  if (two) {
+    quad2<T>(jb, nt, K4, K3, ere, eim, lr, lk, qa, qb);
+    quad2<T>(jb, nt, K4, K4, fre, fim, lr, lk, qa, qb);
+  }
   quad_to_lds<T>(dre, dim, B1, lr, lk, qa, qb);
-  __syncthreads();
-  const double min3 = invert_pivot_block(B1, B3);   // P3
-  double2* P3 = jb.Pb + size_t(K3 & 3) * TT;
-  for (int e = tid; e < TB * TB; e += 256) P3[e] = B1[e / TB][e % TB];
-  if (tid == 0) jb.health[K3] = min3;
-  if (!two) return;
-  V4 ere[1][2], eim[1][2], fre[1][2], fim[1][2];
-  quad2<T>(jb, nt, K4, K3, ere, eim, lr, lk, qa, qb);
-  quad_to_lds<T>(ere, eim, B2, lr, lk, qa, qb);
-  {   // E is row K4 of the K3 panel's L buffer
+  if (two) {
+    quad_to_lds<T>(ere, eim, B2, lr, lk, qa, qb);
+    // E is row K4 of the K3 panel's L buffer
     T2* Lt = slot_ptr<T2>(jb.Lb, K3, nt) + K4 * TT + (16 * qb) * TB + 16 * qa;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -1012,8 +1010,12 @@ __device__ void pivot2_work(const GJ2Job& jb, int nt, double2 (*B1)[TB + 1],
       Lt[lr * TB + mfma_row<T>(lk, q)] = v;
     }
   }
-  quad2<T>(jb, nt, K4, K4, fre, fim, lr, lk, qa, qb);
   __syncthreads();
+  const double min3 = invert_pivot_block(B1, B3);   // P3
+  double2* P3 = jb.Pb + size_t(K3 & 3) * TT;
+  for (int e = tid; e < TB * TB; e += 256) P3[e] = B1[e / TB][e % TB];
+  if (tid == 0) jb.health[K3] = min3;
+  if (!two) return;
   V4 qre = V4{0, 0, 0, 0}, qim = V4{0, 0, 0, 0};   // Q3_K4 = E P3, quadrant (qa, qb)
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
