@@ -69,9 +69,9 @@ DESCR = {
 # for the kernel source it was measured on: reported when factor.hip still has
 # this hash.
 TRAFFIC = {"config": "config2", "batch": 8,
-           "sha256": "5855cde44615b08c2ca963cadd59df072035a10f96ad42f6613391425180a561",
-           "fetch_bytes": 213067399,     # 104039.9 KiB FETCH_SIZE x 1.99994
-           "write_bytes": 156783411}    # 153108.8 KiB WRITE_SIZE x 1.00000
+           "sha256": "45fc15907279bfcccfe5b66c55a80bbcc9fc486e6393eb7974cc9ad82676a4ff",
+           "fetch_bytes": 212384019,     # 103705.9 KiB FETCH_SIZE x 1.99995
+           "write_bytes": 156785292}    # 153110.6 KiB WRITE_SIZE x 1.00000
 
 
 def factor_source_sha256():
@@ -219,6 +219,20 @@ def serving(args):
     log(f"serving: engine, largest first {s_lpt}, occupancy {lpt.engine_occupancy():.2f}")
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    # the same stream on complex-FP32 factors with FP64 refinement (half the
+    # factor memory per geometry, twice the matrix-core rate)
+    import paper_2207_10701_amd as rcp
+    ex32 = GpuExecutor(precision=rcp.RCP_FP32_REFINED)
+    f32 = Server(ex32, factor_slots=8, eval_slots=4, hbm_budget=budget, cache=True)
+    res_32 = f32.run(reqs, realtime=True)
+    f32.close()
+    s_32 = summarize(res_32)
+    ref = {r.rid: r.F for r in res if r.F is not None}
+    dF = [abs(r.F - ref[r.rid]) / abs(ref[r.rid]) for r in res_32
+          if r.F is not None and r.rid in ref and ref[r.rid] != 0]
+    log(f"serving: engine, FP32 refined {s_32}, occupancy {f32.engine_occupancy():.2f}")
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     seq = serve_sequential(ex, reqs, realtime=True)
     s_seq = summarize(seq)
     log(f"serving: sequential {s_seq}")
@@ -241,6 +255,12 @@ def serving(args):
                              "makespan_s": round(s_lpt["makespan_s"], 3),
                              "engine_mean_geometries": round(lpt.engine_occupancy(), 2),
                              "failed": s_lpt["failed"]},
+           "fp32_refined": {"p50_ms": round(s_32["p50_ms"], 2), "p99_ms": round(s_32["p99_ms"], 2),
+                            "evals_per_s": round(s_32["evals_per_s"], 3),
+                            "makespan_s": round(s_32["makespan_s"], 3),
+                            "engine_mean_geometries": round(f32.engine_occupancy(), 2),
+                            "max_rel_diff_F_vs_fp64": max(dF) if dF else None,
+                            "failed": s_32["failed"]},
            "peak_ledger_gb": round(conc.peak_bytes / 2 ** 30, 2),
            "failed": s_con["failed"], "errors": errors,
            "latency_note": "from arrival to result; the stream offers far more work than one GPU "
