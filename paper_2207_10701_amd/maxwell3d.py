@@ -13,7 +13,7 @@ from typing import Optional
 import torch
 
 from workloads import CONCENTRATOR, Problem3D
-from . import _lib
+from . import _lib, _on_stream
 from ._lib import RCP_COLLIMATOR, RCP_CONCENTRATOR, RecipError, check, lib
 
 
@@ -30,6 +30,7 @@ def grid_struct(p: Problem3D, eps: Optional[torch.Tensor] = None) -> _lib.Grid3D
                        eps.data_ptr() if eps is not None else None)
 
 
+@_on_stream
 def eps_from_pillars(p: Problem3D, device="cuda", stream=None) -> torch.Tensor:
     """Permittivity at the E positions, (nx, 3, ny, nz) float64."""
     centers = torch.tensor([c for xy in p.pillar_centers for c in xy] or [0.0],
@@ -47,6 +48,13 @@ class Factors3D:
     """Factored 3D operator of one geometry; owns its device buffer."""
 
     def __init__(self, p: Problem3D, eps: torch.Tensor, stream=None):
+        if stream is not None:   # temporaries belong to the stream the kernels run on
+            with torch.cuda.stream(stream):
+                self._init(p, eps, stream)
+        else:
+            self._init(p, eps, None)
+
+    def _init(self, p: Problem3D, eps: torch.Tensor, stream):
         self.problem = p
         eps = eps.to(torch.float64).contiguous()
         g = grid_struct(p, eps)
@@ -71,6 +79,7 @@ class Factors3D:
             pass
 
 
+@_on_stream
 def solve(fac: Factors3D, b: torch.Tensor, conj_transpose: bool = False, stream=None):
     b = b.to(torch.complex128).contiguous()
     x = torch.empty_like(b)
@@ -104,6 +113,7 @@ def _work(fac, o, lt, device):
     return torch.empty(need, dtype=torch.uint8, device=device), need
 
 
+@_on_stream
 def reciprocal_average(fac: Factors3D, dirs: torch.Tensor, p: Optional[Problem3D] = None,
                        stream=None) -> torch.Tensor:
     """Eq. 7 in 3D: one reciprocal solve per component the objective reads."""
@@ -117,6 +127,7 @@ def reciprocal_average(fac: Factors3D, dirs: torch.Tensor, p: Optional[Problem3D
     return F
 
 
+@_on_stream
 def brute_force_average(fac: Factors3D, dirs: torch.Tensor, p: Optional[Problem3D] = None,
                         per: bool = False, stream=None):
     """Eq. 6 in 3D: one forward solve per direction and polarisation."""

@@ -90,3 +90,22 @@ def test_3d_argument_errors(rcp):
     outside = replace(CONC, focus=(1, 1, 1))             # in the PML
     with pytest.raises(RecipError):
         M.reciprocal_average(fac, M.directions(th, az, wt), outside)
+
+
+def test_3d_wrappers_on_a_side_stream(rcp):
+    """Called with a stream outside any stream context, the 3D wrappers
+    allocate their temporaries on that stream: the same F as on the default
+    stream."""
+    import torch
+    from paper_2207_10701_amd import maxwell3d as M
+    p = COLL
+    th, az, wt = W.cone_directions3d(p, 2, 4)
+    dirs = M.directions(th, az, wt)
+    fac = M.Factors3D(p, M.eps_from_pillars(p))
+    F0 = M.reciprocal_average(fac, dirs).item()
+    s = torch.cuda.Stream()
+    eps = M.eps_from_pillars(p, stream=s)
+    fac2 = M.Factors3D(p, eps, stream=s)
+    F = M.reciprocal_average(fac2, dirs, stream=s)
+    s.synchronize()
+    assert F.item() == F0
