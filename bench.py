@@ -304,6 +304,51 @@ def serving(args):
     return out
 
 
+def threed_extra(args):
+    """The 3D vector problem (Sec. "Concluding remarks") at a size where the
+    blocks fill the GPU: 4 x 4 wavelengths of pillars, 2.5 wavelengths deep, h =
+    lambda / 8 (48 x 48 x 36 cells, n = 3 ny nz = 5184 unknowns per x-slice, 48
+    slices).  Times the factorisation (one geometry through the engine), the
+    reciprocal average of a focal spot (three solves) and the forward average
+    over a rule of 4 x 16 directions, both polarisations (128 solves)."""
+    import torch
+
+    import workloads as W
+    from paper_2207_10701_amd import maxwell3d as M
+    p3 = W.metasurface3d("bench3d", 4, 2.5, 3001, npml=8, focus_height=0.5, c_deg=20.0)
+    n = 3 * p3.ny * p3.nz
+    eps = M.eps_from_pillars(p3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fac = M.Factors3D(p3, eps)
+    torch.cuda.synchronize()
+    t_f = time.perf_counter() - t0
+    th, az, wt = W.cone_directions3d(p3, 4, 16)
+    dirs = M.directions(th, az, wt)
+    F = M.reciprocal_average(fac, dirs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        F = M.reciprocal_average(fac, dirs)
+    torch.cuda.synchronize()
+    t_rec = (time.perf_counter() - t0) / 3
+    t0 = time.perf_counter()
+    Fb = M.brute_force_average(fac, dirs)
+    torch.cuda.synchronize()
+    t_bf = time.perf_counter() - t0
+    work = 4.0 * n ** 3 * p3.nx
+    out = {"grid": [p3.nx, p3.ny, p3.nz], "unknowns_per_slice": n, "slices": p3.nx,
+           "factor_gb": round(fac.nbytes / 2 ** 30, 2), "factor_seconds": round(t_f, 4),
+           "factor_tflops_method_4n3": round(work / t_f / 1e12, 2),
+           "frac_peak_method": round(work / t_f / 1e12 / FP64_PEAK_TFLOPS, 4),
+           "reciprocal_ms": round(t_rec * 1e3, 3), "reciprocal_solves": 3,
+           "directions": len(th), "brute_force_solves": 2 * len(th),
+           "brute_force_ms": round(t_bf * 1e3, 3), "speedup_cached": round(t_bf / t_rec, 2),
+           "F": F.item(), "rel_diff_brute_force": abs(Fb.item() - F.item()) / abs(F.item())}
+    fac.release()
+    return out
+
+
 def dense_extra(args, rcp, W, p, fac, t_rec, stream):
     """Any correlation W and many outputs on cached factors.
 
@@ -422,6 +467,8 @@ def main():
     # launch back by a few microseconds: sample sparsely
     ap.add_argument("--timing-every", type=int, default=32)
     ap.add_argument("--no-extras", action="store_true", help="time the step only")
+    ap.add_argument("--no-threed", dest="threed", action="store_false",
+                    help="skip the 3D vector problem extra")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests of the serving stream (0 = skip)")
@@ -765,6 +812,11 @@ def main():
             log(f"design: {out['design']}")
     # the step's factor buffers are not needed any more: serving gets the memory
     results = fac = bufs = buf = bufsets = None
+    if not args.no_extras and args.threed:
+        import torch
+        torch.cuda.empty_cache()
+        out["threed"] = threed_extra(args)
+        log(f"3d: {out['threed']}")
     if args.serve_requests > 0:
         out["serving"] = serving(args)
         out["p50_ms"] = out["serving"]["p50_ms"]
