@@ -723,6 +723,8 @@ def main():
         # the brute force it replaces, same factors
         if p.light in (W.CONE, W.ANNULUS) and args.bf_angles > 0:
             chunk = min(args.bf_chunk, args.bf_angles)
+            # once untimed: the block-product library loads its kernels on first use
+            rcp.brute_force_average(fac, args.bf_angles, p, rhs_chunk=chunk)
             torch.cuda.synchronize()
             a.record(stream)
             Fb = rcp.brute_force_average(fac, args.bf_angles, p, rhs_chunk=chunk)

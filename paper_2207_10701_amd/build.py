@@ -30,6 +30,10 @@ FLAGS = [
 ]
 
 
+# rocBLAS: the brute-force comparison's block products are plain complex GEMMs
+LIBS = ["-lrocblas"]
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and Path(cand).exists():
@@ -40,7 +44,7 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> Path:
     tmp = LIB.with_suffix(".so.tmp")
     cmd = [hipcc(), *FLAGS, f"-I{INCLUDE}", f"-I{CSRC}",
-           *[str(CSRC / s) for s in SOURCES], "-o", str(tmp)]
+           *[str(CSRC / s) for s in SOURCES], *LIBS, "-o", str(tmp)]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -18,6 +18,11 @@
 #include <cmath>
 #include <vector>
 
+#include <limits>
+#include <mutex>
+
+#include <rocblas/rocblas.h>
+
 #include "rcp_internal.h"
 
 namespace {
@@ -898,6 +903,74 @@ int solve_vec_refined(rcp_factors* f, const double2* rhs, double2* u, int conjop
   return RCP_OK;
 }
 
+// The brute force's sweep step as a library GEMM: the right-hand sides of job
+// jb formed once (g = f + line source - C1 v1 - C2 v2, n x R column-major,
+// leading dimension ny) and X_i unpacked from its packed symmetric tiles into a
+// dense matrix (element (k, j) at k ny + j, as the tiled sweep reads it), then
+// out = base + X^T g by rocBLAS ZGEMM (base = out or none).
+__global__ __launch_bounds__(256) void k_form_rhs(MmJob jb, int R, int nx, int ny, size_t rstride,
+                                                   int jline, int conjop, double2* __restrict__ G) {
+  const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= size_t(R) * ny) return;
+  const int r = static_cast<int>(t / ny), k = static_cast<int>(t % ny);
+  const size_t q = size_t(r) * rstride + size_t(jb.block) * ny + k;
+  double2 v = make_double2(0.0, 0.0);
+  if (jb.f) v = jb.f[q];
+  if (jb.fline && k == jline) v = cadd(v, jb.fline[size_t(r) * nx + jb.block]);
+  if (jb.v1) v = csub(v, cmul(maybe_conj(jb.c1[k], conjop), jb.v1[q]));
+  if (jb.v2) v = csub(v, cmul(maybe_conj(jb.c2[k], conjop), jb.v2[q]));
+  G[t] = v;
+}
+
+__global__ __launch_bounds__(256) void k_unpack_sym(const double2* __restrict__ X, int ny, int conjop,
+                                                     double2* __restrict__ Xd) {
+  const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= size_t(ny) * ny) return;
+  const int k = static_cast<int>(t / ny), j = static_cast<int>(t % ny);
+  const int K = k / TB, J = j / TB;
+  double2 x = K >= J ? X[tile_index(K, J) * TB * TB + (k % TB) * TB + (j % TB)]
+                     : X[tile_index(J, K) * TB * TB + (j % TB) * TB + (k % TB)];
+  if (conjop) x.y = -x.y;
+  Xd[t] = x;
+}
+
+// One rocBLAS handle per device, made on first use (the library is not
+// thread-safe per handle: calls take the lock).
+constexpr int kMaxDevices = 64;
+rocblas_handle g_blas[kMaxDevices] = {};
+std::mutex g_blas_mu;
+
+int library_step(const MmJobs& js, int R, int nx, int ny, size_t rstride, int jline, int conjop,
+                 double2* ws, hipStream_t s) {
+  int dev = 0;
+  RCP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(RCP_EINVAL, "device index out of range");
+  double2* G = ws;
+  double2* Xd = ws + align256(size_t(R) * ny * 16) / 16;
+  std::lock_guard<std::mutex> lk(g_blas_mu);
+  if (!g_blas[dev] && rocblas_create_handle(&g_blas[dev]) != rocblas_status_success)
+    return fail(RCP_EHIP, "rocblas_create_handle failed");
+  rocblas_handle h = g_blas[dev];
+  if (rocblas_set_stream(h, s) != rocblas_status_success) return fail(RCP_EHIP, "rocblas_set_stream failed");
+  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+  for (int q = 0; q < js.n; ++q) {
+    const MmJob& jb = js.j[q];
+    k_form_rhs<<<static_cast<int>((size_t(R) * ny + 255) / 256), 256, 0, s>>>(jb, R, nx, ny, rstride, jline,
+                                                                             conjop, G);
+    RCP_HIP(hipGetLastError());
+    k_unpack_sym<<<static_cast<int>((size_t(ny) * ny + 255) / 256), 256, 0, s>>>(jb.X, ny, conjop, Xd);
+    RCP_HIP(hipGetLastError());
+    if (jb.base && jb.base != jb.out) return fail(RCP_EINVAL, "internal: a sweep base other than its output");
+    rocblas_double_complex* C = reinterpret_cast<rocblas_double_complex*>(jb.out + size_t(jb.block) * ny);
+    if (rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, ny, R, ny, &one,
+                      reinterpret_cast<const rocblas_double_complex*>(Xd), ny,
+                      reinterpret_cast<const rocblas_double_complex*>(G), ny, jb.base ? &one : &zero, C,
+                      static_cast<rocblas_int>(rstride)) != rocblas_status_success)
+      return fail(RCP_EHIP, "rocblas_zgemm failed");
+  }
+  return RCP_OK;
+}
+
 // How a sweep step's tiles are split (see k_gemm_sweep): the tiles beyond the
 // last whole round over the CUs are cut into the number of k parts (at most
 // 8, at most GEMM_SPLIT_TILES partial tiles in all) that gives the busiest CU
@@ -905,6 +978,8 @@ int solve_vec_refined(rcp_factors* f, const double2* rhs, double2* u, int conjop
 struct GemmSplit {
   int nwhole, nsplit;
 };
+// Workspace of library_step: the right-hand sides and the dense block.
+size_t library_ws(int R, int ny) { return align256(size_t(R) * ny * 16) + size_t(ny) * ny * 16; }
 GemmSplit gemm_split(int tiles, int nk, bool have_ws) {
   GemmSplit g{tiles, 1};
   if (!have_ws) return g;
@@ -946,7 +1021,11 @@ int solve_multi_fp64(rcp_factors* f, int R, const double2* B, const double2* fli
     if (narrow)
       RCP_HIP(klaunch(K_GEMM, w, k_mm_narrow, dim3(per_job * js.n), dim3(64 * MW_WAVES), s, js, R, N,
                       ny, nt, rs, jline, conjop));
-    else {
+    else if (split_ws && library_ws(R, ny) <= GEMM_SPLIT_BYTES &&
+             rs <= size_t(std::numeric_limits<rocblas_int>::max())) {
+      KTimer kt(K_GEMM, s, w);
+      return library_step(js, R, N, ny, rs, jline, conjop, split_ws, s);
+    } else {
       const int tiles = per_job * js.n;
       const GemmSplit g = gemm_split(tiles, nt * TB / KC, split_ws != nullptr);
       const int grid = g.nwhole + (tiles - g.nwhole) * g.nsplit;
