@@ -69,9 +69,9 @@ DESCR = {
 # for the kernel source it was measured on: reported when factor.hip still has
 # this hash.
 TRAFFIC = {"config": "config2", "batch": 8,
-           "sha256": "45fc15907279bfcccfe5b66c55a80bbcc9fc486e6393eb7974cc9ad82676a4ff",
-           "fetch_bytes": 212384019,     # 103705.9 KiB FETCH_SIZE x 1.99995
-           "write_bytes": 156785292}    # 153110.6 KiB WRITE_SIZE x 1.00000
+           "sha256": "fa324389ea7c95166488625e94f1c5f6d3e12704701f5c611f2e43fd2d12b17d",
+           "fetch_bytes": 179869975,     # 87829.7 KiB FETCH_SIZE x 1.99994
+           "write_bytes": 156775753}    # 153101.3 KiB WRITE_SIZE x 1.00000
 
 
 def factor_source_sha256():
@@ -467,6 +467,8 @@ def main():
     # launch back by a few microseconds: sample sparsely
     ap.add_argument("--timing-every", type=int, default=32)
     ap.add_argument("--no-extras", action="store_true", help="time the step only")
+    ap.add_argument("--factor-batch-only", choices=["fp64", "fp32"], default=None,
+                    help="only factor one batch of the workload's geometries (for profiles)")
     ap.add_argument("--no-threed", dest="threed", action="store_false",
                     help="skip the 3D vector problem extra")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -508,6 +510,26 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    if args.factor_batch_only:
+        # one batch of the step's geometries factored alone (a warm-up, then
+        # timed), for profiling the factorisation kernels of one precision
+        prec = rcp.RCP_FP64 if args.factor_batch_only == "fp64" else rcp.RCP_FP32_REFINED
+        B = max(1, min(8, args.batch))
+        eps_b = [rcp.eps_from_widths(p, torch.tensor(W.seeded_widths(len(p.pillar_centers), 1002 + 97 * k),
+                                                     dtype=torch.float64, device=dev), device=dev)
+                 for k in range(B)]
+        nbytes = rcp.factor_bytes(p, prec)
+        bufs = [torch.empty(nbytes, dtype=torch.uint8, device=dev) for _ in range(B)]
+        rcp.factor_batch([p] * B, eps_b, prec, buffers=bufs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rcp.factor_batch([p] * B, eps_b, prec, buffers=bufs)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        peak = FP64_PEAK_TFLOPS if prec == rcp.RCP_FP64 else FP32_PEAK_TFLOPS
+        print(json.dumps({"factor_batch_only": args.factor_batch_only, "geometries": B,
+                          "seconds": round(t, 5), **lu_rates(p, t, B, peak)}), flush=True)
+        return
     log(f"bench: {p.name} {p.nx}x{p.ny}, steps={args.steps} warmup={args.warmup}")
 
     # inputs resident in HBM before timing: B seeded geometries per step

@@ -111,6 +111,28 @@ __device__ __forceinline__ GJJob pick(const GJJobs& js, int q) {
   return jb;
 }
 
+// The factor tiles S stream through a pass once (read, updated, written back):
+// loaded and stored with the nontemporal hint, so that they do not push the
+// panel rows, which every tile of the pass reads, out of L2.
+__device__ __forceinline__ double2 load_stream(const double2* p) {
+  using v2 = double __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 load_stream(const float2* p) {
+  using v2 = float __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void store_stream(double2* p, double2 a) {
+  using v2 = double __attribute__((ext_vector_type(2)));
+  __builtin_nontemporal_store(v2{a.x, a.y}, reinterpret_cast<v2*>(p));
+}
+__device__ __forceinline__ void store_stream(float2* p, float2 a) {
+  using v2 = float __attribute__((ext_vector_type(2)));
+  __builtin_nontemporal_store(v2{a.x, a.y}, reinterpret_cast<v2*>(p));
+}
+
 // 1 / d for d > 0: hardware reciprocal estimate refined by two steps of
 // Newton's method r <- r (2 - d r).
 __device__ __forceinline__ double recip_pos(double d) {
@@ -303,7 +325,7 @@ __device__ __forceinline__ void tile_update_pipelined(typename cplx<T>::t* dst,
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) sv[a][b][q] = dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr];
+      for (int q = 0; q < 4; ++q) sv[a][b][q] = load_stream(&dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr]);
   V4 cre[2][2], cim[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -330,7 +352,7 @@ __device__ __forceinline__ void tile_update_pipelined(typename cplx<T>::t* dst,
         T2 v;
         v.x = (sv[a][b][q].x + cre[a][b][q]) * sg;
         v.y = (sv[a][b][q].y + cim[a][b][q]) * sg;
-        dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr] = v;
+        store_stream(&dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr], v);
       }
 }
 
@@ -762,7 +784,7 @@ __device__ __forceinline__ void tile_update2_pipelined(typename cplx<T>::t* dst,
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) sv[a][b][q] = dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr];
+      for (int q = 0; q < 4; ++q) sv[a][b][q] = load_stream(&dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr]);
   mma_ksteps<T>(cre, cim, a0, b0);
   load_ksteps_t(a0, b0, A0, B0, 2, lr, lk);
   mma_ksteps<T>(cre, cim, a1, b1);
@@ -786,7 +808,7 @@ __device__ __forceinline__ void tile_update2_pipelined(typename cplx<T>::t* dst,
         T2 v;
         v.x = (sv[a][b][q].x + cre[a][b][q]) * sg;
         v.y = (sv[a][b][q].y + cim[a][b][q]) * sg;
-        dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr] = v;
+        store_stream(&dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr], v);
       }
 }
 
