@@ -111,28 +111,6 @@ __device__ __forceinline__ GJJob pick(const GJJobs& js, int q) {
   return jb;
 }
 
-// The factor tiles S stream through a pass once (read, updated, written back):
-// loaded and stored with the nontemporal hint, so that they do not push the
-// panel rows, which every tile of the pass reads, out of L2.
-__device__ __forceinline__ double2 load_stream(const double2* p) {
-  using v2 = double __attribute__((ext_vector_type(2)));
-  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
-  return make_double2(v.x, v.y);
-}
-__device__ __forceinline__ float2 load_stream(const float2* p) {
-  using v2 = float __attribute__((ext_vector_type(2)));
-  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
-  return make_float2(v.x, v.y);
-}
-__device__ __forceinline__ void store_stream(double2* p, double2 a) {
-  using v2 = double __attribute__((ext_vector_type(2)));
-  __builtin_nontemporal_store(v2{a.x, a.y}, reinterpret_cast<v2*>(p));
-}
-__device__ __forceinline__ void store_stream(float2* p, float2 a) {
-  using v2 = float __attribute__((ext_vector_type(2)));
-  __builtin_nontemporal_store(v2{a.x, a.y}, reinterpret_cast<v2*>(p));
-}
-
 // 1 / d for d > 0: hardware reciprocal estimate refined by two steps of
 // Newton's method r <- r (2 - d r).
 __device__ __forceinline__ double recip_pos(double d) {

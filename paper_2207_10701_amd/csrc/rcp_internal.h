@@ -323,6 +323,28 @@ template <typename T> struct cplx;
 template <> struct cplx<double> { using t = double2; };
 template <> struct cplx<float> { using t = float2; };
 
+// Loads and stores of data that streams through a kernel once (the factor
+// tiles of a pass or of a block product), with the nontemporal hint, so that
+// they do not push data the kernel reads again (panel rows, vectors) out of L2.
+__device__ __forceinline__ double2 load_stream(const double2* p) {
+  using v2 = double __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 load_stream(const float2* p) {
+  using v2 = float __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void store_stream(double2* p, double2 a) {
+  using v2 = double __attribute__((ext_vector_type(2)));
+  __builtin_nontemporal_store(v2{a.x, a.y}, reinterpret_cast<v2*>(p));
+}
+__device__ __forceinline__ void store_stream(float2* p, float2 a) {
+  using v2 = float __attribute__((ext_vector_type(2)));
+  __builtin_nontemporal_store(v2{a.x, a.y}, reinterpret_cast<v2*>(p));
+}
+
 __device__ __forceinline__ double2 to_c128(double2 a) { return a; }
 __device__ __forceinline__ double2 to_c128(float2 a) { return make_double2(a.x, a.y); }
 template <typename T2> __device__ __forceinline__ T2 from_c128(double2 a);

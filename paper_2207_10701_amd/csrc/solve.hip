@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void k_symv_tiles(SvJobs<NJ> jobs, int ny, int
   const T2* X = static_cast<const T2*>(jb.X) + size_t(tt) * TB * TB + lane;
   T2 x[16];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) x[c] = X[c * 64];
+  for (int c = 0; c < 16; ++c) x[c] = load_stream(&X[c * 64]);
   {
     const int k = (lane < 32 ? J : I) * TB + (lane & 31);
     double2 v = make_double2(0.0, 0.0);
