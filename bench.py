@@ -69,9 +69,9 @@ DESCR = {
 # for the kernel source it was measured on: reported when factor.hip still has
 # this hash.
 TRAFFIC = {"config": "config2", "batch": 8,
-           "sha256": "fa324389ea7c95166488625e94f1c5f6d3e12704701f5c611f2e43fd2d12b17d",
-           "fetch_bytes": 179869975,     # 87829.7 KiB FETCH_SIZE x 1.99994
-           "write_bytes": 156775753}    # 153101.3 KiB WRITE_SIZE x 1.00000
+           "sha256": "2e5d8cd323c6b87d8700e9ff539f606591c30c63f04e8b19865679310aa3d024",
+           "fetch_bytes": 180101113,     # 87942.4 KiB FETCH_SIZE x 1.99994
+           "write_bytes": 156777812}    # 153103.3 KiB WRITE_SIZE x 1.00000
 
 
 def factor_source_sha256():
