@@ -69,9 +69,9 @@ DESCR = {
 # for the kernel source it was measured on: reported when factor.hip still has
 # this hash.
 TRAFFIC = {"config": "config2", "batch": 8,
-           "sha256": "2e5d8cd323c6b87d8700e9ff539f606591c30c63f04e8b19865679310aa3d024",
-           "fetch_bytes": 180101113,     # 87942.4 KiB FETCH_SIZE x 1.99994
-           "write_bytes": 156777812}    # 153103.3 KiB WRITE_SIZE x 1.00000
+           "sha256": "2aebc0bf1690c722264dfb5c7ba956d117944b0758fbbc983b911fdd1e9bef05",
+           "fetch_bytes": 179804212,     # 87797.6 KiB FETCH_SIZE x 1.99994
+           "write_bytes": 156769413}    # 153095.1 KiB WRITE_SIZE x 1.00000
 
 
 def factor_source_sha256():
@@ -117,11 +117,26 @@ def method_lu_flops(p):
 
 
 def executed_lu_flops(p):
-    """Flops the symmetric tile sweep executes: per block, nt panels each updating the
-    nt (nt + 1) / 2 packed 32 x 32 tiles with a rank-32 complex product (padded rows
-    and whole diagonal tiles included)."""
+    """Complex multiply-adds the symmetric tile sweep executes, at 8 flops each: per
+    block, nt panels each updating the nt (nt + 1) / 2 packed 32 x 32 tiles with a
+    rank-32 complex product (padded rows and whole diagonal tiles included).  The
+    matrix cores take three real products per complex one in most of them, so they
+    execute fewer real flops than this (mfma_real_pass_flops)."""
     nt = -(-p.ny // 32)
     return 8.0 * 32 ** 3 * nt * (nt * (nt + 1) // 2) * p.nx
+
+
+def mfma_real_pass_flops(nt, chains):
+    """Real flops the matrix cores execute in one two-panel pass of `chains` blocks of
+    nt x nt packed tiles: rank-64 updates in three real products per complex one
+    (6 flops per complex multiply-add) on the tiles outside columns K, K+1 and the next
+    pivot pair; rank-32 four-product updates (8 flops) on column K; the pivot work
+    (three rank-64 quadrant updates, Q3_K4, D4' and the K3 row tile of panel K4) in
+    three products.  Columns K+1 are copies."""
+    tb3 = 32.0 ** 3
+    regular = nt * (nt + 1) // 2 - nt - (nt - 1) - 3
+    per_chain = regular * 2 * 6 * tb3 + (nt - 1) * 8 * tb3 + (3 * 2 + 3) * 6 * tb3
+    return chains * per_chain
 
 
 def lu_rates(p, seconds, count=1, peak=None):
@@ -647,8 +662,15 @@ def main():
                 "traffic": measured_traffic(args.config, B),
                 "avg_launch_us": round(1e3 * upd["ms"] / max(upd["samples"], 1), 3),
                 "flops_per_launch": method_per_exec * upd["work"] / max(upd["samples"], 1),
-                "flop_count": "method: 64 columns x 4 ny^2 per chain (16 chains), "
-                              "padded rows and whole diagonal tiles not counted"}
+                "flop_count": "method: 64 columns x 4 ny^2 per chain (16 chains), 8 flops per "
+                              "complex multiply-add; padded rows and whole diagonal tiles not counted"}
+    if upd["ms"] > 0 and upd["samples"]:
+        # what the matrix cores execute: three real products per complex one
+        mfma = mfma_real_pass_flops(nt, 2 * B)
+        mfma_rate = mfma * upd["samples"] / (upd["ms"] * 1e-3) / 1e12
+        roofline["mfma_real_flops_per_launch"] = mfma
+        roofline["mfma_real_tflops"] = round(mfma_rate, 3)
+        roofline["mfma_real_frac"] = round(mfma_rate / FP64_PEAK_TFLOPS, 4)
     kernels = {}
     for name, st in kstats.items():
         if st["samples"]:

@@ -266,28 +266,47 @@ __device__ __forceinline__ void load_ksteps_t(T2 (&av)[2][2], T2 (&bv)[2][2], co
     }
 }
 
+// Complex products on the matrix cores take three real products each (Gauss):
+// a b accumulates as t1 += ar br, t2 -= ai bi, t3 += (ar + ai)(br + bi), and
+// the complex sum is (t1 + t2, t3 - t1 + t2).  A product to subtract passes
+// -a.  A quarter fewer MFMAs than the four-product form; the rounding error of
+// the imaginary part is bounded by the magnitudes of the operands rather than
+// of the parts, which is the normwise accuracy the elimination relies on.
+template <typename V4, typename T>
+__device__ __forceinline__ void cmac3(V4& t1, V4& t2, V4& t3, T ar, T ai, T br, T bi) {
+  t1 = mfma16(ar, br, t1);
+  t2 = mfma16(-ai, bi, t2);
+  t3 = mfma16(ar + ai, br + bi, t3);
+}
+
+template <typename V4>
+__device__ __forceinline__ void zero3(V4& t1, V4& t2, V4& t3) {
+  t1 = V4{0, 0, 0, 0};
+  t2 = V4{0, 0, 0, 0};
+  t3 = V4{0, 0, 0, 0};
+}
+
+// element q of the complex sum held by t1, t2, t3
+template <typename V4>
+__device__ __forceinline__ auto re3(const V4& t1, const V4& t2, int q) { return t1[q] + t2[q]; }
+template <typename V4>
+__device__ __forceinline__ auto im3(const V4& t1, const V4& t2, const V4& t3, int q) {
+  return t3[q] - t1[q] + t2[q];
+}
+
 template <typename T>
-__device__ __forceinline__ void mma_ksteps(typename v4of<T>::t (*cre)[2],
-                                           typename v4of<T>::t (*cim)[2],
+__device__ __forceinline__ void mma_ksteps(typename v4of<T>::t (*t1)[2],
+                                           typename v4of<T>::t (*t2)[2],
+                                           typename v4of<T>::t (*t3)[2],
                                            const typename cplx<T>::t (&av)[2][2],
                                            const typename cplx<T>::t (&bv)[2][2]) {
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
+  for (int s = 0; s < 2; ++s)
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const T nare = -av[a][s].x, aim = av[a][s].y, naim = -av[a][s].y;
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        cre[a][b] = mfma16(nare, bv[b][s].x, cre[a][b]);
-        cim[a][b] = mfma16(nare, bv[b][s].y, cim[a][b]);
-      }
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        cre[a][b] = mfma16(aim, bv[b][s].y, cre[a][b]);
-        cim[a][b] = mfma16(naim, bv[b][s].x, cim[a][b]);
-      }
-    }
-  }
+      for (int b = 0; b < 2; ++b)
+        cmac3(t1[a][b], t2[a][b], t3[a][b], -av[a][s].x, -av[a][s].y, bv[b][s].x, bv[b][s].y);
 }
 
 template <typename T>
@@ -304,23 +323,20 @@ __device__ __forceinline__ void tile_update_pipelined(typename cplx<T>::t* dst,
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int q = 0; q < 4; ++q) sv[a][b][q] = load_stream(&dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr]);
-  V4 cre[2][2], cim[2][2];
+  V4 t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      cre[a][b] = V4{0, 0, 0, 0};
-      cim[a][b] = V4{0, 0, 0, 0};
-    }
+    for (int b = 0; b < 2; ++b) zero3(t1[a][b], t2[a][b], t3[a][b]);
   T2 a0[2][2], b0[2][2], a1[2][2], b1[2][2];
   load_ksteps(a0, b0, A, B, 0, lr, lk);
   load_ksteps(a1, b1, A, B, 1, lr, lk);
-  mma_ksteps<T>(cre, cim, a0, b0);
+  mma_ksteps<T>(t1, t2, t3, a0, b0);
   load_ksteps(a0, b0, A, B, 2, lr, lk);
-  mma_ksteps<T>(cre, cim, a1, b1);
+  mma_ksteps<T>(t1, t2, t3, a1, b1);
   load_ksteps(a1, b1, A, B, 3, lr, lk);
-  mma_ksteps<T>(cre, cim, a0, b0);
-  mma_ksteps<T>(cre, cim, a1, b1);
+  mma_ksteps<T>(t1, t2, t3, a0, b0);
+  mma_ksteps<T>(t1, t2, t3, a1, b1);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -328,8 +344,8 @@ __device__ __forceinline__ void tile_update_pipelined(typename cplx<T>::t* dst,
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         T2 v;
-        v.x = (sv[a][b][q].x + cre[a][b][q]) * sg;
-        v.y = (sv[a][b][q].y + cim[a][b][q]) * sg;
+        v.x = (sv[a][b][q].x + re3(t1[a][b], t2[a][b], q)) * sg;
+        v.y = (sv[a][b][q].y + im3(t1[a][b], t2[a][b], t3[a][b], q)) * sg;
         store_stream(&dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr], v);
       }
 }
@@ -745,14 +761,11 @@ __device__ __forceinline__ void tile_update2_pipelined(typename cplx<T>::t* dst,
                                                        int lr, int lk) {
   using T2 = typename cplx<T>::t;
   using V4 = typename v4of<T>::t;
-  V4 cre[2][2], cim[2][2];
+  V4 t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      cre[a][b] = V4{0, 0, 0, 0};
-      cim[a][b] = V4{0, 0, 0, 0};
-    }
+    for (int b = 0; b < 2; ++b) zero3(t1[a][b], t2[a][b], t3[a][b]);
   T2 a0[2][2], b0[2][2], a1[2][2], b1[2][2];
   load_ksteps_t(a0, b0, A0, B0, 0, lr, lk);
   load_ksteps_t(a1, b1, A0, B0, 1, lr, lk);
@@ -763,20 +776,20 @@ __device__ __forceinline__ void tile_update2_pipelined(typename cplx<T>::t* dst,
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int q = 0; q < 4; ++q) sv[a][b][q] = load_stream(&dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr]);
-  mma_ksteps<T>(cre, cim, a0, b0);
+  mma_ksteps<T>(t1, t2, t3, a0, b0);
   load_ksteps_t(a0, b0, A0, B0, 2, lr, lk);
-  mma_ksteps<T>(cre, cim, a1, b1);
+  mma_ksteps<T>(t1, t2, t3, a1, b1);
   load_ksteps_t(a1, b1, A0, B0, 3, lr, lk);
-  mma_ksteps<T>(cre, cim, a0, b0);
+  mma_ksteps<T>(t1, t2, t3, a0, b0);
   load_ksteps_t(a0, b0, A1, B1, 0, lr, lk);
-  mma_ksteps<T>(cre, cim, a1, b1);
+  mma_ksteps<T>(t1, t2, t3, a1, b1);
   load_ksteps_t(a1, b1, A1, B1, 1, lr, lk);
-  mma_ksteps<T>(cre, cim, a0, b0);
+  mma_ksteps<T>(t1, t2, t3, a0, b0);
   load_ksteps_t(a0, b0, A1, B1, 2, lr, lk);
-  mma_ksteps<T>(cre, cim, a1, b1);
+  mma_ksteps<T>(t1, t2, t3, a1, b1);
   load_ksteps_t(a1, b1, A1, B1, 3, lr, lk);
-  mma_ksteps<T>(cre, cim, a0, b0);
-  mma_ksteps<T>(cre, cim, a1, b1);
+  mma_ksteps<T>(t1, t2, t3, a0, b0);
+  mma_ksteps<T>(t1, t2, t3, a1, b1);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -784,8 +797,8 @@ __device__ __forceinline__ void tile_update2_pipelined(typename cplx<T>::t* dst,
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         T2 v;
-        v.x = (sv[a][b][q].x + cre[a][b][q]) * sg;
-        v.y = (sv[a][b][q].y + cim[a][b][q]) * sg;
+        v.x = (sv[a][b][q].x + re3(t1[a][b], t2[a][b], q)) * sg;
+        v.y = (sv[a][b][q].y + im3(t1[a][b], t2[a][b], t3[a][b], q)) * sg;
         store_stream(&dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr], v);
       }
 }
@@ -876,19 +889,21 @@ __device__ __forceinline__ void quad_nt_update_t(typename v4of<T>::t& cre, typen
                                                  const typename cplx<T>::t* A,
                                                  const typename cplx<T>::t* B, int lr, int lk) {
   using T2 = typename cplx<T>::t;
+  using V4 = typename v4of<T>::t;
   T2 av[8], bv[8];
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     av[s] = A[(4 * s + lk) * TB + lr];
     bv[s] = B[(4 * s + lk) * TB + lr];
   }
+  V4 t1, t2, t3;
+  zero3(t1, t2, t3);
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const T nare = -av[s].x, aim = av[s].y, naim = -av[s].y;
-    cre = mfma16(nare, bv[s].x, cre);
-    cim = mfma16(nare, bv[s].y, cim);
-    cre = mfma16(aim, bv[s].y, cre);
-    cim = mfma16(naim, bv[s].x, cim);
+  for (int s = 0; s < 8; ++s) cmac3(t1, t2, t3, -av[s].x, -av[s].y, bv[s].x, bv[s].y);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    cre[q] += re3(t1, t2, q);
+    cim[q] += im3(t1, t2, t3, q);
   }
 }
 
@@ -951,22 +966,18 @@ __device__ __forceinline__ void q_quad_f(const typename v4of<T>::t (*cre)[2],
                                          typename cplx<T>::t* Qt, int lr, int lk, int qa, int qb) {
   using T2 = typename cplx<T>::t;
   using V4 = typename v4of<T>::t;
-  V4 qre = V4{0, 0, 0, 0}, qim = V4{0, 0, 0, 0};
+  V4 t1, t2, t3;
+  zero3(t1, t2, t3);
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const T bre = static_cast<T>(pf[s].x), bim = static_cast<T>(pf[s].y);
-    const T are = cre[s >> 2][0][s & 3], aim = cim[s >> 2][0][s & 3];
-    qre = mfma16(are, bre, qre);
-    qim = mfma16(are, bim, qim);
-    qre = mfma16(-aim, bim, qre);
-    qim = mfma16(aim, bre, qim);
-  }
+  for (int s = 0; s < 8; ++s)
+    cmac3(t1, t2, t3, cre[s >> 2][0][s & 3], cim[s >> 2][0][s & 3], static_cast<T>(pf[s].x),
+          static_cast<T>(pf[s].y));
   T2* Qb = Qt + (16 * qb) * TB + 16 * qa;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     T2 v;
-    v.x = qre[q];
-    v.y = qim[q];
+    v.x = re3(t1, t2, q);
+    v.y = im3(t1, t2, t3, q);
     Qb[lr * TB + mfma_row<T>(lk, q)] = v;
   }
 }
@@ -1016,17 +1027,22 @@ __device__ void pivot2_work(const GJ2Job& jb, int nt, double2 (*B1)[TB + 1],
   for (int e = tid; e < TB * TB; e += 256) P3[e] = B1[e / TB][e % TB];
   if (tid == 0) jb.health[K3] = min3;
   if (!two) return;
-  V4 qre = V4{0, 0, 0, 0}, qim = V4{0, 0, 0, 0};   // Q3_K4 = E P3, quadrant (qa, qb)
+  V4 qre, qim;   // Q3_K4 = E P3, quadrant (qa, qb)
+  {
+    V4 t1, t2, t3;
+    zero3(t1, t2, t3);
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const int kk = 4 * s + lk;
-    const double2 av = B2[16 * qa + lr][kk], pv = B1[kk][16 * qb + lr];
-    const T are = static_cast<T>(av.x), aim = static_cast<T>(av.y);
-    const T bre = static_cast<T>(pv.x), bim = static_cast<T>(pv.y);
-    qre = mfma16(are, bre, qre);
-    qim = mfma16(are, bim, qim);
-    qre = mfma16(-aim, bim, qre);
-    qim = mfma16(aim, bre, qim);
+    for (int s = 0; s < 8; ++s) {
+      const int kk = 4 * s + lk;
+      const double2 av = B2[16 * qa + lr][kk], pv = B1[kk][16 * qb + lr];
+      cmac3(t1, t2, t3, static_cast<T>(av.x), static_cast<T>(av.y), static_cast<T>(pv.x),
+            static_cast<T>(pv.y));
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      qre[q] = re3(t1, t2, q);
+      qim[q] = im3(t1, t2, t3, q);
+    }
   }
   {
     T2* Qt = slot_ptr<T2>(jb.Qb, K3, nt) + K4 * TT + (16 * qb) * TB + 16 * qa;
@@ -1041,17 +1057,21 @@ __device__ void pivot2_work(const GJ2Job& jb, int nt, double2 (*B1)[TB + 1],
     }
   }
   __syncthreads();
+  {   // D4' = D4 - Q3_K4 E^T
+    V4 t1, t2, t3;
+    zero3(t1, t2, t3);
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {   // D4' = D4 - Q3_K4 E^T
-    const int kk = 4 * s + lk;
-    const double2 av = B3[16 * qa + lr][kk], bv = B2[16 * qb + lr][kk];
-    const T nare = static_cast<T>(-av.x), aim = static_cast<T>(av.y),
-            naim = static_cast<T>(-av.y);
-    const T bre = static_cast<T>(bv.x), bim = static_cast<T>(bv.y);
-    fre[0][0] = mfma16(nare, bre, fre[0][0]);
-    fim[0][0] = mfma16(nare, bim, fim[0][0]);
-    fre[0][0] = mfma16(aim, bim, fre[0][0]);
-    fim[0][0] = mfma16(naim, bre, fim[0][0]);
+    for (int s = 0; s < 8; ++s) {
+      const int kk = 4 * s + lk;
+      const double2 av = B3[16 * qa + lr][kk], bv = B2[16 * qb + lr][kk];
+      cmac3(t1, t2, t3, static_cast<T>(-av.x), static_cast<T>(-av.y), static_cast<T>(bv.x),
+            static_cast<T>(bv.y));
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      fre[0][0][q] += re3(t1, t2, q);
+      fim[0][0][q] += im3(t1, t2, t3, q);
+    }
   }
   __syncthreads();
   quad_to_lds<T>(fre, fim, B2, lr, lk, qa, qb);
@@ -1160,14 +1180,17 @@ __device__ void rows2_work(const GJ2Job& jb, int I, int nt, typename cplx<T>::t 
   // here, block (1 - qb, qa) in the wave of the same qa, exchanged in LDS
   V4 hre = qb ? c4re[1][0] : c4re[0][0];
   V4 him = qb ? c4im[1][0] : c4im[0][0];
+  {
+    V4 t1, t2, t3;
+    zero3(t1, t2, t3);
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const T bre = c3re[s >> 2][0][s & 3], bim = c3im[s >> 2][0][s & 3];
-    const T nare = -qk[s].x, aim = qk[s].y, naim = -qk[s].y;
-    hre = mfma16(nare, bre, hre);
-    him = mfma16(nare, bim, him);
-    hre = mfma16(aim, bim, hre);
-    him = mfma16(naim, bre, him);
+    for (int s = 0; s < 8; ++s)
+      cmac3(t1, t2, t3, -qk[s].x, -qk[s].y, c3re[s >> 2][0][s & 3], c3im[s >> 2][0][s & 3]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      hre[q] += re3(t1, t2, q);
+      him[q] += im3(t1, t2, t3, q);
+    }
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
