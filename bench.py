@@ -69,9 +69,9 @@ DESCR = {
 # for the kernel source it was measured on: reported when factor.hip still has
 # this hash.
 TRAFFIC = {"config": "config2", "batch": 8,
-           "sha256": "2aebc0bf1690c722264dfb5c7ba956d117944b0758fbbc983b911fdd1e9bef05",
-           "fetch_bytes": 179804212,     # 87797.6 KiB FETCH_SIZE x 1.99994
-           "write_bytes": 156769413}    # 153095.1 KiB WRITE_SIZE x 1.00000
+           "sha256": "a84037293dd49ef9b3b10314606b9464cc049e46d3f103ad1196727fcb078fcc",
+           "fetch_bytes": 179870630,     # 87829.9 KiB FETCH_SIZE x 1.99994
+           "write_bytes": 156768316}    # 153094.1 KiB WRITE_SIZE x 1.00000
 
 
 def factor_source_sha256():

@@ -198,6 +198,54 @@ __device__ double invert_pivot_block(double2 (*A)[TB + 1], double2 (*W)[TB + 1])
   return sqrt(sqrt(mindet2));   // |det B|^(1/2): same scale as a scalar pivot
 }
 
+// Complex products on the matrix cores take three real products each (Gauss):
+// a b accumulates as t1 += ar br, t2 -= ai bi, t3 += (ar + ai)(br + bi), and
+// the complex sum is (t1 + t2, t3 - t1 + t2).  A product to subtract passes
+// -a.  A quarter fewer MFMAs than the four-product form; the rounding error of
+// the imaginary part is bounded by the magnitudes of the operands rather than
+// of the parts, which is the normwise accuracy the elimination relies on.
+template <typename V4, typename T>
+__device__ __forceinline__ void cmac3(V4& t1, V4& t2, V4& t3, T ar, T ai, T br, T bi) {
+  t1 = mfma16(ar, br, t1);
+  t2 = mfma16(-ai, bi, t2);
+  t3 = mfma16(ar + ai, br + bi, t3);
+}
+
+template <typename V4>
+__device__ __forceinline__ void zero3(V4& t1, V4& t2, V4& t3) {
+  t1 = V4{0, 0, 0, 0};
+  t2 = V4{0, 0, 0, 0};
+  t3 = V4{0, 0, 0, 0};
+}
+
+// element q of the complex sum held by t1, t2, t3
+template <typename V4>
+__device__ __forceinline__ auto re3(const V4& t1, const V4& t2, int q) { return t1[q] + t2[q]; }
+template <typename V4>
+__device__ __forceinline__ auto im3(const V4& t1, const V4& t2, const V4& t3, int q) {
+  return t3[q] - t1[q] + t2[q];
+}
+
+// (re, im) blocks (a, b), a in [a0, a1), b in [b0, b1), += the sums in t1, t2, t3
+template <typename T>
+__device__ __forceinline__ void fold3_blocks(typename v4of<T>::t (*re)[2], typename v4of<T>::t (*im)[2],
+                                             const typename v4of<T>::t (*t1)[2],
+                                             const typename v4of<T>::t (*t2)[2],
+                                             const typename v4of<T>::t (*t3)[2], int a0, int a1, int b0,
+                                             int b1) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      if (a < a0 || a >= a1 || b < b0 || b >= b1) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        re[a][b][q] += re3(t1[a][b], t2[a][b], q);
+        im[a][b][q] += im3(t1[a][b], t2[a][b], t3[a][b], q);
+      }
+    }
+}
+
 // acc (one 32 x 32 tile in MFMA accumulator layout) -= A B^T, with A and B
 // 32 x 32 row-major tiles; blocks (a, b) with a in [a0, a1), b in [b0, b1).
 template <typename T>
@@ -215,26 +263,24 @@ __device__ __forceinline__ void tile_nt_update(typename v4of<T>::t (*cre)[2],
       if (x >= a0 && x < a1) av[x][s] = A[(16 * x + lr) * TB + 4 * s + lk];
       if (x >= b0 && x < b1) bv[x][s] = B[(16 * x + lr) * TB + 4 * s + lk];
     }
+  using V4 = typename v4of<T>::t;
+  V4 t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) zero3(t1[a][b], t2[a][b], t3[a][b]);
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       if (a < a0 || a >= a1) continue;
-      const T nare = -av[a][s].x, aim = av[a][s].y, naim = -av[a][s].y;
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         if (b < b0 || b >= b1) continue;
-        cre[a][b] = mfma16(nare, bv[b][s].x, cre[a][b]);
-        cim[a][b] = mfma16(nare, bv[b][s].y, cim[a][b]);
-      }
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        if (b < b0 || b >= b1) continue;
-        cre[a][b] = mfma16(aim, bv[b][s].y, cre[a][b]);
-        cim[a][b] = mfma16(naim, bv[b][s].x, cim[a][b]);
+        cmac3(t1[a][b], t2[a][b], t3[a][b], -av[a][s].x, -av[a][s].y, bv[b][s].x, bv[b][s].y);
       }
     }
-  }
+  fold3_blocks<T>(cre, cim, t1, t2, t3, a0, a1, b0, b1);
 }
 
 // Trailing-update product of one tile, pipelined: acc = S - A B^T with the
@@ -264,34 +310,6 @@ __device__ __forceinline__ void load_ksteps_t(T2 (&av)[2][2], T2 (&bv)[2][2], co
       av[x][s] = A[(8 * ch + 4 * s + lk) * TB + 16 * x + lr];
       bv[x][s] = B[(8 * ch + 4 * s + lk) * TB + 16 * x + lr];
     }
-}
-
-// Complex products on the matrix cores take three real products each (Gauss):
-// a b accumulates as t1 += ar br, t2 -= ai bi, t3 += (ar + ai)(br + bi), and
-// the complex sum is (t1 + t2, t3 - t1 + t2).  A product to subtract passes
-// -a.  A quarter fewer MFMAs than the four-product form; the rounding error of
-// the imaginary part is bounded by the magnitudes of the operands rather than
-// of the parts, which is the normwise accuracy the elimination relies on.
-template <typename V4, typename T>
-__device__ __forceinline__ void cmac3(V4& t1, V4& t2, V4& t3, T ar, T ai, T br, T bi) {
-  t1 = mfma16(ar, br, t1);
-  t2 = mfma16(-ai, bi, t2);
-  t3 = mfma16(ar + ai, br + bi, t3);
-}
-
-template <typename V4>
-__device__ __forceinline__ void zero3(V4& t1, V4& t2, V4& t3) {
-  t1 = V4{0, 0, 0, 0};
-  t2 = V4{0, 0, 0, 0};
-  t3 = V4{0, 0, 0, 0};
-}
-
-// element q of the complex sum held by t1, t2, t3
-template <typename V4>
-__device__ __forceinline__ auto re3(const V4& t1, const V4& t2, int q) { return t1[q] + t2[q]; }
-template <typename V4>
-__device__ __forceinline__ auto im3(const V4& t1, const V4& t2, const V4& t3, int q) {
-  return t3[q] - t1[q] + t2[q];
 }
 
 template <typename T>
@@ -575,24 +593,20 @@ __device__ __forceinline__ void q_row(const GJJob& jb, int I, const typename v4o
                                       int lr, int lk, int qa, int qb) {
   using T2 = typename cplx<T>::t;
   using V4 = typename v4of<T>::t;
-  V4 qre = V4{0, 0, 0, 0}, qim = V4{0, 0, 0, 0};
+  V4 t1, t2, t3;
+  zero3(t1, t2, t3);
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
-    const int kk = acc_k<T>(s, lk);
-    const double2 pv = Ps[kk][16 * qb + lr];
-    const T bre = static_cast<T>(pv.x), bim = static_cast<T>(pv.y);
-    const T are = cre[s >> 2][0][s & 3], aim = cim[s >> 2][0][s & 3];
-    qre = mfma16(are, bre, qre);
-    qim = mfma16(are, bim, qim);
-    qre = mfma16(-aim, bim, qre);
-    qim = mfma16(aim, bre, qim);
+    const double2 pv = Ps[acc_k<T>(s, lk)][16 * qb + lr];
+    cmac3(t1, t2, t3, cre[s >> 2][0][s & 3], cim[s >> 2][0][s & 3], static_cast<T>(pv.x),
+          static_cast<T>(pv.y));
   }
   T2* Qb = static_cast<T2*>(jb.Qn) + size_t(I) * TB * TB + (16 * qa) * TB + 16 * qb;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     T2 v;
-    v.x = qre[q];
-    v.y = qim[q];
+    v.x = re3(t1, t2, q);
+    v.y = im3(t1, t2, t3, q);
     Qb[mfma_row<T>(lk, q) * TB + lr] = v;
   }
 }
@@ -721,6 +735,12 @@ __device__ __forceinline__ void tile_nn_update(typename v4of<T>::t (*cre)[2],
                                                const typename cplx<T>::t* B, int lr, int lk,
                                                int a0, int a1, int b0, int b1) {
   using T2 = typename cplx<T>::t;
+  using V4 = typename v4of<T>::t;
+  V4 t1[2][2], t2[2][2], t3[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) zero3(t1[a][b], t2[a][b], t3[a][b]);
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     const int kk = 4 * s + lk;
@@ -733,17 +753,14 @@ __device__ __forceinline__ void tile_nn_update(typename v4of<T>::t (*cre)[2],
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       if (a < a0 || a >= a1) continue;
-      const T nare = -av[a].x, aim = av[a].y, naim = -av[a].y;
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         if (b < b0 || b >= b1) continue;
-        cre[a][b] = mfma16(nare, bv[b].x, cre[a][b]);
-        cim[a][b] = mfma16(nare, bv[b].y, cim[a][b]);
-        cre[a][b] = mfma16(aim, bv[b].y, cre[a][b]);
-        cim[a][b] = mfma16(naim, bv[b].x, cim[a][b]);
+        cmac3(t1[a][b], t2[a][b], t3[a][b], -av[a].x, -av[a].y, bv[b].x, bv[b].y);
       }
     }
   }
+  fold3_blocks<T>(cre, cim, t1, t2, t3, a0, a1, b0, b1);
 }
 
 // dst = sg (S - A0 B0^T - A1 B1^T) with k-major panel tiles A0, B0, A1, B1:
