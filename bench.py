@@ -529,7 +529,9 @@ def main():
         # one batch of the step's geometries factored alone (a warm-up, then
         # timed), for profiling the factorisation kernels of one precision
         prec = rcp.RCP_FP64 if args.factor_batch_only == "fp64" else rcp.RCP_FP32_REFINED
-        B = max(1, min(8, args.batch))
+        # up to 16 with FP32 factors (two groups on two streams); FP64 factors of
+        # more than eight config-2 geometries exceed the HBM
+        B = max(1, min(16 if prec == rcp.RCP_FP32_REFINED else 8, args.batch))
         eps_b = [rcp.eps_from_widths(p, torch.tensor(W.seeded_widths(len(p.pillar_centers), 1002 + 97 * k),
                                                      dtype=torch.float64, device=dev), device=dev)
                  for k in range(B)]
@@ -830,6 +832,22 @@ def main():
             torch.cuda.synchronize()
             t_b32 = a.elapsed_time(b) * 1e-3
             del facs32, eps_b
+        t_b32x2 = None
+        if B == 8:   # sixteen geometries with FP32 factors (half the bytes): two groups of eight
+            # on two streams of the library, the FP64 step's buffers holding eight of them
+            eps_16 = [rcp.eps_from_widths(p, torch.tensor(W.seeded_widths(len(p.pillar_centers), 1002 + 97 * k),
+                                                          dtype=torch.float64, device=dev), device=dev)
+                      for k in range(16)]
+            more = [torch.empty(rcp.factor_bytes(p, rcp.RCP_FP32_REFINED), dtype=torch.uint8, device=dev)
+                    for _ in range(8)]
+            torch.cuda.synchronize()
+            a.record(stream)
+            facs32 = rcp.factor_batch([p] * 16, eps_16, rcp.RCP_FP32_REFINED, buffers=list(bufs) + more)
+            b.record(stream)
+            torch.cuda.synchronize()
+            t_b32x2 = a.elapsed_time(b) * 1e-3
+            del facs32, eps_16, more
+            torch.cuda.empty_cache()
         fac = rcp.Factors(p, eps, rcp.RCP_FP64, buffer=buf)
         F64, z64 = rcp.reciprocal_average(fac, p, want_z=True)
         torch.cuda.synchronize()
@@ -845,6 +863,12 @@ def main():
                 **lu_rates(p, t_b32, B, FP32_PEAK_TFLOPS),
                 "speedup_vs_fp64_batch": round(out["lu_batch"]["seconds"] / t_b32, 3)
                 if "lu_batch" in out else None}
+        if t_b32x2 is not None:
+            out["fp32_refined"]["lu_batch16"] = {
+                "geometries": 16, "groups": "two groups of 8, each on a stream of the library",
+                "seconds": round(t_b32x2, 5), **lu_rates(p, t_b32x2, 16, FP32_PEAK_TFLOPS),
+                "speedup_vs_fp64_batch_per_geometry":
+                    round(out["lu_batch"]["seconds"] / 8 / (t_b32x2 / 16), 3) if "lu_batch" in out else None}
         log(f"fp32 refined: factor {t_f32 * 1e3:.1f} ms, {it} steps, field err {zerr:.2e}")
         del f32, buf32
         # broadband: the geometry at the eight wavelengths of a flat spectral rule

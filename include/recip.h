@@ -154,11 +154,17 @@ size_t rcp_factor_bytes(const rcp_grid* grid, int32_t precision);
 int rcp_factor(const rcp_grid* grid, int32_t precision, void* buf_dev, size_t buf_bytes,
                rcp_stream stream, rcp_factors** out);
 
-/* a2 + a3 for `count` (1..8) geometries of identical grid shape (eps and k0 may
- * differ: several wavelengths of one geometry factor side by side),
+/* a2 + a3 for `count` (1..16) geometries of identical grid shape (eps and k0
+ * may differ: several wavelengths of one geometry factor side by side),
  * factored in the same kernel launches (their elimination chains run side by
  * side, two Gauss-Jordan panels per pass over the tiles; a lone geometry takes
  * one panel per launch, so its factors agree with a batch's to rounding).
+ * Above 8 the geometries form two groups ([0, ceil(count/2)) and the rest),
+ * each factored in its own launches on one of two streams that the library
+ * creates per device (default priority, kept until the process ends), forked
+ * from and joined back into `stream`; one call enqueues the second group from
+ * a host thread of its own.  A geometry's factors are the same in any batch of
+ * two or more, so they do not depend on the grouping.
  * grids[g], bufs[g] (each buf_bytes >= rcp_factor_bytes, 256-byte aligned,
  * non-overlapping) and out[g] as for rcp_factor.  On failure no
  * handle is returned and the message names the geometry. */

@@ -166,13 +166,14 @@ class Factors:
 @_on_stream
 def factor_batch(problems, eps_list, precision: int = RCP_FP64, buffers=None, stream=None,
                  wait: bool = True):
-    """Factor 1-8 same-grid geometries in the same kernel launches (chains side by side).
+    """Factor 1-16 same-grid geometries in the same kernel launches (chains side by side;
+    above 8 as two groups on two library streams, side by side).
 
     wait=False enqueues only (rcp_factor_batch_async): the pivot check stays on
     the device until status() or status_dev() of a returned Factors reads it."""
     B = len(problems)
-    if B < 1 or B > 8 or len(eps_list) != B:
-        raise ValueError("factor_batch takes 1 to 8 problems with one eps map each")
+    if B < 1 or B > 16 or len(eps_list) != B:
+        raise ValueError("factor_batch takes 1 to 16 problems with one eps map each")
     nbytes = factor_bytes(problems[0], precision)
     dev = eps_list[0].device
     if buffers is None:

@@ -4,6 +4,8 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <system_error>
+#include <thread>
 #include <vector>
 
 #include "rcp_internal.h"
@@ -396,10 +398,94 @@ size_t rcp_factor_bytes(const rcp_grid* grid, int32_t precision) {
 }  // extern "C"
 
 namespace {
+// rcp_factor_batch takes up to two groups of MAX_BATCH geometries: above
+// MAX_BATCH the groups run on two streams of the library, side by side.  A pass
+// of one group waits on its chain of pivot inversions while the tile updates of
+// the other fill the matrix cores (FP32 factors, half the bytes, fit sixteen
+// config-2 geometries in HBM).
+constexpr int MAX_FACTOR_BATCH = 2 * MAX_BATCH;
+constexpr int MAX_DEVICES = 64;
+
+// The two streams of a device (default priority), created on first use and
+// kept until the process ends.
+std::mutex g_side_mu;
+hipStream_t g_side[MAX_DEVICES][2] = {};
+
+int side_streams(int dev, hipStream_t* out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(RCP_EINVAL, "device index above 63");
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  for (int i = 0; i < 2; ++i) {
+    if (!g_side[dev][i]) RCP_HIP(hipStreamCreateWithFlags(&g_side[dev][i], hipStreamNonBlocking));
+    out[i] = g_side[dev][i];
+  }
+  return RCP_OK;
+}
+
+struct Events {
+  hipEvent_t e[3] = {};
+  ~Events() {
+    for (hipEvent_t x : e)
+      if (x) (void)hipEventDestroy(x);   // released once the recorded work is done
+  }
+};
+
+// Geometries [0, h) and [h, count) (h = ceil(count / 2)) assembled and factored
+// on the two side streams, both forked from and joined back into s.  The
+// second group is enqueued by a thread of its own: enqueuing blocks once a
+// stream's launch queue is full, and one thread would then run the groups one
+// after the other.  Each group has at least two geometries when count > 8, so
+// every geometry's factors are those of any batch of two or more.
+int factor_two_groups(int32_t count, const rcp_grid* grids, int32_t precision, const Layout& L,
+                      void* const* bufs, hipStream_t s, rcp_factors** fs) {
+  int dev = 0;
+  RCP_HIP(hipGetDevice(&dev));
+  hipStream_t side[2];
+  int rc = side_streams(dev, side);
+  if (rc) return rc;
+  Events ev;
+  for (hipEvent_t& x : ev.e) RCP_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+  RCP_HIP(hipEventRecord(ev.e[0], s));
+  for (hipStream_t x : side) RCP_HIP(hipStreamWaitEvent(x, ev.e[0], 0));
+  const int h = (count + 1) / 2;
+  const int first[2] = {0, h}, n[2] = {h, count - h};
+  int grc[2] = {RCP_OK, RCP_OK};
+  std::string gerr[2];
+  auto group = [&](int i) {
+    int r = i ? (hipSetDevice(dev) == hipSuccess ? RCP_OK : fail(RCP_EHIP, "hipSetDevice failed"))
+              : RCP_OK;
+    for (int g = first[i]; g < first[i] + n[i] && !r; ++g)
+      r = init_factors(&grids[g], precision, L, bufs[g], side[i], &fs[g]);
+    if (!r) r = factor_blocks_async(fs + first[i], n[i], side[i]);
+    grc[i] = r;
+    if (r) gerr[i] = g_err;
+  };
+  bool threaded = true;
+  std::thread t1;
+  try {
+    t1 = std::thread(group, 1);
+  } catch (const std::system_error&) {
+    threaded = false;   // no thread: the groups are enqueued one after the other
+  }
+  group(0);
+  if (threaded)
+    t1.join();
+  else
+    group(1);
+  for (int i = 0; i < 2; ++i) {
+    RCP_HIP(hipEventRecord(ev.e[1 + i], side[i]));
+    RCP_HIP(hipStreamWaitEvent(s, ev.e[1 + i], 0));
+  }
+  for (int i = 0; i < 2; ++i)
+    if (grc[i])
+      return fail(grc[i], "geometries " + std::to_string(first[i]) + ".." +
+                              std::to_string(first[i] + n[i] - 1) + ": " + gerr[i]);
+  return RCP_OK;
+}
+
 int factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, void* const* bufs,
                  size_t buf_bytes, rcp_stream stream, rcp_factors** out, bool wait) {
   if (!out || !grids || !bufs) return fail(RCP_EINVAL, "NULL argument");
-  if (count < 1 || count > MAX_BATCH) return fail(RCP_EINVAL, "count must be 1 to 8");
+  if (count < 1 || count > MAX_FACTOR_BATCH) return fail(RCP_EINVAL, "count must be 1 to 16");
   for (int g = 0; g < count; ++g) out[g] = nullptr;
   if (precision != RCP_FP64 && precision != RCP_FP32_REFINED)
     return fail(RCP_EINVAL, "unknown precision");
@@ -427,10 +513,16 @@ int factor_batch(int32_t count, const rcp_grid* grids, int32_t precision, void* 
       if (x0 < y0 + L.total && y0 < x0 + L.total) return fail(RCP_EINVAL, "factor buffers overlap");
     }
   }
-  rcp_factors* fs[MAX_BATCH] = {};   // count <= MAX_BATCH checked above
+  rcp_factors* fs[MAX_FACTOR_BATCH] = {};   // count <= MAX_FACTOR_BATCH checked above
   int rc = RCP_OK;
-  for (int g = 0; g < count && !rc; ++g) rc = init_factors(&grids[g], precision, L, bufs[g], stream, &fs[g]);
-  if (!rc) rc = wait ? factor_blocks(fs, count, stream) : factor_blocks_async(fs, count, stream);
+  if (count <= MAX_BATCH) {
+    for (int g = 0; g < count && !rc; ++g) rc = init_factors(&grids[g], precision, L, bufs[g], stream, &fs[g]);
+    if (!rc) rc = wait ? factor_blocks(fs, count, stream) : factor_blocks_async(fs, count, stream);
+  } else {
+    rc = factor_two_groups(count, grids, precision, L, bufs, stream, fs);
+    for (int g = 0; g < count && !rc && wait; ++g)
+      rc = read_pivot_check(fs[g], stream, "geometry " + std::to_string(g) + ": ");
+  }
   if (rc) {
     for (int g = 0; g < count; ++g) delete fs[g];
     return rc;

@@ -79,8 +79,9 @@ def test_batch_rejects_mismatched_grids_on_host():
     outs = (C.c_void_p * 2)()
     rc = lib.rcp_factor_batch(2, grids, 0, bufs, 1 << 40, None, outs)
     assert rc == _lib.RCP_EINVAL and b"identical" in lib.rcp_last_error()
-    rc = lib.rcp_factor_batch(9, grids, 0, bufs, 1 << 40, None, outs)   # count checked first
-    assert rc == _lib.RCP_EINVAL
+    for count in (0, 17):   # count checked first
+        rc = lib.rcp_factor_batch(count, grids, 0, bufs, 1 << 40, None, outs)
+        assert rc == _lib.RCP_EINVAL and b"1 to 16" in lib.rcp_last_error()
 
 
 def test_null_handles_are_rejected():
