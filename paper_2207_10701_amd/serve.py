@@ -3,12 +3,14 @@
 Requests (a geometry, an objective, a light distribution, optionally a
 gradient) arrive over time.  Their work has two parts:
 
-* factorisation of a geometry not in the cache: one host thread drives the
-  factorisation engine (``rcp_engine_*``), in which every geometry in flight
-  (up to ``factor_slots``, at most 8) advances one pass per round of shared
-  kernel launches, whatever its grid size; a geometry admitted while others
-  are in progress joins at the next round (continuous batching at the level of
-  the factorisation passes);
+* factorisation of a geometry not in the cache: one host thread drives each
+  factorisation engine (``rcp_engine_*``, ``engines`` of them, each on its own
+  stream), in which every geometry in flight (up to 8 per engine,
+  ``factor_slots`` in all) advances one pass per round of shared kernel
+  launches, whatever its grid size; a geometry admitted while others are in
+  progress joins the emptier engine at its next round (continuous batching at
+  the level of the factorisation passes); two engines overlap one's chains of
+  pivot inversions with the other's tile updates;
 * evaluation on factors that are ready: up to ``eval_slots`` evaluations run
   at once, each on its own HIP stream, beside the engine's stream.  Plain
   requests for the same geometry that are waiting go together (up to
@@ -343,9 +345,11 @@ class Server:
 
     def __init__(self, executor, factor_slots: int = 8, eval_slots: int = 4,
                  hbm_budget: int = 200 << 30, cache: bool = True, group: int = 16,
-                 rounds_per_step: int = 4, order: str = "arrival"):
-        if not 1 <= factor_slots <= 8:
-            raise ValueError("factor_slots must be 1 to 8")
+                 rounds_per_step: int = 4, order: str = "arrival", engines: int = 1):
+        if not 1 <= engines <= 4:
+            raise ValueError("engines must be 1 to 4")
+        if not 1 <= factor_slots <= 8 * engines:
+            raise ValueError("factor_slots must be 1 to 8 per engine")
         if eval_slots < 1:
             raise ValueError("eval_slots must be >= 1")
         if not 1 <= group <= 64:
@@ -366,18 +370,24 @@ class Server:
         self.free_slots = list(range(eval_slots))
         self.streams = [executor.new_stream() for _ in range(eval_slots)]
         self.results: Dict[int, Result] = {}
-        self.to_factor: List[_Entry] = []   # admitted, not yet in the engine
+        # per engine: admitted, not yet in it; and its geometries (queued or in it)
+        self.to_factor: List[List[_Entry]] = [[] for _ in range(engines)]
+        self.assigned = [0] * engines
         self.factoring = 0                  # entries in the engine or queued for it
         self.peak_bytes = 0
         self.max_inflight = 0               # evaluations at once
-        self.max_factoring = 0              # geometries in the engine at once
-        self.engine_time = 0.0              # wall time with geometries in the engine
+        self.max_factoring = 0              # geometries in the engines at once
+        self.engine_time = 0.0              # wall time with geometries in an engine (summed over engines)
         self.engine_geom_time = 0.0         # ... times the geometries in it
         self.inflight = 0
-        self.engine = executor.new_engine()
+        # each engine on its own stream, driven by a thread of its own: while one
+        # waits on its chains of pivot inversions the other's tile updates run
+        self.engines = [executor.new_engine() for _ in range(engines)]
         self._stop = False
-        self._ft = threading.Thread(target=self._factor_loop, daemon=True)
-        self._ft.start()
+        self._ft = [threading.Thread(target=self._factor_loop, args=(i,), daemon=True)
+                    for i in range(engines)]
+        for th in self._ft:
+            th.start()
 
     # -- memory ledger ----------------------------------------------------------------
     @property
@@ -408,20 +418,20 @@ class Server:
         self.arena.release(entry.off, entry.nbytes)
 
     # -- the engine's thread ----------------------------------------------------------------
-    def _factor_loop(self):
+    def _factor_loop(self, i: int):
         made: Dict[int, _Entry] = {}
+        eng, queue = self.engines[i], self.to_factor[i]
         while True:
             with self.cv:
-                while (not self._stop and not self.to_factor
-                       and self.ex.engine_size(self.engine) == 0):
+                while not self._stop and not queue and self.ex.engine_size(eng) == 0:
                     self.cv.wait()
-                if self._stop and not self.to_factor and self.ex.engine_size(self.engine) == 0:
+                if self._stop and not queue and self.ex.engine_size(eng) == 0:
                     return
-                adds = self.to_factor[:]
-                self.to_factor.clear()
+                adds = queue[:]
+                queue.clear()
             for entry in adds:
                 try:
-                    fac = self.ex.engine_add(self.engine, entry.p, entry.off)
+                    fac = self.ex.engine_add(eng, entry.p, entry.off)
                     made[id(fac)] = entry
                     entry.fac = fac
                 except Exception as e:     # bad geometry: fail its requests only
@@ -429,17 +439,20 @@ class Server:
                         entry.error = str(e)
                         entry.ready = True
                         self.factoring -= 1
+                        self.assigned[i] -= 1
                         self.cv.notify_all()
             with self.cv:
-                self.max_factoring = max(self.max_factoring, self.ex.engine_size(self.engine))
-            if self.ex.engine_size(self.engine) == 0:
+                self.max_factoring = max(self.max_factoring,
+                                         sum(self.ex.engine_size(e) for e in self.engines))
+            if self.ex.engine_size(eng) == 0:
                 continue
-            n_in = self.ex.engine_size(self.engine)
+            n_in = self.ex.engine_size(eng)
             t_step = time.perf_counter()
-            done = self.ex.engine_step(self.engine, self.rounds)
+            done = self.ex.engine_step(eng, self.rounds)
             dt = time.perf_counter() - t_step
-            self.engine_time += dt
-            self.engine_geom_time += dt * n_in
+            with self.cv:
+                self.engine_time += dt
+                self.engine_geom_time += dt * n_in
             if done:
                 with self.cv:
                     for fac, err in done:
@@ -447,6 +460,7 @@ class Server:
                         entry.ready = True
                         entry.error = err
                         self.factoring -= 1
+                        self.assigned[i] -= 1
                     self.cv.notify_all()
 
     # -- evaluations (run on a slot's thread) -----------------------------------------------
@@ -541,7 +555,9 @@ class Server:
             key = geometry_key(req.problem)
             entry = _Entry(key, req.problem, need, off)
             self.cache[key] = entry
-            self.to_factor.append(entry)
+            i = min(range(len(self.engines)), key=lambda j: self.assigned[j])   # the emptier engine
+            self.to_factor[i].append(entry)
+            self.assigned[i] += 1
             self.factoring += 1
             self._fresh[req.rid] = True
             changed = True
@@ -603,21 +619,23 @@ class Server:
         return changed
 
     def engine_occupancy(self) -> float:
-        """Time-weighted mean number of geometries in the engine while it ran."""
+        """Time-weighted mean number of geometries in an engine while it ran."""
         return self.engine_geom_time / self.engine_time if self.engine_time > 0 else 0.0
 
     def close(self):
         with self.cv:
             self._stop = True
             self.cv.notify_all()
-        self._ft.join()
+        for th in self._ft:
+            th.join()
         with self.cv:
             for e in list(self.cache.values()):
                 if e.fac is not None:
                     self.ex.release(e.fac)
             self.cache.clear()
             self.arena = Arena(self.budget)
-        self.ex.engine_close(self.engine)
+        for eng in self.engines:
+            self.ex.engine_close(eng)
         self.ex.close_arena()
 
 

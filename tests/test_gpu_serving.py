@@ -7,12 +7,13 @@ from oracle import average as ora
 pytestmark = pytest.mark.gpu
 
 
-def test_mix_equals_alone_and_oracle(rcp):
+@pytest.mark.parametrize("engines", [1, 2])
+def test_mix_equals_alone_and_oracle(rcp, engines):
     import torch
     from paper_2207_10701_amd.serve import GpuExecutor, Server, summarize
     reqs = W.serving_stream(8, rate=500.0, seed=5001, scale=0.04, geometry_pool=5)
     ex = GpuExecutor()
-    srv = Server(ex, eval_slots=3, hbm_budget=8 << 30)
+    srv = Server(ex, eval_slots=3, hbm_budget=8 << 30, engines=engines)
     out = srv.run(reqs, realtime=True)
     srv.close()
     assert all(r.error is None for r in out), [r.error for r in out]

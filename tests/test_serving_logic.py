@@ -221,7 +221,41 @@ def test_server_arguments():
     with pytest.raises(ValueError):
         Server(FakeExecutor(), factor_slots=9)
     with pytest.raises(ValueError):
+        Server(FakeExecutor(), factor_slots=17, engines=2)
+    for engines in (0, 5):
+        with pytest.raises(ValueError):
+            Server(FakeExecutor(), engines=engines)
+    with pytest.raises(ValueError):
         Server(FakeExecutor(), eval_slots=0)
+    Server(FakeExecutor(), factor_slots=16, engines=2).close()
+
+
+def test_two_engines_share_the_fresh_geometries():
+    """With two engines, geometries that arrive together go to the emptier one:
+    twelve split six and six, each engine's rounds shared by its six; every
+    result is the one a lone evaluation gives."""
+    reqs = [W.Request(rid=i, arrival=0.0, problem=W.small_problem(2, 4, seed=300 + i),
+                      adjoint=i % 3 == 0) for i in range(12)]
+    ex = FakeExecutor(factor_seconds=lambda p: 0.02, round_seconds=0.001)
+    srv, out = serve(ex, reqs, realtime=False, factor_slots=16, engines=2, hbm_budget=10 ** 12)
+    assert all(r.error is None for r in out)
+    assert srv.max_factoring == 12 and max(ex.round_sizes) == 6
+    alone = FakeExecutor()
+    for q, r in zip(reqs, out):
+        F, _ = alone.evaluate(None, q.problem, q.adjoint, None)
+        assert r.F == F
+
+
+def test_two_engines_respect_the_slot_limit_and_fail_alone():
+    """factor_slots bounds the geometries in both engines together; a failing
+    geometry in one engine fails only its own requests."""
+    reqs = [W.Request(rid=i, arrival=0.0, problem=W.small_problem(2, 4, seed=320 + i),
+                      adjoint=False) for i in range(10)]
+    bad = reqs[3].problem
+    ex = FakeExecutor(factor_seconds=lambda p: 0.01, round_seconds=0.001, fail_on=lambda p: p is bad)
+    srv, out = serve(ex, reqs, realtime=False, factor_slots=5, engines=2, hbm_budget=10 ** 12)
+    assert srv.max_factoring <= 5 and max(ex.round_sizes) <= 3
+    assert [r.error is not None for r in out] == [i == 3 for i in range(10)]
 
 
 def test_arena_places_first_fit_and_merges_free_neighbours():
