@@ -528,7 +528,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU; the reciprocal solve of one "
+        print(json.dumps({"error": "this benchmark runs on one GPU; the reciprocal solve of one "
                                    "geometry is not sharded (N must be 1)"}))
         sys.exit(2)
 
