@@ -399,10 +399,10 @@ size_t rcp_factor_bytes(const rcp_grid* grid, int32_t precision) {
 
 namespace {
 // rcp_factor_batch takes up to two groups of MAX_BATCH geometries: above
-// MAX_BATCH the groups run on two streams of the library, side by side.  A pass
-// of one group waits on its chain of pivot inversions while the tile updates of
-// the other fill the matrix cores (FP32 factors, half the bytes, fit sixteen
-// config-2 geometries in HBM).
+// MAX_BATCH the groups run on two streams of the library, side by side: the
+// matrix cores idle by one group's passes (while its tile loads and its pivot
+// chains are in flight) run the other's (single-precision factors, half the
+// bytes, fit sixteen geometries of 2040 x 1080 cells in HBM).
 constexpr int MAX_FACTOR_BATCH = 2 * MAX_BATCH;
 constexpr int MAX_DEVICES = 64;
 

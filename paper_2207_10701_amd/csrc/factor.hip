@@ -198,6 +198,91 @@ __device__ double invert_pivot_block(double2 (*A)[TB + 1], double2 (*W)[TB + 1])
   return sqrt(sqrt(mindet2));   // |det B|^(1/2): same scale as a scalar pivot
 }
 
+// The same inversion in single precision, for single-precision factors (their
+// tile products are single precision too, and their solves are refined in
+// double): the block is read from A, the steps run on two float2 views of W
+// (W holds two single-precision blocks), and the inverse is written back to
+// A.  The chain of dependent operations per step is shorter in single
+// precision (hardware reciprocal and one Newton step), about 6.9 against
+// 11.5 us per inversion.
+__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ void pivot_step_f(int P, float2 (&m)[4], const float2 (*S)[TB + 1],
+                                             float2 (*D)[TB + 1], int r, int c0, float& mindet2) {
+  const float2 a = S[P][P], bb = S[P][P + 1], cc = S[P + 1][P], d = S[P + 1][P + 1];
+  const float2 f0 = S[r][P], f1 = S[r][P + 1];
+  float2 q0[4], q1[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    q0[c] = S[P][c0 + c];
+    q1[c] = S[P + 1][c0 + c];
+  }
+  const float2 ad = cmulf(a, d), bc = cmulf(bb, cc);
+  const float2 det = make_float2(ad.x - bc.x, ad.y - bc.y);
+  const float dd = det.x * det.x + det.y * det.y;
+  mindet2 = (dd < mindet2 || dd != dd) ? dd : mindet2;
+  float rd = __builtin_amdgcn_rcpf(dd);
+  rd = fmaf(rd, fmaf(-dd, rd, 1.0f), rd);
+  const float2 idet = make_float2(det.x * rd, -det.y * rd);
+  const float2 i00 = cmulf(d, idet), i11 = cmulf(a, idet);
+  const float2 t01 = cmulf(bb, idet), t10 = cmulf(cc, idet);
+  const float2 i01 = make_float2(-t01.x, -t01.y), i10 = make_float2(-t10.x, -t10.y);
+  const bool r0 = (r == P), r1 = (r == P + 1);
+  const float2 u0 = cmulf(f0, i00), u1 = cmulf(f1, i10), w0 = cmulf(f0, i01), w1 = cmulf(f1, i11);
+  const float2 g0 = make_float2(u0.x + u1.x, u0.y + u1.y), g1 = make_float2(w0.x + w1.x, w0.y + w1.y);
+  const float2 b0 = r0 ? make_float2(-i00.x, -i00.y) : r1 ? make_float2(-i10.x, -i10.y) : g0;
+  const float2 b1 = r0 ? make_float2(-i01.x, -i01.y) : r1 ? make_float2(-i11.x, -i11.y) : g1;
+  const bool keep = !(r0 || r1);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int col = c0 + c;
+    float2 v = keep ? m[c] : make_float2(0.0f, 0.0f);
+    const float2 x0 = cmulf(b0, q0[c]), x1 = cmulf(b1, q1[c]);
+    v = make_float2(v.x - x0.x - x1.x, v.y - x0.y - x1.y);
+    m[c] = (col == P) ? make_float2(-b0.x, -b0.y) : (col == P + 1) ? make_float2(-b1.x, -b1.y) : v;
+    D[r][col] = m[c];
+  }
+  __syncthreads();
+}
+
+__device__ double invert_pivot_block_f(double2 (*A)[TB + 1], double2 (*W)[TB + 1]) {
+  static_assert(2 * sizeof(float2) == sizeof(double2), "W holds two single-precision blocks");
+  const int tid = threadIdx.x;
+  const int r = tid >> 3, c0 = (tid & 7) * 4;
+  float2 (*S)[TB + 1] = reinterpret_cast<float2 (*)[TB + 1]>(&W[0][0]);
+  float2 (*D)[TB + 1] = S + TB;
+  float2 m[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double2 v = A[r][c0 + c];
+    m[c] = make_float2(static_cast<float>(v.x), static_cast<float>(v.y));
+    S[r][c0 + c] = m[c];
+  }
+  __syncthreads();
+  float mindet2 = INFINITY;
+#pragma unroll 1
+  for (int P = 0; P < TB; P += 2) {
+    pivot_step_f(P, m, S, D, r, c0, mindet2);
+    float2 (*t)[TB + 1] = S;
+    S = D;
+    D = t;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) A[r][c0 + c] = make_double2(m[c].x, m[c].y);
+  __syncthreads();
+  return sqrt(sqrt(static_cast<double>(mindet2)));
+}
+
+// The pivot-block inverse in the precision of the factors
+template <typename T>
+__device__ __forceinline__ double invert_pivot(double2 (*A)[TB + 1], double2 (*W)[TB + 1]) {
+  if constexpr (sizeof(T) == sizeof(float))
+    return invert_pivot_block_f(A, W);
+  else
+    return invert_pivot_block(A, W);
+}
+
 // Complex products on the matrix cores take three real products each (Gauss):
 // a b accumulates as t1 += ar br, t2 -= ai bi, t3 += (ar + ai)(br + bi), and
 // the complex sum is (t1 + t2, t3 - t1 + t2).  A product to subtract passes
@@ -462,7 +547,7 @@ __device__ void panel_work(const GJJob& jb, int wg, int nt, double2 (*Ps)[TB + 1
       }
   }
   __syncthreads();
-  const double minpiv = invert_pivot_block(Ps, Ws);
+  const double minpiv = invert_pivot<T>(Ps, Ws);
   if (wg == 0) {
     for (int e = tid; e < TB * TB; e += 256) jb.Pn[e] = Ps[e / TB][e % TB];
     if (tid == 0) *jb.health = minpiv;
@@ -646,7 +731,7 @@ __device__ void lookahead_work(const GJJob& jb, int g, int nt, double2 (*Ps)[TB 
           make_double2(static_cast<double>(dre[0][0][q]), static_cast<double>(dim[0][0][q]));
   }
   __syncthreads();
-  const double minpiv = invert_pivot_block(Ps, Ws);
+  const double minpiv = invert_pivot<T>(Ps, Ws);
   if (g == 0) {
     for (int e = tid; e < TB * TB; e += 256) jb.Pn[e] = Ps[e / TB][e % TB];
     if (tid == 0) *jb.health = minpiv;
@@ -764,11 +849,12 @@ __device__ __forceinline__ void tile_nn_update(typename v4of<T>::t (*cre)[2],
 }
 
 // dst = sg (S - A0 B0^T - A1 B1^T) with k-major panel tiles A0, B0, A1, B1:
-// eight chunks of two k-steps into zeroed accumulators, the next chunk in
-// flight while the current one multiplies; S is added at the end.  Vector
-// loads retire in issue order, so the tile S (from HBM) is requested after
-// the first two chunks (from L2): the first products wait only for L2, and
-// S arrives while they run.
+// eight chunks of two k-steps into zeroed accumulators, each chunk requested
+// two chunks ahead of its products (a chunk's products take less than a round
+// trip to L2 in single precision); S is added at the end.  Vector loads retire
+// in issue order, so the tile S (from HBM) is requested after the first three
+// chunks (from L2): the first products wait only for L2, and S arrives while
+// they run.
 template <typename T>
 __device__ __forceinline__ void tile_update2_pipelined(typename cplx<T>::t* dst,
                                                        const typename cplx<T>::t* A0,
@@ -783,9 +869,11 @@ __device__ __forceinline__ void tile_update2_pipelined(typename cplx<T>::t* dst,
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) zero3(t1[a][b], t2[a][b], t3[a][b]);
-  T2 a0[2][2], b0[2][2], a1[2][2], b1[2][2];
-  load_ksteps_t(a0, b0, A0, B0, 0, lr, lk);
-  load_ksteps_t(a1, b1, A0, B0, 1, lr, lk);
+  // eight chunks of two k-steps (four from panel k, four from panel k + 1),
+  // each requested two chunks ahead of its products
+  T2 av[3][2][2], bv[3][2][2];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) load_ksteps_t(av[ch], bv[ch], A0, B0, ch, lr, lk);
   T2 sv[2][2][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -793,20 +881,12 @@ __device__ __forceinline__ void tile_update2_pipelined(typename cplx<T>::t* dst,
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int q = 0; q < 4; ++q) sv[a][b][q] = load_stream(&dst[(16 * a + mfma_row<T>(lk, q)) * TB + 16 * b + lr]);
-  mma_ksteps<T>(t1, t2, t3, a0, b0);
-  load_ksteps_t(a0, b0, A0, B0, 2, lr, lk);
-  mma_ksteps<T>(t1, t2, t3, a1, b1);
-  load_ksteps_t(a1, b1, A0, B0, 3, lr, lk);
-  mma_ksteps<T>(t1, t2, t3, a0, b0);
-  load_ksteps_t(a0, b0, A1, B1, 0, lr, lk);
-  mma_ksteps<T>(t1, t2, t3, a1, b1);
-  load_ksteps_t(a1, b1, A1, B1, 1, lr, lk);
-  mma_ksteps<T>(t1, t2, t3, a0, b0);
-  load_ksteps_t(a0, b0, A1, B1, 2, lr, lk);
-  mma_ksteps<T>(t1, t2, t3, a1, b1);
-  load_ksteps_t(a1, b1, A1, B1, 3, lr, lk);
-  mma_ksteps<T>(t1, t2, t3, a0, b0);
-  mma_ksteps<T>(t1, t2, t3, a1, b1);
+#pragma unroll
+  for (int ch = 0; ch < 8; ++ch) {
+    mma_ksteps<T>(t1, t2, t3, av[ch % 3], bv[ch % 3]);
+    const int nx = ch + 3;
+    if (nx < 8) load_ksteps_t(av[ch % 3], bv[ch % 3], nx < 4 ? A0 : A1, nx < 4 ? B0 : B1, nx & 3, lr, lk);
+  }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -1039,7 +1119,7 @@ __device__ void pivot2_work(const GJ2Job& jb, int nt, double2 (*B1)[TB + 1],
     }
   }
   __syncthreads();
-  const double min3 = invert_pivot_block(B1, B3);   // P3
+  const double min3 = invert_pivot<T>(B1, B3);   // P3
   double2* P3 = jb.Pb + size_t(K3 & 3) * TT;
   for (int e = tid; e < TB * TB; e += 256) P3[e] = B1[e / TB][e % TB];
   if (tid == 0) jb.health[K3] = min3;
@@ -1093,7 +1173,7 @@ __device__ void pivot2_work(const GJ2Job& jb, int nt, double2 (*B1)[TB + 1],
   __syncthreads();
   quad_to_lds<T>(fre, fim, B2, lr, lk, qa, qb);
   __syncthreads();
-  const double min4 = invert_pivot_block(B2, B1);   // P4
+  const double min4 = invert_pivot<T>(B2, B1);   // P4
   double2* P4 = jb.Pb + size_t(K4 & 3) * TT;
   for (int e = tid; e < TB * TB; e += 256) P4[e] = B2[e / TB][e % TB];
   if (tid == 0) jb.health[K4] = min4;
